@@ -90,6 +90,9 @@ def lib():
         L.or_solve.restype = C.c_int32
         L.or_sweep_energy_trace.argtypes = [C.POINTER(_Problem), _ip, _dp, C.POINTER(_Opts), _dp]
         L.or_sweep_energy_trace.restype = C.c_int32
+        L.or_update_vertices.argtypes = [C.POINTER(_Problem), _dp, C.c_int32, _ip,
+                                         C.POINTER(_Opts), _dp]
+        L.or_update_vertices.restype = C.c_int32
         L.or_hvp.argtypes = [C.POINTER(_Problem), _dp, _dp, _dp]
         L.or_hvp.restype = C.c_int32
         L.or_adjoint_gradients.argtypes = [C.POINTER(_Problem), _dp, _dp, _dp, _dp, _dp]
@@ -330,6 +333,22 @@ def solve(op: OracleProblem, colors, x, max_sweeps=100, accel="none", rho=0.95, 
     if history:
         return x, stats, hist[: max(0, st.sweeps // max(1, check_every))]
     return x, stats
+
+
+def update_vertices(op: OracleProblem, x, verts, safeguard="backtrack", max_halvings=8,
+                    emulate_f32=False):
+    """New positions of `verts` after one update each from positions x."""
+    s = op.struct()
+    x = _f64(x, (-1, 3))
+    verts = np.ascontiguousarray(verts, np.int32)
+    o = _Opts(max_sweeps=1, check_every=1, rel_tol=0.0, accel=0, rho=0, gamma=1, omega=1,
+              safeguard=SAFEGUARD[safeguard], max_halvings=max_halvings, skip_tol=0.0,
+              emulate_f32=int(emulate_f32), n_threads=1)
+    out = np.zeros((verts.size, 3))
+    rc = lib().or_update_vertices(C.byref(s), _d(x), verts.size, _i(verts), C.byref(o), _d(out))
+    if rc:
+        raise ValueError("oracle update failed (%d)" % rc)
+    return out
 
 
 def sweep_energy_trace(op: OracleProblem, colors, x, safeguard="backtrack", max_halvings=8):

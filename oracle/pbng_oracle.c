@@ -849,6 +849,31 @@ int32_t or_sweep_energy_trace(const or_problem* p, const int32_t* colors, double
     return n;
 }
 
+/* The single-vertex update of Eq. (pbgn_dx) (with the safeguard of *o)
+ * applied to each listed vertex, every one computed from the same
+ * positions y (valid for vertices of one colour, which share no term).
+ * out[k] receives the new position of verts[k]; y is not modified. */
+int32_t or_update_vertices(const or_problem* p, const double* y, int32_t n, const int32_t* verts,
+                           const or_opts* o, double* out)
+{
+    or_adj A;
+    int rc = adj_build(p, &A);
+    if (rc) return rc;
+    double* z = (double*)malloc(sizeof(double) * 3 * (size_t)p->nv);
+    memcpy(z, y, sizeof(double) * 3 * (size_t)p->nv);
+    for (int k = 0; k < n; ++k) {
+        int i = verts[k];
+        update_vertex(p, &A, z, i, o);
+        for (int a = 0; a < 3; ++a) {
+            out[3 * k + a] = z[3 * i + a];
+            z[3 * i + a] = y[3 * i + a];
+        }
+    }
+    free(z);
+    adj_free(&A);
+    return 0;
+}
+
 /* ------------------------------------------------------------------ */
 /* True Hessian (Neo-Hookean only) and adjoint gradient assembly         */
 /* ------------------------------------------------------------------ */

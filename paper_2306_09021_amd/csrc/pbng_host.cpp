@@ -1,0 +1,1439 @@
+// libpbng host side: validation, node colouring, packing of the device
+// layout, the solve / residual / adjoint drivers and the C ABI of
+// include/pbng.h.  No C++ exception leaves this file.
+#include "pbng.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "pbng_internal.hpp"
+
+using namespace pbng;
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Error {
+    int code;
+    std::string msg;
+};
+
+[[noreturn]] void fail(int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw Error{code, buf};
+}
+
+void hipchk(hipError_t e, const char* what)
+{
+    if (e == hipSuccess) return;
+    const int code = (e == hipErrorOutOfMemory) ? PBNG_ENOMEM : PBNG_EHIP;
+    fail(code, "%s: %s", what, hipGetErrorString(e));
+}
+
+template <class F>
+int32_t guard(F&& f)
+{
+    try {
+        return f();
+    } catch (const Error& e) {
+        g_err = e.msg;
+        return e.code;
+    } catch (const std::bad_alloc&) {
+        g_err = "out of host memory";
+        return PBNG_ENOMEM;
+    } catch (const std::exception& e) {
+        g_err = e.what();
+        return PBNG_EINVAL;
+    } catch (...) {
+        g_err = "unknown error";
+        return PBNG_EINVAL;
+    }
+}
+
+// Owning device allocation.
+struct Dev {
+    void* p = nullptr;
+    size_t bytes = 0;
+    Dev() = default;
+    Dev(const Dev&) = delete;
+    Dev& operator=(const Dev&) = delete;
+    ~Dev() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    void alloc(size_t n)
+    {
+        release();
+        if (n == 0) n = 16;
+        hipchk(hipMalloc(&p, n), "hipMalloc");
+        bytes = n;
+    }
+    template <class T>
+    void upload(const std::vector<T>& v)
+    {
+        alloc(v.size() * sizeof(T));
+        if (!v.empty()) hipchk(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice), "upload");
+    }
+    template <class T>
+    T* as() const
+    {
+        return static_cast<T*>(p);
+    }
+};
+
+bool finite_arr(const double* a, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        if (!std::isfinite(a[i])) return false;
+    return true;
+}
+
+double det3(const double* A)
+{
+    return A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+           A[2] * (A[3] * A[7] - A[4] * A[6]);
+}
+
+// Rest-state data of one tet: Dm = [X1 - X0, X2 - X0, X3 - X0] (columns),
+// V0 = det(Dm) / 6, and Dm^{-1} (row j-1 = dN_j for j = 1..3).
+bool tet_rest(const double* X, const int32_t* t, double* dminv, double* V0)
+{
+    double Dm[9];
+    for (int r = 0; r < 3; ++r)
+        for (int c = 0; c < 3; ++c) Dm[3 * r + c] = X[3 * t[c + 1] + r] - X[3 * t[0] + r];
+    const double d = det3(Dm);
+    if (!(d > 0.0) || !std::isfinite(d)) return false;
+    // inverse = adj / det, adj_ij = cof_ji
+    double C[9];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            const int r0 = (i + 1) % 3, r1 = (i + 2) % 3, c0 = (j + 1) % 3, c1 = (j + 2) % 3;
+            C[3 * i + j] = Dm[3 * r0 + c0] * Dm[3 * r1 + c1] - Dm[3 * r0 + c1] * Dm[3 * r1 + c0];
+        }
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) dminv[3 * i + j] = C[3 * j + i] / d;
+    *V0 = d / 6.0;
+    return true;
+}
+
+void validate_problem(const pbng_problem* p, int q)
+{
+    if (!p) fail(PBNG_EINVAL, "problem %d: null", q);
+    if (p->n_verts <= 0 || p->n_tets < 0) fail(PBNG_EINVAL, "problem %d: bad sizes", q);
+    if (!p->rest_pos) fail(PBNG_EINVAL, "problem %d: rest_pos is null", q);
+    if (p->n_tets > 0 && !p->tets) fail(PBNG_EINVAL, "problem %d: tets is null", q);
+    if (p->model != PBNG_NEOHOOKEAN && p->model != PBNG_COROTATED)
+        fail(PBNG_EINVAL, "problem %d: unknown model %d", q, p->model);
+    if (!finite_arr(p->rest_pos, 3ll * p->n_verts)) fail(PBNG_ENAN, "problem %d: non-finite rest_pos", q);
+    for (int64_t e = 0; e < p->n_tets; ++e) {
+        const int32_t* t = p->tets + 4 * e;
+        for (int j = 0; j < 4; ++j) {
+            if (t[j] < 0 || t[j] >= p->n_verts)
+                fail(PBNG_EMESH, "problem %d: tet %lld has vertex %d out of range", q, (long long)e, t[j]);
+            for (int k = 0; k < j; ++k)
+                if (t[k] == t[j]) fail(PBNG_EMESH, "problem %d: tet %lld repeats a vertex", q, (long long)e);
+        }
+    }
+    const bool pt = p->mu_tet != nullptr || p->lambda_tet != nullptr;
+    if (pt && (!p->mu_tet || !p->lambda_tet))
+        fail(PBNG_EINVAL, "problem %d: mu_tet and lambda_tet must be given together", q);
+    if (pt) {
+        for (int64_t e = 0; e < p->n_tets; ++e) {
+            if (!std::isfinite(p->mu_tet[e]) || !std::isfinite(p->lambda_tet[e]))
+                fail(PBNG_ENAN, "problem %d: non-finite Lame parameter", q);
+            if (!(p->mu_tet[e] > 0.0) || !(p->lambda_tet[e] > 0.0))
+                fail(PBNG_EMATERIAL, "problem %d: tet %lld has mu or lambda <= 0", q, (long long)e);
+        }
+    } else {
+        if (!std::isfinite(p->mu) || !std::isfinite(p->lambda))
+            fail(PBNG_ENAN, "problem %d: non-finite Lame parameter", q);
+        if (!(p->mu > 0.0) || !(p->lambda > 0.0))
+            fail(PBNG_EMATERIAL, "problem %d: mu and lambda must be > 0", q);
+    }
+    if (!std::isfinite(p->density) || !finite_arr(p->gravity, 3))
+        fail(PBNG_ENAN, "problem %d: non-finite body force", q);
+    if (p->nodal_force && !finite_arr(p->nodal_force, 3ll * p->n_verts))
+        fail(PBNG_ENAN, "problem %d: non-finite nodal_force", q);
+    if (p->n_dirichlet < 0 || p->n_dirichlet > p->n_verts) fail(PBNG_EINVAL, "problem %d: bad n_dirichlet", q);
+    if (p->n_dirichlet > 0) {
+        if (!p->dirichlet_idx || !p->dirichlet_x) fail(PBNG_EINVAL, "problem %d: Dirichlet arrays are null", q);
+        std::vector<char> seen(p->n_verts, 0);
+        for (int k = 0; k < p->n_dirichlet; ++k) {
+            const int v = p->dirichlet_idx[k];
+            if (v < 0 || v >= p->n_verts) fail(PBNG_EINVAL, "problem %d: Dirichlet index %d out of range", q, v);
+            if (seen[v]) fail(PBNG_EINVAL, "problem %d: Dirichlet index %d repeated", q, v);
+            seen[v] = 1;
+        }
+        if (!finite_arr(p->dirichlet_x, 3ll * p->n_dirichlet)) fail(PBNG_ENAN, "problem %d: non-finite Dirichlet target", q);
+    }
+    if (p->n_wc < 0) fail(PBNG_EINVAL, "problem %d: bad n_wc", q);
+    if (p->n_wc > 0) {
+        if (!p->wc_ptr || !p->wc_vert || !p->wc_w || !p->wc_K) fail(PBNG_EINVAL, "problem %d: weak-constraint arrays are null", q);
+        if (p->wc_ptr[0] != 0) fail(PBNG_EINVAL, "problem %d: wc_ptr[0] must be 0", q);
+        for (int c = 0; c < p->n_wc; ++c)
+            if (p->wc_ptr[c + 1] < p->wc_ptr[c]) fail(PBNG_EINVAL, "problem %d: wc_ptr not monotone", q);
+        const int nnz = p->wc_ptr[p->n_wc];
+        for (int k = 0; k < nnz; ++k)
+            if (p->wc_vert[k] < 0 || p->wc_vert[k] >= p->n_verts) fail(PBNG_EMESH, "problem %d: weak-constraint vertex out of range", q);
+        for (int c = 0; c < p->n_wc; ++c)
+            for (int k = p->wc_ptr[c]; k < p->wc_ptr[c + 1]; ++k)
+                for (int j = p->wc_ptr[c]; j < k; ++j)
+                    if (p->wc_vert[j] == p->wc_vert[k]) fail(PBNG_EMESH, "problem %d: weak constraint %d repeats a vertex", q, c);
+        if (!finite_arr(p->wc_w, nnz) || !finite_arr(p->wc_K, 6ll * p->n_wc)) fail(PBNG_ENAN, "problem %d: non-finite weak constraint", q);
+    }
+    if (p->n_planes < 0) fail(PBNG_EINVAL, "problem %d: bad n_planes", q);
+    if (p->n_planes > 0) {
+        if (!p->planes) fail(PBNG_EINVAL, "problem %d: planes is null", q);
+        if (!finite_arr(p->planes, 5ll * p->n_planes)) fail(PBNG_ENAN, "problem %d: non-finite plane", q);
+        for (int k = 0; k < p->n_planes; ++k)
+            if (p->planes[5 * k + 4] < 0.0) fail(PBNG_EINVAL, "problem %d: plane stiffness < 0", q);
+    }
+}
+
+// Vertex -> incident tets (ascending tet index, with local slot) and
+// vertex -> incident weak constraints.
+struct Incidence {
+    std::vector<int> tptr, tlist, cptr, clist, cpos;
+};
+
+Incidence incidence(const pbng_problem* p)
+{
+    Incidence I;
+    const int nv = p->n_verts;
+    I.tptr.assign(nv + 1, 0);
+    for (int64_t e = 0; e < p->n_tets; ++e)
+        for (int j = 0; j < 4; ++j) I.tptr[p->tets[4 * e + j] + 1]++;
+    for (int i = 0; i < nv; ++i) I.tptr[i + 1] += I.tptr[i];
+    I.tlist.resize(I.tptr[nv]);
+    std::vector<int> fill(I.tptr.begin(), I.tptr.end() - 1);
+    for (int64_t e = 0; e < p->n_tets; ++e)
+        for (int j = 0; j < 4; ++j) I.tlist[fill[p->tets[4 * e + j]]++] = int(4 * e + j);
+    const int nnz = p->n_wc > 0 ? p->wc_ptr[p->n_wc] : 0;
+    I.cptr.assign(nv + 1, 0);
+    for (int k = 0; k < nnz; ++k) I.cptr[p->wc_vert[k] + 1]++;
+    for (int i = 0; i < nv; ++i) I.cptr[i + 1] += I.cptr[i];
+    I.clist.resize(nnz);
+    I.cpos.resize(nnz);
+    std::vector<int> f2(I.cptr.begin(), I.cptr.end() - 1);
+    for (int c = 0; c < p->n_wc; ++c)
+        for (int k = p->wc_ptr[c]; k < p->wc_ptr[c + 1]; ++k) {
+            const int v = p->wc_vert[k];
+            I.clist[f2[v]] = c;
+            I.cpos[f2[v]] = k;
+            f2[v]++;
+        }
+    return I;
+}
+
+std::vector<char> dirichlet_mask(const pbng_problem* p)
+{
+    std::vector<char> d(p->n_verts, 0);
+    for (int k = 0; k < p->n_dirichlet; ++k) d[p->dirichlet_idx[k]] = 1;
+    return d;
+}
+
+// Greedy node colouring with used-colour sets S_c held as 64-bit masks on
+// every tet and weak constraint (Sec. "Coloring and Parallelism").
+int color_instance(const pbng_problem* p, int32_t* colors)
+{
+    const Incidence I = incidence(p);
+    const std::vector<char> dir = dirichlet_mask(p);
+    std::vector<uint64_t> St(p->n_tets, 0), Sc(p->n_wc, 0);
+    int ncol = 0;
+    for (int i = 0; i < p->n_verts; ++i) {
+        if (dir[i]) {
+            colors[i] = -1;
+            continue;
+        }
+        uint64_t used = 0;
+        for (int k = I.tptr[i]; k < I.tptr[i + 1]; ++k) used |= St[I.tlist[k] >> 2];
+        for (int k = I.cptr[i]; k < I.cptr[i + 1]; ++k) used |= Sc[I.clist[k]];
+        if (used == ~uint64_t(0)) fail(PBNG_ECOLOR, "more than 64 colours needed at vertex %d", i);
+        const int c = __builtin_ctzll(~used);
+        colors[i] = c;
+        ncol = std::max(ncol, c + 1);
+        const uint64_t bit = uint64_t(1) << c;
+        for (int k = I.tptr[i]; k < I.tptr[i + 1]; ++k) St[I.tlist[k] >> 2] |= bit;
+        for (int k = I.cptr[i]; k < I.cptr[i + 1]; ++k) Sc[I.clist[k]] |= bit;
+    }
+    return ncol;
+}
+
+int check_colors(const pbng_problem* p, const int32_t* colors)
+{
+    const std::vector<char> dir = dirichlet_mask(p);
+    int ncol = 0;
+    for (int i = 0; i < p->n_verts; ++i) {
+        if (dir[i]) {
+            if (colors[i] != -1) fail(PBNG_ECOLOR, "Dirichlet vertex %d must have colour -1", i);
+            continue;
+        }
+        if (colors[i] < 0 || colors[i] >= 64) fail(PBNG_ECOLOR, "vertex %d has colour %d outside [0, 64)", i, colors[i]);
+        ncol = std::max(ncol, colors[i] + 1);
+    }
+    for (int64_t e = 0; e < p->n_tets; ++e) {
+        uint64_t m = 0;
+        for (int j = 0; j < 4; ++j) {
+            const int c = colors[p->tets[4 * e + j]];
+            if (c < 0) continue;
+            if (m >> c & 1) fail(PBNG_ECOLOR, "tet %lld has two vertices of colour %d", (long long)e, c);
+            m |= uint64_t(1) << c;
+        }
+    }
+    for (int k = 0; k < p->n_wc; ++k) {
+        uint64_t m = 0;
+        for (int j = p->wc_ptr[k]; j < p->wc_ptr[k + 1]; ++j) {
+            const int c = colors[p->wc_vert[j]];
+            if (c < 0) continue;
+            if (m >> c & 1) fail(PBNG_ECOLOR, "weak constraint %d has two vertices of colour %d", k, c);
+            m |= uint64_t(1) << c;
+        }
+    }
+    return ncol;
+}
+
+double now_ms()
+{
+    using namespace std::chrono;
+    return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Workspace
+// ---------------------------------------------------------------------------
+struct pbng_workspace {
+    int real = PBNG_F32;
+    int model = PBNG_NEOHOOKEAN;
+    int n_inst = 0;
+    int64_t nv = 0, nt = 0, nfree = 0, nvis = 0, nvis_all = 0;
+    int ncol = 0;
+    int n_wc = 0, n_planes = 0, nd = 0;
+    bool any_wc = false;
+    int device = 0;
+    std::vector<int> col_ptr;              // internal free-vertex range of each colour
+    std::vector<int64_t> v_off, t_off;     // per instance
+    std::vector<int> ncol_inst;
+    std::vector<int64_t> nfree_inst;
+    std::vector<int64_t> phase_bytes, phase_verts, phase_visits;
+    double mean_valence = 0.0;
+
+    // sweep data
+    Dev W, P, N, Wres;
+    Dev j1, j2, j3, m, vmu, vlam, vptr, fext, vinst, active, rejected;
+    Dev wvptr, wv_c, wv_s, wc_ptr, wc_vert, wc_w, wc_K, plane_ptr, planes;
+    // FP64 data
+    Dev tet, geo, vp, ebuf, tet_eidx, vorder, vert_eidx, rvptr, rv, fext64, vinst_all;
+    Dev wv_s64, wc_w64, wc_K64, wc_eidx, planes64, orig_of, rsq;
+    Dev xd_int, dir_internal, dir_pos;
+    Dev seg_r_cb, seg_r_ce, seg_r_q, seg_r_part, seg_e_cb, seg_e_ce, seg_e_q, seg_e_part;
+    SegPlan plan_r, plan_e;
+    Dev out_r, out_e;
+    double* hbuf = nullptr;  // pinned [2 n_inst]
+    int* hact = nullptr;     // pinned [n_inst]
+    // adjoint
+    Dev L, LP, LN, B;
+
+    // acceleration state
+    int64_t sweep_l = 0;
+    double omega_l = 1.0;
+    bool ring_valid = false;
+
+    ~pbng_workspace()
+    {
+        if (hbuf) (void)hipHostFree(hbuf);
+        if (hact) (void)hipHostFree(hact);
+    }
+    size_t r4() const { return real == PBNG_F64 ? 32 : 16; }
+    size_t rs() const { return real == PBNG_F64 ? 8 : 4; }
+};
+
+namespace {
+
+template <class R>
+void upload_real(Dev& d, const std::vector<double>& v)
+{
+    std::vector<R> t(v.begin(), v.end());
+    d.upload(t);
+}
+
+SegPlan make_plan(const std::vector<int64_t>& seg, Dev& cb, Dev& ce, Dev& qp, Dev& part)
+{
+    const int64_t chunk = 4096;
+    std::vector<int64_t> b, e;
+    std::vector<int> q(seg.size(), 0);
+    for (size_t i = 0; i + 1 < seg.size(); ++i) {
+        q[i] = int(b.size());
+        for (int64_t s = seg[i]; s < seg[i + 1]; s += chunk) {
+            b.push_back(s);
+            e.push_back(std::min(seg[i + 1], s + chunk));
+        }
+    }
+    q.back() = int(b.size());
+    cb.upload(b);
+    ce.upload(e);
+    qp.upload(q);
+    part.alloc(std::max<size_t>(1, b.size()) * sizeof(double));
+    SegPlan P;
+    P.cbeg = cb.as<int64_t>();
+    P.cend = ce.as<int64_t>();
+    P.qptr = qp.as<int>();
+    P.partial = part.as<double>();
+    P.n_chunks = int(b.size());
+    return P;
+}
+
+void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const int32_t* colors_in)
+{
+    ws->n_inst = n;
+    ws->model = ps[0].model;
+    ws->v_off.assign(n + 1, 0);
+    ws->t_off.assign(n + 1, 0);
+    std::vector<int64_t> c_off(n + 1, 0), p_off(n + 1, 0), d_off(n + 1, 0);
+    for (int q = 0; q < n; ++q) {
+        validate_problem(ps + q, q);
+        if (ps[q].model != ws->model) fail(PBNG_EINVAL, "all instances of a workspace must use the same model");
+        ws->v_off[q + 1] = ws->v_off[q] + ps[q].n_verts;
+        ws->t_off[q + 1] = ws->t_off[q] + ps[q].n_tets;
+        c_off[q + 1] = c_off[q] + ps[q].n_wc;
+        p_off[q + 1] = p_off[q] + ps[q].n_planes;
+        d_off[q + 1] = d_off[q] + ps[q].n_dirichlet;
+    }
+    const int64_t nv = ws->v_off[n], nt = ws->t_off[n];
+    if (nv >= (int64_t(1) << 31) / 2 || nt >= (int64_t(1) << 29))
+        fail(PBNG_EINVAL, "problem too large for 32-bit indices");
+    ws->nv = nv;
+    ws->nt = nt;
+    ws->n_wc = int(c_off[n]);
+    ws->n_planes = int(p_off[n]);
+    ws->nd = int(d_off[n]);
+    ws->any_wc = ws->n_wc > 0 || ws->n_planes > 0;
+
+    // colours, rest data, loads
+    std::vector<int32_t> colors(nv);
+    std::vector<double> dminv(9 * nt), V0(nt), mu(nt), lam(nt);
+    std::vector<double> fext(3 * nv, 0.0);
+    std::vector<char> isdir(nv, 0);
+    std::vector<int> valence(nv, 0);
+    std::vector<Incidence> inc(n);
+    ws->ncol_inst.assign(n, 0);
+    ws->nfree_inst.assign(n, 0);
+    for (int q = 0; q < n; ++q) {
+        const pbng_problem* p = ps + q;
+        const int64_t vo = ws->v_off[q], to = ws->t_off[q];
+        int nc;
+        if (colors_in) {
+            nc = check_colors(p, colors_in + vo);
+            std::copy(colors_in + vo, colors_in + vo + p->n_verts, colors.begin() + vo);
+        } else {
+            nc = color_instance(p, colors.data() + vo);
+        }
+        ws->ncol_inst[q] = nc;
+        ws->ncol = std::max(ws->ncol, nc);
+        for (int64_t e = 0; e < p->n_tets; ++e) {
+            if (!tet_rest(p->rest_pos, p->tets + 4 * e, &dminv[9 * (to + e)], &V0[to + e]))
+                fail(PBNG_EMESH, "problem %d: tet %lld has rest volume <= 0", q, (long long)e);
+            mu[to + e] = p->mu_tet ? p->mu_tet[e] : p->mu;
+            lam[to + e] = p->mu_tet ? p->lambda_tet[e] : p->lambda;
+            for (int j = 0; j < 4; ++j)
+                for (int a = 0; a < 3; ++a)
+                    fext[3 * (vo + p->tets[4 * e + j]) + a] += p->density * p->gravity[a] * V0[to + e] / 4.0;
+        }
+        if (p->nodal_force)
+            for (int64_t i = 0; i < 3ll * p->n_verts; ++i) fext[3 * vo + i] += p->nodal_force[i];
+        for (int k = 0; k < p->n_dirichlet; ++k) isdir[vo + p->dirichlet_idx[k]] = 1;
+        inc[q] = incidence(p);
+        for (int i = 0; i < p->n_verts; ++i) {
+            valence[vo + i] = inc[q].tptr[i + 1] - inc[q].tptr[i];
+            if (!isdir[vo + i]) ws->nfree_inst[q]++;
+        }
+    }
+    if (ws->ncol > 64) fail(PBNG_ECOLOR, "more than 64 colours");
+
+    // internal order
+    std::vector<int> inst_of(nv);
+    for (int q = 0; q < n; ++q)
+        for (int64_t i = ws->v_off[q]; i < ws->v_off[q + 1]; ++i) inst_of[i] = q;
+    std::vector<int> order;
+    order.reserve(nv);
+    for (int64_t i = 0; i < nv; ++i)
+        if (!isdir[i]) order.push_back(int(i));
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (colors[a] != colors[b]) return colors[a] < colors[b];
+        if (inst_of[a] != inst_of[b]) return inst_of[a] < inst_of[b];
+        if (valence[a] != valence[b]) return valence[a] > valence[b];
+        return a < b;
+    });
+    const int64_t nfree = int64_t(order.size());
+    ws->nfree = nfree;
+    for (int64_t i = 0; i < nv; ++i)
+        if (isdir[i]) order.push_back(int(i));
+    std::vector<int> int_of(nv);
+    for (int64_t k = 0; k < nv; ++k) int_of[order[k]] = int(k);
+    ws->col_ptr.assign(ws->ncol + 1, 0);
+    for (int64_t k = 0; k < nfree; ++k) ws->col_ptr[colors[order[k]] + 1]++;
+    for (int c = 0; c < ws->ncol; ++c) ws->col_ptr[c + 1] += ws->col_ptr[c];
+
+    // visits: free vertices first (their records drive the sweeps), then
+    // Dirichlet vertices (FP64 gathers only)
+    std::vector<int> rvptr(nv + 1, 0), rv;
+    std::vector<int> J1, J2, J3;
+    std::vector<double> M9, VMU, VLAM;
+    rv.reserve(4 * nt);
+    for (int64_t k = 0; k < nv; ++k) {
+        const int gv = order[k];
+        const int q = inst_of[gv];
+        const int64_t vo = ws->v_off[q], to = ws->t_off[q];
+        const int li = int(gv - vo);
+        const Incidence& I = inc[q];
+        for (int s = I.tptr[li]; s < I.tptr[li + 1]; ++s) {
+            const int64_t e = to + (I.tlist[s] >> 2);
+            const int slot = I.tlist[s] & 3;
+            rv.push_back(int(e * 4 + slot));
+            if (k < nfree) {
+                int others[3], no = 0;
+                double mrow[9];
+                for (int j = 0; j < 4; ++j) {
+                    if (j == slot) continue;
+                    others[no] = int_of[vo + ps[q].tets[4 * (e - to) + j]];
+                    // dN_j: row j-1 of Dm^{-1}, or minus the sum of the rows for j = 0
+                    for (int c = 0; c < 3; ++c)
+                        mrow[3 * no + c] = (j == 0) ? -(dminv[9 * e + c] + dminv[9 * e + 3 + c] + dminv[9 * e + 6 + c])
+                                                    : dminv[9 * e + 3 * (j - 1) + c];
+                    ++no;
+                }
+                J1.push_back(others[0]);
+                J2.push_back(others[1]);
+                J3.push_back(others[2]);
+                for (int c = 0; c < 9; ++c) M9.push_back(mrow[c]);
+                VMU.push_back(V0[e] * mu[e]);
+                VLAM.push_back(V0[e] * lam[e]);
+            }
+        }
+        rvptr[k + 1] = int(rv.size());
+    }
+    ws->nvis = int64_t(J1.size());
+    ws->nvis_all = int64_t(rv.size());
+    ws->mean_valence = nfree > 0 ? double(ws->nvis) / double(nfree) : 0.0;
+
+    // SoA [9][nvis]
+    std::vector<double> Msoa(9 * ws->nvis);
+    for (int64_t k = 0; k < ws->nvis; ++k)
+        for (int c = 0; c < 9; ++c) Msoa[c * ws->nvis + k] = M9[9 * k + c];
+
+    // algorithmic bytes per colour phase
+    ws->phase_bytes.assign(ws->ncol, 0);
+    ws->phase_verts.assign(ws->ncol, 0);
+    ws->phase_visits.assign(ws->ncol, 0);
+    {
+        std::vector<int> mark(nv, -1);
+        for (int c = 0; c < ws->ncol; ++c) {
+            int64_t uniq = 0;
+            const int64_t vis = int64_t(rvptr[ws->col_ptr[c + 1]]) - rvptr[ws->col_ptr[c]];
+            for (int64_t k = rvptr[ws->col_ptr[c]]; k < rvptr[ws->col_ptr[c + 1]]; ++k)
+                for (int o : {J1[k], J2[k], J3[k]})
+                    if (mark[o] != c) {
+                        mark[o] = c;
+                        ++uniq;
+                    }
+            ws->phase_visits[c] = vis;
+            ws->phase_verts[c] = ws->col_ptr[c + 1] - ws->col_ptr[c];
+            ws->phase_bytes[c] = vis * 60 + ws->phase_verts[c] * 24 + uniq * 12;
+        }
+    }
+
+    // per-vertex arrays in internal order
+    std::vector<double> fext_int(3 * nv), fext_free(4 * nfree, 0.0);
+    std::vector<int> vinst_all(nv), orig_of(nv);
+    for (int64_t k = 0; k < nv; ++k) {
+        const int gv = order[k];
+        orig_of[k] = gv;
+        vinst_all[k] = inst_of[gv];
+        for (int a = 0; a < 3; ++a) fext_int[3 * k + a] = fext[3 * gv + a];
+        if (k < nfree)
+            for (int a = 0; a < 3; ++a) fext_free[4 * k + a] = fext[3 * gv + a];
+    }
+
+    // weak constraints: global list with internal members, per-vertex CSR
+    std::vector<int> wc_ptr(ws->n_wc + 1, 0), wc_vert, wvptr(nv + 1, 0), wv_c;
+    std::vector<double> wc_w, wc_K, wv_s;
+    {
+        std::vector<std::vector<std::pair<int, double>>> per(nv);
+        for (int q = 0; q < n; ++q) {
+            const pbng_problem* p = ps + q;
+            for (int c = 0; c < p->n_wc; ++c) {
+                const int gc = int(c_off[q] + c);
+                for (int k = p->wc_ptr[c]; k < p->wc_ptr[c + 1]; ++k) {
+                    const int iv = int_of[ws->v_off[q] + p->wc_vert[k]];
+                    wc_vert.push_back(iv);
+                    wc_w.push_back(p->wc_w[k]);
+                    per[iv].push_back({gc, p->wc_w[k]});
+                }
+                wc_ptr[gc + 1] = int(wc_vert.size());
+                for (int j = 0; j < 6; ++j) wc_K.push_back(p->wc_K[6 * c + j]);
+            }
+        }
+        for (int64_t k = 0; k < nv; ++k) {
+            for (auto& pr : per[k]) {
+                wv_c.push_back(pr.first);
+                wv_s.push_back(pr.second);
+            }
+            wvptr[k + 1] = int(wv_c.size());
+        }
+    }
+    std::vector<int> plane_ptr(n + 1, 0);
+    std::vector<double> planes;
+    for (int q = 0; q < n; ++q) {
+        for (int k = 0; k < 5 * ps[q].n_planes; ++k) planes.push_back(ps[q].planes[k]);
+        plane_ptr[q + 1] = int(p_off[q + 1]);
+    }
+
+    // FP64 tet data and energy slots
+    std::vector<int4> tet(nt);
+    std::vector<TetGeo> geo(nt);
+    std::vector<int> tet_eidx(nt), vert_eidx(nv), wc_eidx(ws->n_wc), vorder(nv);
+    std::vector<int64_t> seg_r(n + 1), seg_e(n + 1);
+    for (int q = 0; q < n; ++q) {
+        const pbng_problem* p = ps + q;
+        const int64_t vo = ws->v_off[q], to = ws->t_off[q];
+        const int64_t eo = to + vo + c_off[q];
+        seg_r[q] = vo;
+        seg_e[q] = eo;
+        for (int64_t e = 0; e < p->n_tets; ++e) {
+            const int32_t* t = p->tets + 4 * e;
+            tet[to + e] = int4{int_of[vo + t[0]], int_of[vo + t[1]], int_of[vo + t[2]], int_of[vo + t[3]]};
+            TetGeo& G = geo[to + e];
+            for (int c = 0; c < 9; ++c) G.dm[c] = dminv[9 * (to + e) + c];
+            G.V0 = V0[to + e];
+            G.mu = mu[to + e];
+            G.lam = lam[to + e];
+            tet_eidx[to + e] = int(eo + e);
+        }
+        for (int i = 0; i < p->n_verts; ++i) {
+            vorder[vo + i] = int_of[vo + i];
+            vert_eidx[vo + i] = int(eo + p->n_tets + i);
+        }
+        for (int c = 0; c < p->n_wc; ++c) wc_eidx[c_off[q] + c] = int(eo + p->n_tets + p->n_verts + c);
+    }
+    seg_r[n] = nv;
+    seg_e[n] = nt + nv + ws->n_wc;
+
+    // Dirichlet targets
+    std::vector<int> dir_internal(ws->nd), dir_pos(nv - nfree);
+    std::vector<double> xd_int(4 * (nv - nfree), 0.0);
+    {
+        int k = 0;
+        for (int q = 0; q < n; ++q)
+            for (int j = 0; j < ps[q].n_dirichlet; ++j, ++k) {
+                const int iv = int_of[ws->v_off[q] + ps[q].dirichlet_idx[j]];
+                dir_internal[k] = iv;
+                dir_pos[iv - nfree] = k;
+                for (int a = 0; a < 3; ++a) xd_int[4 * (iv - nfree) + a] = ps[q].dirichlet_x[3 * j + a];
+            }
+    }
+
+    // upload (the first HIP call: everything above is host-side validation and packing)
+    hipchk(hipGetDevice(&ws->device), "hipGetDevice");
+    const bool f64 = ws->real == PBNG_F64;
+    auto upR = [&](Dev& d, const std::vector<double>& v) {
+        if (f64) upload_real<double>(d, v);
+        else upload_real<float>(d, v);
+    };
+    std::vector<int> vptr_free(rvptr.begin(), rvptr.begin() + nfree + 1);
+    ws->vptr.upload(vptr_free);
+    ws->j1.upload(J1);
+    ws->j2.upload(J2);
+    ws->j3.upload(J3);
+    upR(ws->m, Msoa);
+    upR(ws->vmu, VMU);
+    upR(ws->vlam, VLAM);
+    upR(ws->fext, fext_free);
+    std::vector<int> vinst_free(vinst_all.begin(), vinst_all.begin() + nfree);
+    ws->vinst.upload(vinst_free);
+    ws->active.alloc(n * sizeof(int));
+    ws->rejected.alloc(n * sizeof(int));
+    ws->wvptr.upload(wvptr);
+    ws->wv_c.upload(wv_c);
+    upR(ws->wv_s, wv_s);
+    ws->wc_ptr.upload(wc_ptr);
+    ws->wc_vert.upload(wc_vert);
+    upR(ws->wc_w, wc_w);
+    upR(ws->wc_K, wc_K);
+    ws->plane_ptr.upload(plane_ptr);
+    upR(ws->planes, planes);
+    ws->tet.upload(tet);
+    ws->geo.upload(geo);
+    ws->vp.alloc(std::max<int64_t>(1, nt) * 9 * sizeof(double));
+    ws->ebuf.alloc(std::max<int64_t>(1, nt + nv + ws->n_wc) * sizeof(double));
+    ws->tet_eidx.upload(tet_eidx);
+    ws->vorder.upload(vorder);
+    ws->vert_eidx.upload(vert_eidx);
+    ws->rvptr.upload(rvptr);
+    ws->rv.upload(rv);
+    ws->fext64.upload(fext_int);
+    ws->vinst_all.upload(vinst_all);
+    ws->wv_s64.upload(wv_s);
+    ws->wc_w64.upload(wc_w);
+    ws->wc_K64.upload(wc_K);
+    ws->wc_eidx.upload(wc_eidx);
+    ws->planes64.upload(planes);
+    ws->orig_of.upload(orig_of);
+    ws->rsq.alloc(std::max<int64_t>(1, nv) * sizeof(double));
+    upR(ws->xd_int, xd_int);
+    ws->dir_internal.upload(dir_internal);
+    ws->dir_pos.upload(dir_pos);
+    ws->plan_r = make_plan(seg_r, ws->seg_r_cb, ws->seg_r_ce, ws->seg_r_q, ws->seg_r_part);
+    ws->plan_e = make_plan(seg_e, ws->seg_e_cb, ws->seg_e_ce, ws->seg_e_q, ws->seg_e_part);
+    ws->out_r.alloc(n * sizeof(double));
+    ws->out_e.alloc(n * sizeof(double));
+    ws->W.alloc(nv * ws->r4());
+    ws->Wres.alloc(nv * ws->r4());
+    hipchk(hipHostMalloc((void**)&ws->hbuf, 2 * n * sizeof(double)), "hipHostMalloc");
+    hipchk(hipHostMalloc((void**)&ws->hact, n * sizeof(int)), "hipHostMalloc");
+    hipchk(hipDeviceSynchronize(), "upload");
+}
+
+template <class R>
+SweepArgs<R> sweep_args(pbng_workspace* ws, double omega, double gamma, int max_halvings)
+{
+    using R4 = typename R4t<R>::T;
+    SweepArgs<R> a;
+    a.W = ws->W.as<R4>();
+    a.P = ws->P.as<R4>();
+    a.N = ws->N.as<R4>();
+    a.vptr = ws->vptr.as<int>();
+    a.j1 = ws->j1.as<int>();
+    a.j2 = ws->j2.as<int>();
+    a.j3 = ws->j3.as<int>();
+    a.m = ws->m.as<R>();
+    a.vmu = ws->vmu.as<R>();
+    a.vlam = ws->vlam.as<R>();
+    a.nvis = ws->nvis;
+    a.fext = ws->fext.as<R4>();
+    a.vinst = ws->vinst.as<int>();
+    a.active = ws->active.as<int>();
+    a.wvptr = ws->wvptr.as<int>();
+    a.wv_c = ws->wv_c.as<int>();
+    a.wv_s = ws->wv_s.as<R>();
+    a.wc_ptr = ws->wc_ptr.as<int>();
+    a.wc_vert = ws->wc_vert.as<int>();
+    a.wc_w = ws->wc_w.as<R>();
+    a.wc_K = ws->wc_K.as<R>();
+    a.plane_ptr = ws->plane_ptr.as<int>();
+    a.planes = ws->planes.as<R>();
+    a.rejected = ws->rejected.as<int>();
+    a.omega = R(omega);
+    a.gamma = R(gamma);
+    a.max_halvings = max_halvings;
+    return a;
+}
+
+template <class R>
+ResArgs<R> res_args(pbng_workspace* ws, const void* X)
+{
+    using R4 = typename R4t<R>::T;
+    ResArgs<R> a;
+    a.X = static_cast<const R4*>(X);
+    a.tet = ws->tet.as<int4>();
+    a.geo = ws->geo.as<TetGeo>();
+    a.vp = ws->vp.as<double>();
+    a.ebuf = ws->ebuf.as<double>();
+    a.tet_eidx = ws->tet_eidx.as<int>();
+    a.vorder = ws->vorder.as<int>();
+    a.vert_eidx = ws->vert_eidx.as<int>();
+    a.rvptr = ws->rvptr.as<int>();
+    a.rv = ws->rv.as<int>();
+    a.fext64 = ws->fext64.as<double>();
+    a.vinst_all = ws->vinst_all.as<int>();
+    a.wvptr = ws->wvptr.as<int>();
+    a.wv_c = ws->wv_c.as<int>();
+    a.wv_s64 = ws->wv_s64.as<double>();
+    a.wc_ptr = ws->wc_ptr.as<int>();
+    a.wc_vert = ws->wc_vert.as<int>();
+    a.wc_w64 = ws->wc_w64.as<double>();
+    a.wc_K64 = ws->wc_K64.as<double>();
+    a.wc_eidx = ws->wc_eidx.as<int>();
+    a.plane_ptr = ws->plane_ptr.as<int>();
+    a.planes64 = ws->planes64.as<double>();
+    a.orig_of = ws->orig_of.as<int>();
+    a.n_free = int(ws->nfree);
+    a.n_verts = int(ws->nv);
+    a.n_tets = int(ws->nt);
+    a.n_wc = ws->n_wc;
+    a.model = ws->model;
+    return a;
+}
+
+// FP64 residual norms and energies of positions X (internal order) into
+// ws->hbuf[0..n) and ws->hbuf[n..2n); synchronises the stream.
+template <class R>
+void residual_internal(pbng_workspace* ws, const void* X, double* r_out, hipStream_t s)
+{
+    const ResArgs<R> a = res_args<R>(ws, X);
+    hipchk(launch_residual<R>(a, ws->rsq.as<double>(), r_out, s), "residual");
+    hipchk(launch_segsum(ws->rsq.as<double>(), ws->plan_r, ws->n_inst, ws->out_r.as<double>(), s), "residual sum");
+    hipchk(launch_segsum(ws->ebuf.as<double>(), ws->plan_e, ws->n_inst, ws->out_e.as<double>(), s), "energy sum");
+    hipchk(hipMemcpyAsync(ws->hbuf, ws->out_r.p, ws->n_inst * sizeof(double), hipMemcpyDeviceToHost, s), "d2h");
+    hipchk(hipMemcpyAsync(ws->hbuf + ws->n_inst, ws->out_e.p, ws->n_inst * sizeof(double), hipMemcpyDeviceToHost, s), "d2h");
+    hipchk(hipStreamSynchronize(s), "sync");
+    for (int q = 0; q < ws->n_inst; ++q) ws->hbuf[q] = std::sqrt(ws->hbuf[q]);
+}
+
+int pick_lanes(const pbng_workspace* ws, int requested)
+{
+    if (requested == 1 || requested == 2 || requested == 4 || requested == 8 || requested == 16) return requested;
+    if (requested != 0) fail(PBNG_EINVAL, "lanes must be 0, 1, 2, 4, 8 or 16");
+    const double mv = ws->mean_valence;
+    if (mv >= 24) return 8;
+    if (mv >= 10) return 4;
+    if (mv >= 4) return 2;
+    return 1;
+}
+
+void check_solve_opts(const pbng_solve_opts* o)
+{
+    if (!o) fail(PBNG_EINVAL, "options are null");
+    if (o->max_sweeps < 0 || o->check_every < 1) fail(PBNG_EINVAL, "max_sweeps must be >= 0 and check_every >= 1");
+    if (o->accel < 0 || o->accel > 2) fail(PBNG_EINVAL, "unknown acceleration %d", o->accel);
+    if (o->safeguard < 0 || o->safeguard > 1) fail(PBNG_EINVAL, "unknown safeguard %d", o->safeguard);
+    if (o->max_halvings < 0 || o->max_halvings > 60) fail(PBNG_EINVAL, "max_halvings out of range");
+    if (!std::isfinite(o->rel_tol) || o->rel_tol < 0) fail(PBNG_EINVAL, "rel_tol must be >= 0");
+    if (o->accel == PBNG_ACCEL_CHEBYSHEV && !(o->rho > 0 && o->rho < 1 && o->gamma > 0))
+        fail(PBNG_EINVAL, "Chebyshev needs 0 < rho < 1 and gamma > 0");
+    if (o->accel == PBNG_ACCEL_SOR && !(o->omega > 0 && o->omega < 2)) fail(PBNG_EINVAL, "SOR needs 0 < omega < 2");
+}
+
+// Chebyshev weight for the sweep that produces x^{l+1} (Sec. "Acceleration
+// Techniques"): 1 for l < 2, 2 / (2 - rho^2) for l = 2, 4 / (4 - rho^2
+// omega_l) for l > 2.
+double chebyshev_next(int64_t l, double rho, double prev)
+{
+    if (l < 2) return 1.0;
+    if (l == 2) return 2.0 / (2.0 - rho * rho);
+    return 4.0 / (4.0 - rho * rho * prev);
+}
+
+template <class R>
+void ensure_ring(pbng_workspace* ws)
+{
+    if (!ws->P.p) ws->P.alloc(ws->nv * ws->r4());
+    if (!ws->N.p) ws->N.alloc(ws->nv * ws->r4());
+}
+
+template <class R>
+void launch_sweep(pbng_workspace* ws, const pbng_solve_opts* o, int lanes, double omega,
+                  double gamma, hipStream_t s)
+{
+    const bool accel = o->accel != PBNG_ACCEL_NONE;
+    const SweepArgs<R> a = sweep_args<R>(ws, omega, gamma, o->max_halvings);
+    for (int c = 0; c < ws->ncol; ++c)
+        hipchk(launch_phase<R>(a, ws->model, lanes, accel, o->safeguard == PBNG_SAFEGUARD_BACKTRACK,
+                               ws->any_wc, ws->col_ptr[c], ws->col_ptr[c + 1], s),
+               "sweep launch");
+    if (accel) std::swap(ws->W.p, ws->N.p);
+}
+
+template <class R>
+int32_t solve_t(pbng_workspace* ws, void* x, const pbng_solve_opts* o, pbng_stats* st, hipStream_t s)
+{
+    using R4 = typename R4t<R>::T;
+    const int n = ws->n_inst;
+    const bool accel = o->accel != PBNG_ACCEL_NONE;
+    const int lanes = pick_lanes(ws, o->lanes);
+    if (accel) ensure_ring<R>(ws);
+    const bool resume = o->resume && ws->ring_valid;
+    if (!resume) {
+        hipchk(launch_load<R>(static_cast<const R*>(x), ws->orig_of.as<int>(), ws->xd_int.as<R4>(),
+                              ws->W.as<R4>(), accel ? ws->P.as<R4>() : nullptr,
+                              accel ? ws->N.as<R4>() : nullptr, int(ws->nfree), int(ws->nv), s),
+               "load");
+        ws->sweep_l = 0;
+        ws->omega_l = 1.0;
+    } else {
+        hipchk(launch_load<R>(static_cast<const R*>(x), ws->orig_of.as<int>(), ws->xd_int.as<R4>(),
+                              ws->W.as<R4>(), nullptr, nullptr, int(ws->nfree), int(ws->nv), s),
+               "load");
+    }
+    ws->ring_valid = accel;
+    hipchk(hipMemsetAsync(ws->rejected.p, 0, n * sizeof(int), s), "memset");
+    residual_internal<R>(ws, ws->W.p, nullptr, s);
+    std::vector<double> r0(ws->hbuf, ws->hbuf + n), rr(r0), en(ws->hbuf + n, ws->hbuf + 2 * n);
+    std::vector<int> act(n, 1), sweeps(n, 0), conv(n, 0);
+    std::vector<double> ttol(n, -1.0);
+    for (int q = 0; q < n; ++q) {
+        if (!std::isfinite(r0[q])) fail(PBNG_ENAN, "instance %d: non-finite initial residual", q);
+        if (r0[q] == 0.0 || (o->rel_tol > 0 && r0[q] <= 0.0)) {
+            act[q] = 0;
+            conv[q] = 1;
+            ttol[q] = 0.0;
+        }
+    }
+    auto push_active = [&]() {
+        for (int q = 0; q < n; ++q) ws->hact[q] = act[q];
+        hipchk(hipMemcpyAsync(ws->active.p, ws->hact, n * sizeof(int), hipMemcpyHostToDevice, s), "h2d");
+    };
+    push_active();
+    hipchk(hipStreamSynchronize(s), "sync");
+    const double t0 = now_ms();
+    int n_active = 0;
+    for (int q = 0; q < n; ++q) n_active += act[q];
+    bool nan = false;
+    for (int sw = 0; sw < o->max_sweeps && n_active > 0; ++sw) {
+        double omega = 1.0, gamma = 1.0;
+        if (o->accel == PBNG_ACCEL_CHEBYSHEV) {
+            omega = chebyshev_next(ws->sweep_l, o->rho, ws->omega_l);
+            gamma = o->gamma;
+        } else if (o->accel == PBNG_ACCEL_SOR) {
+            omega = o->omega;
+        }
+        launch_sweep<R>(ws, o, lanes, omega, gamma, s);
+        ws->omega_l = omega;
+        ws->sweep_l++;
+        for (int q = 0; q < n; ++q) sweeps[q] += act[q];
+        if ((sw + 1) % o->check_every == 0 || sw + 1 == o->max_sweeps) {
+            residual_internal<R>(ws, ws->W.p, nullptr, s);
+            const double t = now_ms() - t0;
+            bool changed = false;
+            for (int q = 0; q < n; ++q) {
+                if (!act[q]) continue;
+                rr[q] = ws->hbuf[q];
+                en[q] = ws->hbuf[n + q];
+                if (!std::isfinite(rr[q])) {
+                    nan = true;
+                    act[q] = 0;
+                    changed = true;
+                    continue;
+                }
+                if (o->rel_tol > 0 && rr[q] <= o->rel_tol * r0[q]) {
+                    conv[q] = 1;
+                    ttol[q] = t;
+                    act[q] = 0;
+                    changed = true;
+                }
+            }
+            if (changed) {
+                n_active = 0;
+                for (int q = 0; q < n; ++q) n_active += act[q];
+                push_active();
+            }
+        }
+    }
+    hipchk(launch_store<R>(ws->W.as<R4>(), ws->orig_of.as<int>(), static_cast<R*>(x), int(ws->nv), s), "store");
+    std::vector<int> rej(n);
+    hipchk(hipMemcpyAsync(rej.data(), ws->rejected.p, n * sizeof(int), hipMemcpyDeviceToHost, s), "d2h");
+    hipchk(hipStreamSynchronize(s), "sync");
+    const double t_all = now_ms() - t0;
+    bool all = true;
+    for (int q = 0; q < n; ++q) {
+        all = all && conv[q];
+        if (st) {
+            st[q].sweeps = sweeps[q];
+            st[q].converged = conv[q];
+            st[q].n_colors = ws->ncol_inst[q];
+            st[q].rejected = rej[q];
+            st[q].residual0 = r0[q];
+            st[q].residual = rr[q];
+            st[q].rel_residual = r0[q] > 0 ? rr[q] / r0[q] : 0.0;
+            st[q].energy = en[q];
+            st[q].time_ms = t_all;
+            st[q].time_to_tol_ms = ttol[q];
+            st[q].vertex_updates = double(sweeps[q]) * double(ws->nfree_inst[q]);
+        }
+    }
+    if (nan) fail(PBNG_ENAN, "iterate became non-finite");
+    return all ? PBNG_OK : PBNG_NOT_CONVERGED;
+}
+
+template <class R>
+AdjArgs<R> adj_args(pbng_workspace* ws, double omega, double gamma)
+{
+    using R4 = typename R4t<R>::T;
+    AdjArgs<R> a;
+    a.X = ws->Wres.as<R4>();
+    a.L = ws->L.as<R4>();
+    a.P = ws->LP.as<R4>();
+    a.N = ws->LN.as<R4>();
+    a.B = ws->B.as<R4>();
+    a.vptr = ws->vptr.as<int>();
+    a.j1 = ws->j1.as<int>();
+    a.j2 = ws->j2.as<int>();
+    a.j3 = ws->j3.as<int>();
+    a.m = ws->m.as<R>();
+    a.vmu = ws->vmu.as<R>();
+    a.vlam = ws->vlam.as<R>();
+    a.nvis = ws->nvis;
+    a.vinst = ws->vinst.as<int>();
+    a.wvptr = ws->wvptr.as<int>();
+    a.wv_c = ws->wv_c.as<int>();
+    a.wv_s = ws->wv_s.as<R>();
+    a.wc_ptr = ws->wc_ptr.as<int>();
+    a.wc_vert = ws->wc_vert.as<int>();
+    a.wc_w = ws->wc_w.as<R>();
+    a.wc_K = ws->wc_K.as<R>();
+    a.plane_ptr = ws->plane_ptr.as<int>();
+    a.planes = ws->planes.as<R>();
+    a.omega = R(omega);
+    a.gamma = R(gamma);
+    return a;
+}
+
+template <class R>
+void adjoint_check(pbng_workspace* ws, double* dmu, double* dlam, double* dxd, hipStream_t s)
+{
+    using R4 = typename R4t<R>::T;
+    const ResArgs<R> a = res_args<R>(ws, ws->Wres.p);
+    hipchk(launch_adjoint_assembly<R>(a, ws->L.as<R4>(), ws->B.as<R4>(), ws->rsq.as<double>(), dmu, dlam, dxd,
+                                      ws->dir_pos.as<int>(), s),
+           "adjoint assembly");
+    hipchk(launch_segsum(ws->rsq.as<double>(), ws->plan_r, ws->n_inst, ws->out_r.as<double>(), s), "sum");
+    hipchk(hipMemcpyAsync(ws->hbuf, ws->out_r.p, ws->n_inst * sizeof(double), hipMemcpyDeviceToHost, s), "d2h");
+    hipchk(hipStreamSynchronize(s), "sync");
+    for (int q = 0; q < ws->n_inst; ++q) ws->hbuf[q] = std::sqrt(ws->hbuf[q]);
+}
+
+template <class R>
+int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double* dxd, double* dmu,
+                  double* dlam, double* lam_out, const pbng_adjoint_opts* o, pbng_stats* st,
+                  hipStream_t s)
+{
+    using R4 = typename R4t<R>::T;
+    const int n = ws->n_inst;
+    const bool accel = o->accel == PBNG_ACCEL_CHEBYSHEV;
+    const int lanes = pick_lanes(ws, o->lanes);
+    if (!ws->L.p) ws->L.alloc(ws->nv * ws->r4());
+    if (!ws->B.p) ws->B.alloc(ws->nv * ws->r4());
+    if (accel) {
+        if (!ws->LP.p) ws->LP.alloc(ws->nv * ws->r4());
+        if (!ws->LN.p) ws->LN.alloc(ws->nv * ws->r4());
+    }
+    hipchk(launch_load<R>(static_cast<const R*>(x_eq), ws->orig_of.as<int>(), nullptr, ws->Wres.as<R4>(), nullptr,
+                          nullptr, int(ws->nfree), int(ws->nv), s),
+           "load");
+    hipchk(launch_load_vec<R>(static_cast<const R*>(dLdx), ws->orig_of.as<int>(), ws->B.as<R4>(), int(ws->nfree),
+                              int(ws->nv), s),
+           "load");
+    hipchk(hipMemsetAsync(ws->L.p, 0, ws->nv * ws->r4(), s), "memset");
+    if (accel) {
+        hipchk(hipMemsetAsync(ws->LP.p, 0, ws->nv * ws->r4(), s), "memset");
+        hipchk(hipMemsetAsync(ws->LN.p, 0, ws->nv * ws->r4(), s), "memset");
+    }
+    adjoint_check<R>(ws, nullptr, nullptr, nullptr, s);
+    std::vector<double> b0(ws->hbuf, ws->hbuf + n), rr(b0);
+    std::vector<int> act(n, 1), sweeps(n, 0), conv(n, 0);
+    int n_active = 0;
+    for (int q = 0; q < n; ++q) {
+        if (!std::isfinite(b0[q])) fail(PBNG_ENAN, "instance %d: non-finite dL/dx", q);
+        if (b0[q] == 0.0) {
+            act[q] = 0;
+            conv[q] = 1;
+        }
+        n_active += act[q];
+    }
+    const double t0 = now_ms();
+    double omega_prev = 1.0;
+    for (int64_t sw = 0; sw < o->max_sweeps && n_active > 0; ++sw) {
+        double omega = 1.0;
+        if (accel) omega = chebyshev_next(sw, o->rho, omega_prev);
+        omega_prev = omega;
+        const AdjArgs<R> a = adj_args<R>(ws, omega, accel ? o->gamma : 1.0);
+        for (int c = 0; c < ws->ncol; ++c)
+            hipchk(launch_adjoint_phase<R>(a, lanes, accel, ws->any_wc, ws->col_ptr[c], ws->col_ptr[c + 1], s),
+                   "adjoint launch");
+        if (accel) std::swap(ws->L.p, ws->LN.p);
+        for (int q = 0; q < n; ++q) sweeps[q] += act[q];
+        if ((sw + 1) % o->check_every == 0 || sw + 1 == o->max_sweeps) {
+            adjoint_check<R>(ws, nullptr, nullptr, nullptr, s);
+            n_active = 0;
+            for (int q = 0; q < n; ++q) {
+                if (!act[q]) continue;
+                rr[q] = ws->hbuf[q];
+                if (!std::isfinite(rr[q])) fail(PBNG_ENAN, "adjoint iterate became non-finite");
+                if (o->rel_tol > 0 && rr[q] <= o->rel_tol * b0[q]) {
+                    conv[q] = 1;
+                    act[q] = 0;
+                }
+                n_active += act[q];
+            }
+        }
+    }
+    // final assembly with the gradients
+    adjoint_check<R>(ws, dmu, dlam, dxd, s);
+    for (int q = 0; q < n; ++q) rr[q] = ws->hbuf[q];
+    if (lam_out)
+        hipchk(launch_store64<R>(ws->L.as<R4>(), ws->orig_of.as<int>(), lam_out, int(ws->nv), s), "store");
+    hipchk(hipStreamSynchronize(s), "sync");
+    const double t_all = now_ms() - t0;
+    bool all = true;
+    for (int q = 0; q < n; ++q) {
+        conv[q] = conv[q] || (o->rel_tol > 0 && rr[q] <= o->rel_tol * b0[q]) || b0[q] == 0.0;
+        all = all && conv[q];
+        if (st) {
+            st[q] = pbng_stats{};
+            st[q].sweeps = sweeps[q];
+            st[q].converged = conv[q];
+            st[q].n_colors = ws->ncol_inst[q];
+            st[q].residual0 = b0[q];
+            st[q].residual = rr[q];
+            st[q].rel_residual = b0[q] > 0 ? rr[q] / b0[q] : 0.0;
+            st[q].time_ms = t_all;
+            st[q].time_to_tol_ms = -1.0;
+            st[q].vertex_updates = double(sweeps[q]) * double(ws->nfree_inst[q]);
+        }
+    }
+    return all ? PBNG_OK : PBNG_NOT_CONVERGED;
+}
+
+void check_ws(const pbng_workspace* ws)
+{
+    if (!ws) fail(PBNG_EINVAL, "workspace is null");
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int32_t pbng_version(void) { return PBNG_ABI_VERSION; }
+
+const char* pbng_last_error(void) { return g_err.c_str(); }
+
+int32_t pbng_lame(int64_t n, const double* E, const double* nu, double* mu_out, double* lambda_out)
+{
+    return guard([&] {
+        if (n < 0 || (n > 0 && (!E || !nu || !mu_out || !lambda_out))) fail(PBNG_EINVAL, "null argument");
+        for (int64_t i = 0; i < n; ++i) {
+            if (!(E[i] > 0) || !(nu[i] > -1.0 && nu[i] < 0.5)) fail(PBNG_EINVAL, "need E > 0 and -1 < nu < 0.5");
+            mu_out[i] = E[i] / (2.0 * (1.0 + nu[i]));
+            lambda_out[i] = E[i] * nu[i] / ((1.0 + nu[i]) * (1.0 - 2.0 * nu[i]));
+        }
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_default_solve_opts(pbng_solve_opts* o)
+{
+    return guard([&] {
+        if (!o) fail(PBNG_EINVAL, "null options");
+        *o = pbng_solve_opts{};
+        o->max_sweeps = 1000;
+        o->rel_tol = 1e-5;
+        o->check_every = 10;
+        o->accel = PBNG_ACCEL_NONE;
+        o->rho = 0.95;
+        o->gamma = 1.7;
+        o->omega = 1.7;
+        o->safeguard = PBNG_SAFEGUARD_BACKTRACK;
+        o->max_halvings = 8;
+        o->lanes = 0;
+        o->sweeps_per_graph = 0;
+        o->resume = 0;
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_default_adjoint_opts(pbng_adjoint_opts* o)
+{
+    return guard([&] {
+        if (!o) fail(PBNG_EINVAL, "null options");
+        *o = pbng_adjoint_opts{};
+        o->max_sweeps = 5000;
+        o->rel_tol = 1e-6;
+        o->check_every = 20;
+        o->accel = PBNG_ACCEL_CHEBYSHEV;
+        o->rho = 0.95;
+        o->gamma = 1.0;
+        o->lanes = 0;
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_color(const pbng_problem* p, int32_t* colors_out, int32_t* n_colors_out)
+{
+    return guard([&] {
+        if (!p || !colors_out || !n_colors_out) fail(PBNG_EINVAL, "null argument");
+        if (p->n_verts <= 0 || p->n_tets < 0) fail(PBNG_EINVAL, "bad sizes");
+        if (p->n_tets > 0 && !p->tets) fail(PBNG_EINVAL, "tets is null");
+        for (int64_t e = 0; e < 4ll * p->n_tets; ++e)
+            if (p->tets[e] < 0 || p->tets[e] >= p->n_verts) fail(PBNG_EMESH, "tet vertex out of range");
+        for (int k = 0; k < p->n_dirichlet; ++k)
+            if (p->dirichlet_idx[k] < 0 || p->dirichlet_idx[k] >= p->n_verts) fail(PBNG_EINVAL, "Dirichlet index out of range");
+        if (p->n_wc > 0) {
+            if (!p->wc_ptr || !p->wc_vert) fail(PBNG_EINVAL, "weak-constraint arrays are null");
+            for (int k = 0; k < p->wc_ptr[p->n_wc]; ++k)
+                if (p->wc_vert[k] < 0 || p->wc_vert[k] >= p->n_verts) fail(PBNG_EMESH, "weak-constraint vertex out of range");
+        }
+        *n_colors_out = color_instance(p, colors_out);
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_workspace_create(const pbng_problem* p, int32_t n_problems, const int32_t* colors, int32_t real,
+                              pbng_workspace** ws_out)
+{
+    return guard([&] {
+        if (!p || !ws_out || n_problems <= 0) fail(PBNG_EINVAL, "null argument or n_problems <= 0");
+        if (real != PBNG_F32 && real != PBNG_F64) fail(PBNG_EINVAL, "real must be PBNG_F32 or PBNG_F64");
+        *ws_out = nullptr;
+        pbng_workspace* ws = new pbng_workspace;
+        ws->real = real;
+        try {
+            build_workspace(ws, p, n_problems, colors);
+        } catch (...) {
+            delete ws;
+            throw;
+        }
+        *ws_out = ws;
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_workspace_destroy(pbng_workspace* ws)
+{
+    return guard([&] {
+        delete ws;
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_workspace_info(const pbng_workspace* ws, int64_t* n_verts, int64_t* n_tets, int64_t* n_free,
+                            int32_t* n_colors, int64_t* n_visits, int32_t* n_instances)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (n_verts) *n_verts = ws->nv;
+        if (n_tets) *n_tets = ws->nt;
+        if (n_free) *n_free = ws->nfree;
+        if (n_colors) *n_colors = ws->ncol;
+        if (n_visits) *n_visits = ws->nvis;
+        if (n_instances) *n_instances = ws->n_inst;
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_workspace_set_materials(pbng_workspace* ws, const double* mu_dev, const double* lambda_dev,
+                                     void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (!mu_dev || !lambda_dev) fail(PBNG_EINVAL, "null material arrays");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        if (ws->real == PBNG_F64)
+            hipchk(launch_set_materials<double>(mu_dev, lambda_dev, ws->geo.as<TetGeo>(), int(ws->nt), ws->rv.as<int>(),
+                                                int(ws->nvis), ws->vmu.as<double>(), ws->vlam.as<double>(), s),
+                   "set materials");
+        else
+            hipchk(launch_set_materials<float>(mu_dev, lambda_dev, ws->geo.as<TetGeo>(), int(ws->nt), ws->rv.as<int>(),
+                                               int(ws->nvis), ws->vmu.as<float>(), ws->vlam.as<float>(), s),
+                   "set materials");
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_workspace_set_dirichlet(pbng_workspace* ws, const double* xd_dev, void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (ws->nd > 0 && !xd_dev) fail(PBNG_EINVAL, "null Dirichlet array");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        if (ws->real == PBNG_F64)
+            hipchk(launch_set_dirichlet<double>(xd_dev, ws->dir_internal.as<int>(), ws->nd, int(ws->nfree),
+                                                ws->xd_int.as<double4>(), s),
+                   "set dirichlet");
+        else
+            hipchk(launch_set_dirichlet<float>(xd_dev, ws->dir_internal.as<int>(), ws->nd, int(ws->nfree),
+                                               ws->xd_int.as<float4>(), s),
+                   "set dirichlet");
+        ws->ring_valid = false;
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_solve(pbng_workspace* ws, void* x_inout, const pbng_solve_opts* o, pbng_stats* stats, void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (!x_inout) fail(PBNG_EINVAL, "x_inout is null");
+        check_solve_opts(o);
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        return ws->real == PBNG_F64 ? solve_t<double>(ws, x_inout, o, stats, s)
+                                    : solve_t<float>(ws, x_inout, o, stats, s);
+    });
+}
+
+int32_t pbng_residual(pbng_workspace* ws, const void* x, double* res_norm, double* energy, double* r_out,
+                      void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (!x) fail(PBNG_EINVAL, "x is null");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        if (ws->real == PBNG_F64) {
+            hipchk(launch_load<double>(static_cast<const double*>(x), ws->orig_of.as<int>(), nullptr,
+                                       ws->Wres.as<double4>(), nullptr, nullptr, int(ws->nfree), int(ws->nv), s),
+                   "load");
+            residual_internal<double>(ws, ws->Wres.p, r_out, s);
+        } else {
+            hipchk(launch_load<float>(static_cast<const float*>(x), ws->orig_of.as<int>(), nullptr,
+                                      ws->Wres.as<float4>(), nullptr, nullptr, int(ws->nfree), int(ws->nv), s),
+                   "load");
+            residual_internal<float>(ws, ws->Wres.p, r_out, s);
+        }
+        for (int q = 0; q < ws->n_inst; ++q) {
+            if (res_norm) res_norm[q] = ws->hbuf[q];
+            if (energy) energy[q] = ws->hbuf[ws->n_inst + q];
+        }
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_adjoint(pbng_workspace* ws, const void* x_eq, const void* dL_dx, double* dL_dxD, double* dL_dmu,
+                     double* dL_dlambda, double* lam_out, const pbng_adjoint_opts* o, pbng_stats* stats,
+                     void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (!x_eq || !dL_dx || !o) fail(PBNG_EINVAL, "null argument");
+        if (ws->model != PBNG_NEOHOOKEAN) fail(PBNG_EUNSUPPORTED, "the adjoint supports the Neo-Hookean model only");
+        if (o->max_sweeps < 0 || o->check_every < 1) fail(PBNG_EINVAL, "bad adjoint sweep counts");
+        if (o->accel != PBNG_ACCEL_NONE && o->accel != PBNG_ACCEL_CHEBYSHEV)
+            fail(PBNG_EINVAL, "adjoint acceleration must be none or Chebyshev");
+        if (o->accel == PBNG_ACCEL_CHEBYSHEV && !(o->rho > 0 && o->rho < 1 && o->gamma > 0))
+            fail(PBNG_EINVAL, "Chebyshev needs 0 < rho < 1 and gamma > 0");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        return ws->real == PBNG_F64
+                   ? adjoint_t<double>(ws, x_eq, dL_dx, dL_dxD, dL_dmu, dL_dlambda, lam_out, o, stats, s)
+                   : adjoint_t<float>(ws, x_eq, dL_dx, dL_dxD, dL_dmu, dL_dlambda, lam_out, o, stats, s);
+    });
+}
+
+int32_t pbng_load(pbng_workspace* ws, const void* x, void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (!x) fail(PBNG_EINVAL, "x is null");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        if (!ws->P.p) ws->P.alloc(ws->nv * ws->r4());
+        if (!ws->N.p) ws->N.alloc(ws->nv * ws->r4());
+        if (ws->real == PBNG_F64)
+            hipchk(launch_load<double>(static_cast<const double*>(x), ws->orig_of.as<int>(), ws->xd_int.as<double4>(),
+                                       ws->W.as<double4>(), ws->P.as<double4>(), ws->N.as<double4>(),
+                                       int(ws->nfree), int(ws->nv), s),
+                   "load");
+        else
+            hipchk(launch_load<float>(static_cast<const float*>(x), ws->orig_of.as<int>(), ws->xd_int.as<float4>(),
+                                      ws->W.as<float4>(), ws->P.as<float4>(), ws->N.as<float4>(), int(ws->nfree),
+                                      int(ws->nv), s),
+                   "load");
+        hipchk(hipMemsetAsync(ws->rejected.p, 0, ws->n_inst * sizeof(int), s), "memset");
+        for (int q = 0; q < ws->n_inst; ++q) ws->hact[q] = 1;
+        hipchk(hipMemcpyAsync(ws->active.p, ws->hact, ws->n_inst * sizeof(int), hipMemcpyHostToDevice, s), "h2d");
+        hipchk(hipStreamSynchronize(s), "sync");
+        ws->sweep_l = 0;
+        ws->omega_l = 1.0;
+        ws->ring_valid = true;
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_store(pbng_workspace* ws, void* x, void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (!x) fail(PBNG_EINVAL, "x is null");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        if (ws->real == PBNG_F64)
+            hipchk(launch_store<double>(ws->W.as<double4>(), ws->orig_of.as<int>(), static_cast<double*>(x),
+                                        int(ws->nv), s),
+                   "store");
+        else
+            hipchk(launch_store<float>(ws->W.as<float4>(), ws->orig_of.as<int>(), static_cast<float*>(x), int(ws->nv),
+                                       s),
+                   "store");
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_sweeps(pbng_workspace* ws, int32_t n_sweeps, const pbng_solve_opts* o, void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        check_solve_opts(o);
+        if (!ws->ring_valid) fail(PBNG_EINVAL, "call pbng_load first");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        const int lanes = pick_lanes(ws, o->lanes);
+        for (int k = 0; k < n_sweeps; ++k) {
+            double omega = 1.0, gamma = 1.0;
+            if (o->accel == PBNG_ACCEL_CHEBYSHEV) {
+                omega = chebyshev_next(ws->sweep_l, o->rho, ws->omega_l);
+                gamma = o->gamma;
+            } else if (o->accel == PBNG_ACCEL_SOR) {
+                omega = o->omega;
+            }
+            if (ws->real == PBNG_F64) launch_sweep<double>(ws, o, lanes, omega, gamma, s);
+            else launch_sweep<float>(ws, o, lanes, omega, gamma, s);
+            ws->omega_l = omega;
+            ws->sweep_l++;
+        }
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_phase(pbng_workspace* ws, int32_t color, const pbng_solve_opts* o, void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        check_solve_opts(o);
+        if (!ws->ring_valid) fail(PBNG_EINVAL, "call pbng_load first");
+        if (color < 0 || color >= ws->ncol) fail(PBNG_EINVAL, "colour out of range");
+        if (o->accel != PBNG_ACCEL_NONE) fail(PBNG_EINVAL, "pbng_phase runs unaccelerated phases only");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        const int lanes = pick_lanes(ws, o->lanes);
+        const bool safe = o->safeguard == PBNG_SAFEGUARD_BACKTRACK;
+        if (ws->real == PBNG_F64)
+            hipchk(launch_phase<double>(sweep_args<double>(ws, 1.0, 1.0, o->max_halvings), ws->model, lanes, false,
+                                        safe, ws->any_wc, ws->col_ptr[color], ws->col_ptr[color + 1], s),
+                   "phase");
+        else
+            hipchk(launch_phase<float>(sweep_args<float>(ws, 1.0, 1.0, o->max_halvings), ws->model, lanes, false,
+                                       safe, ws->any_wc, ws->col_ptr[color], ws->col_ptr[color + 1], s),
+                   "phase");
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_phase_bytes(const pbng_workspace* ws, int32_t color, int64_t* bytes, int64_t* vertices,
+                         int64_t* visits)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (color < 0 || color >= ws->ncol) fail(PBNG_EINVAL, "colour out of range");
+        if (bytes) *bytes = ws->phase_bytes[color];
+        if (vertices) *vertices = ws->phase_verts[color];
+        if (visits) *visits = ws->phase_visits[color];
+        return PBNG_OK;
+    });
+}
+
+}  // extern "C"

@@ -1,0 +1,189 @@
+// Internal layout of a libpbng workspace and the kernel launchers.
+//
+// Vertex order on the device ("internal order"): all free vertices first,
+// grouped by colour; inside a colour by instance, then by decreasing
+// valence (number of incident tets), then by caller index.  Dirichlet
+// vertices follow.  Same-coloured vertices share no tet or weak constraint,
+// so the order inside a colour does not change any computed value.
+//
+// Per-visit records (one per (free vertex i, incident tet e) pair, CSR by
+// internal vertex through vptr) are structure-of-arrays so that a wave's
+// lanes read consecutive addresses:
+//   j1, j2, j3      internal indices of the other three vertices of e
+//   m[9]            rows dN_j1, dN_j2, dN_j3 of the rest-state shape-function
+//                   gradients (so F = sum (x_j - x_i) dN_j^T)
+//   vmu, vlam       V0_e mu_e and V0_e lambda_e
+// In float: 3*4 + 11*4 = 56 bytes per visit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pbng {
+
+template <class R>
+struct R4t;
+template <>
+struct R4t<float> {
+    using T = float4;
+};
+template <>
+struct R4t<double> {
+    using T = double4;
+};
+
+// Geometry of a tet for the FP64 passes: Dm^{-1} (row-major), V0, mu, lambda.
+struct TetGeo {
+    double dm[9];
+    double V0, mu, lam;
+};
+
+template <class R>
+struct SweepArgs {
+    using R4 = typename R4t<R>::T;
+    R4* W;                 // working iterate (Gauss-Seidel, in place)
+    R4* P;                 // x^{l-1}                (acceleration only)
+    R4* N;                 // x^{l+1} being blended  (acceleration only)
+    const int* vptr;       // [n_free + 1]
+    const int* j1;
+    const int* j2;
+    const int* j3;
+    const R* m;            // [9][n_visits]
+    const R* vmu;
+    const R* vlam;
+    int64_t nvis;
+    const R4* fext;        // [n_free] lumped external force
+    const int* vinst;      // [n_free] instance of each free vertex
+    const int* active;     // [n_inst] 1 while the instance iterates
+    const int* wvptr;      // [n_verts + 1] weak constraints per vertex
+    const int* wv_c;
+    const R* wv_s;         // w0 - w1 of this vertex in the constraint
+    const int* wc_ptr;     // [n_wc + 1]
+    const int* wc_vert;    // internal vertex indices
+    const R* wc_w;
+    const R* wc_K;         // [n_wc][6]
+    const int* plane_ptr;  // [n_inst + 1]
+    const R* planes;       // [n_planes][5]
+    int* rejected;         // [n_inst]
+    R omega, gamma;
+    int max_halvings;
+};
+
+// FP64 residual / energy / adjoint assembly arguments.
+template <class R>
+struct ResArgs {
+    using R4 = typename R4t<R>::T;
+    const R4* X;            // positions, internal order
+    const int4* tet;        // [n_tets] internal vertex indices
+    const TetGeo* geo;      // [n_tets]
+    double* vp;             // [n_tets][9] scratch: V0 P(F) or V0 dP[Lam]
+    double* ebuf;           // energy summands
+    const int* tet_eidx;    // [n_tets] slot of each tet energy in ebuf
+    const int* vorder;      // [n_verts] internal vertex at instance-major position k
+    const int* vert_eidx;   // [n_verts] (by position k) slot in ebuf
+    const int* rvptr;       // [n_verts + 1] visits of every vertex (internal order)
+    const int* rv;          // tet * 4 + slot
+    const double* fext64;   // [n_verts][3] internal order
+    const int* vinst_all;   // [n_verts] internal order
+    const int* wvptr;
+    const int* wv_c;
+    const double* wv_s64;
+    const int* wc_ptr;
+    const int* wc_vert;
+    const double* wc_w64;
+    const double* wc_K64;
+    const int* wc_eidx;
+    const int* plane_ptr;
+    const double* planes64;
+    const int* orig_of;     // [n_verts] caller index of each internal vertex
+    int n_free;
+    int n_verts;
+    int n_tets;
+    int n_wc;
+    int model;
+};
+
+// Deterministic segmented sums: chunk c covers [cbeg[c], cend[c]) of the
+// value array; instance q owns chunks [qptr[q], qptr[q+1]).
+struct SegPlan {
+    int64_t* cbeg = nullptr;
+    int64_t* cend = nullptr;
+    int* qptr = nullptr;
+    double* partial = nullptr;
+    int n_chunks = 0;
+};
+
+// ---- launchers (pbng_kernels.hip) -------------------------------------
+// launch_load: free vertices from the caller array, Dirichlet vertices from
+// xd_int (or, when xd_int is null, also from the caller array).
+template <class R>
+hipError_t launch_phase(const SweepArgs<R>& a, int model, int lanes, bool accel, bool safe,
+                        bool wc, int vbeg, int vend, hipStream_t s);
+template <class R>
+hipError_t launch_load(const R* x_user, const int* orig_of, const typename R4t<R>::T* xd_int,
+                       typename R4t<R>::T* d0, typename R4t<R>::T* d1, typename R4t<R>::T* d2,
+                       int n_free, int n_verts, hipStream_t s);
+template <class R>
+hipError_t launch_store(const typename R4t<R>::T* src, const int* orig_of, R* x_user, int n_verts,
+                        hipStream_t s);
+template <class R>
+hipError_t launch_residual(const ResArgs<R>& a, double* rsq, double* r_out, hipStream_t s);
+template <class R>
+hipError_t launch_adjoint_assembly(const ResArgs<R>& a, const typename R4t<R>::T* lam,
+                                   const typename R4t<R>::T* b, double* rsq, double* dmu,
+                                   double* dlam, double* dxd, const int* dir_pos,
+                                   hipStream_t s);
+hipError_t launch_segsum(const double* vals, const SegPlan& plan, int n_inst, double* out,
+                         hipStream_t s);
+template <class R>
+hipError_t launch_set_materials(const double* mu, const double* lam, TetGeo* geo, int n_tets,
+                                const int* rv, int n_vis_free, R* vmu, R* vlam, hipStream_t s);
+template <class R>
+hipError_t launch_set_dirichlet(const double* xd, const int* dir_internal, int nd, int n_free,
+                                typename R4t<R>::T* xd_int, hipStream_t s);
+template <class R>
+hipError_t launch_store64(const typename R4t<R>::T* src, const int* orig_of, double* x_user,
+                          int n_verts, hipStream_t s);
+template <class R>
+hipError_t launch_copy4(const typename R4t<R>::T* src, typename R4t<R>::T* dst, int n,
+                        hipStream_t s);
+template <class R>
+hipError_t launch_load_vec(const R* v_user, const int* orig_of, typename R4t<R>::T* dst,
+                           int n_free, int n_verts, hipStream_t s);
+
+// Adjoint block Gauss-Seidel phase: L holds lambda (internal order), B the
+// right-hand side dL/dx (internal order, free vertices), X the equilibrium.
+template <class R>
+struct AdjArgs {
+    using R4 = typename R4t<R>::T;
+    const R4* X;
+    R4* L;                 // working adjoint iterate
+    R4* P;                 // previous (acceleration)
+    R4* N;                 // next (acceleration)
+    const R4* B;
+    const int* vptr;
+    const int* j1;
+    const int* j2;
+    const int* j3;
+    const R* m;
+    const R* vmu;
+    const R* vlam;
+    int64_t nvis;
+    const int* vinst;
+    const int* wvptr;
+    const int* wv_c;
+    const R* wv_s;
+    const int* wc_ptr;
+    const int* wc_vert;
+    const R* wc_w;
+    const R* wc_K;
+    const int* plane_ptr;
+    const R* planes;
+    R omega, gamma;
+};
+template <class R>
+hipError_t launch_adjoint_phase(const AdjArgs<R>& a, int lanes, bool accel, bool wc, int vbeg,
+                                int vend, hipStream_t s);
+
+}  // namespace pbng

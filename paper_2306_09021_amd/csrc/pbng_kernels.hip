@@ -1,0 +1,988 @@
+// HIP kernels of libpbng for gfx950 (MI355X).
+//
+// Hot path: one launch per colour phase.  A group of LANES lanes of a
+// 64-wide wavefront owns one free vertex; lane l takes the vertex's visits
+// l, l + LANES, ...  Per visit it forms F from the three gathered
+// neighbour positions, the stress contribution V0 P(F) dN_i to the local
+// gradient and the modified-Hessian contribution
+//   V0 (2 mu |dN_i|^2 I + lambda (cof F dN_i)(cof F dN_i)^T)
+// (Eq. mod_hess), then the group sums its partial results with a butterfly
+// of cross-lane shuffles (every lane ends with the same bits), solves the
+// SPD 3x3 system by Cholesky and takes the single modified-Newton step of
+// Eq. pbgn_dx.  All work is FP32 (or FP64) vector ALU work on gathered
+// data; there is no dense contraction to put on the matrix cores.
+#include "pbng_internal.hpp"
+#include "pbng_math.hpp"
+
+namespace pbng {
+
+constexpr int kNeo = 0;
+constexpr int kCor = 1;
+constexpr int kBlock = 256;
+
+template <int LANES, class T>
+__device__ __forceinline__ T lsum(T v)
+{
+#pragma unroll
+    for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LANES);
+    return v;
+}
+
+template <int LANES, class R>
+__device__ __forceinline__ void lsum3(V3<R>& v)
+{
+    v.x = lsum<LANES>(v.x);
+    v.y = lsum<LANES>(v.y);
+    v.z = lsum<LANES>(v.z);
+}
+
+template <int LANES, class R>
+__device__ __forceinline__ void lsum6(Sym<R>& s)
+{
+    s.xx = lsum<LANES>(s.xx);
+    s.xy = lsum<LANES>(s.xy);
+    s.xz = lsum<LANES>(s.xz);
+    s.yy = lsum<LANES>(s.yy);
+    s.yz = lsum<LANES>(s.yz);
+    s.zz = lsum<LANES>(s.zz);
+}
+
+template <class P4>
+__device__ __forceinline__ auto xyz(P4 p)
+{
+    using R = decltype(p.x);
+    return V3<R>{p.x, p.y, p.z};
+}
+
+template <class R>
+__device__ __forceinline__ typename R4t<R>::T pack4(V3<R> v)
+{
+    return typename R4t<R>::T{v.x, v.y, v.z, R(0)};
+}
+
+template <class R>
+__device__ __forceinline__ Sym<R> sym_zero()
+{
+    return Sym<R>{R(0), R(0), R(0), R(0), R(0), R(0)};
+}
+
+template <class R>
+__device__ __forceinline__ void sym_acc(Sym<R>& A, const Sym<R>& B)
+{
+    A.xx += B.xx; A.xy += B.xy; A.xz += B.xz; A.yy += B.yy; A.yz += B.yz; A.zz += B.zz;
+}
+
+template <class R>
+__device__ __forceinline__ void sym_add_scaled(Sym<R>& A, R w, const R* K)
+{
+    A.xx += w * K[0]; A.xy += w * K[1]; A.xz += w * K[2];
+    A.yy += w * K[3]; A.yz += w * K[4]; A.zz += w * K[5];
+}
+
+template <class R>
+__device__ __forceinline__ V3<R> symK_mul(const R* K, V3<R> v)
+{
+    return {K[0] * v.x + K[1] * v.y + K[2] * v.z, K[1] * v.x + K[3] * v.y + K[4] * v.z,
+            K[2] * v.x + K[4] * v.y + K[5] * v.z};
+}
+
+// Visit k of vertex at xi: deformation gradient, own gradient a = dN_i,
+// V0 mu, V0 lambda.
+template <class R, class A>
+__device__ __forceinline__ void load_visit(const A& a, int k, V3<R> xi, Cols<R>& F, V3<R>& av,
+                                           R& vm, R& vl)
+{
+    const int i1 = a.j1[k], i2 = a.j2[k], i3 = a.j3[k];
+    R m[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) m[q] = a.m[q * a.nvis + k];
+    vm = a.vmu[k];
+    vl = a.vlam[k];
+    const V3<R> e1 = xyz(a.W[i1]) - xi;
+    const V3<R> e2 = xyz(a.W[i2]) - xi;
+    const V3<R> e3 = xyz(a.W[i3]) - xi;
+    F = edge_F(e1, e2, e3, m);
+    av = mk(-(m[0] + m[3] + m[6]), -(m[1] + m[4] + m[7]), -(m[2] + m[5] + m[8]));
+}
+
+// Corotated energy density times V0 from the signed singular values:
+// mu |F - R|^2 = mu sum (sigma_i - 1)^2.
+template <class R>
+__device__ __forceinline__ R corot_energy(const Polar<R>& P, R J, R vm, R vl)
+{
+    const V3<R> s = P.sigma;
+    const R d0 = s.x - R(1), d1 = s.y - R(1), d2 = s.z - R(1);
+    return vm * (d0 * d0 + d1 * d1 + d2 * d2) + R(0.5) * vl * (J - R(1)) * (J - R(1));
+}
+
+template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool WC>
+__global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int vend)
+{
+    using R4 = typename R4t<R>::T;
+    const int gid = blockIdx.x * kBlock + threadIdx.x;
+    const int v = vbeg + gid / LANES;
+    const int lane = gid & (LANES - 1);
+    if (v >= vend) return;
+    const int inst = a.vinst[v];
+    const R4 xw = a.W[v];
+    if (!a.active[inst]) {
+        if (ACCEL && lane == 0) a.N[v] = xw;
+        return;
+    }
+    const V3<R> xi = xyz(xw);
+
+    V3<R> g = mk<R>(0, 0, 0);   // elastic + weak-constraint gradient
+    R S = R(0);                 // sum V0 mu |dN_i|^2
+    Sym<R> Aw = sym_zero<R>();  // sum V0 lambda c c^T + sum s^2 K
+    Sym<R> Cm = sym_zero<R>();  // Neo-Hookean safeguard: sum V0 mu c c^T
+    V3<R> gw = mk<R>(0, 0, 0);  // corotated safeguard: weak-constraint part of g
+    Sym<R> Kw = sym_zero<R>();  // corotated safeguard: sum s^2 K
+    R E0 = R(0), E0a = R(0);    // corotated safeguard: elastic energy, sum |.|
+
+    const int kb = a.vptr[v], ke = a.vptr[v + 1];
+    for (int k = kb + lane; k < ke; k += LANES) {
+        Cols<R> F;
+        V3<R> av;
+        R vm, vl;
+        load_visit(a, k, xi, F, av, vm, vl);
+        const Cols<R> C = cofactor(F);
+        const R J = dot(F.c0, C.c0);
+        const V3<R> c = apply(C, av);   // cof(F) dN_i
+        const V3<R> p = apply(F, av);   // F dN_i
+        S += vm * dot(av, av);
+        sym_add_outer(Aw, vl, c);
+        if (MODEL == kNeo) {
+            // V0 P dN_i, P = mu F + (lhat (J - 1) - mu) cof F, lhat = mu + lambda
+            g = g + vm * p + ((vm + vl) * (J - R(1)) - vm) * c;
+            if (SAFE) sym_add_outer(Cm, vm, c);
+        } else {
+            // V0 P dN_i, P = 2 mu (F - R) + lambda (J - 1) cof F
+            Polar<R> pol;
+            polar(F, pol);
+            const V3<R> ra = polar_apply(pol, av);
+            g = g + (R(2) * vm) * (p - ra) + (vl * (J - R(1))) * c;
+            if (SAFE) {
+                const R e = corot_energy(pol, J, vm, vl);
+                E0 += e;
+                E0a += abs_(e);
+            }
+        }
+    }
+    if (WC) {
+        for (int k = a.wvptr[v] + lane; k < a.wvptr[v + 1]; k += LANES) {
+            const int cc = a.wv_c[k];
+            const R s = a.wv_s[k];
+            V3<R> Cc = mk<R>(0, 0, 0);
+            for (int j = a.wc_ptr[cc]; j < a.wc_ptr[cc + 1]; ++j)
+                Cc = Cc + a.wc_w[j] * xyz(a.W[a.wc_vert[j]]);
+            const R* K = a.wc_K + 6 * cc;
+            const V3<R> gk = s * symK_mul(K, Cc);
+            g = g + gk;
+            sym_add_scaled(Aw, s * s, K);
+            if (SAFE && MODEL == kCor) {
+                gw = gw + gk;
+                sym_add_scaled(Kw, s * s, K);
+            }
+        }
+    }
+    if (LANES > 1) {
+        lsum3<LANES>(g);
+        S = lsum<LANES>(S);
+        lsum6<LANES>(Aw);
+        if (SAFE && MODEL == kNeo) lsum6<LANES>(Cm);
+        if (SAFE && MODEL == kCor) {
+            E0 = lsum<LANES>(E0);
+            E0a = lsum<LANES>(E0a);
+            if (WC) {
+                lsum3<LANES>(gw);
+                lsum6<LANES>(Kw);
+            }
+        }
+    }
+    const V3<R> f = xyz(a.fext[v]);
+    const V3<R> gt = g - f;
+    Sym<R> A = Aw;
+    A.xx += R(2) * S;
+    A.yy += R(2) * S;
+    A.zz += R(2) * S;
+    V3<R> gtot = gt;
+    int pb = 0, pe = 0;
+    if (WC) {
+        pb = a.plane_ptr[inst];
+        pe = a.plane_ptr[inst + 1];
+        for (int q = pb; q < pe; ++q) {
+            const R* pl = a.planes + 5 * q;
+            const V3<R> n = mk(pl[0], pl[1], pl[2]);
+            const R phi = dot(n, xi) - pl[3];
+            if (phi < R(0)) {
+                gtot = gtot + (pl[4] * phi) * n;
+                sym_add_outer(A, pl[4], n);
+            }
+        }
+    }
+    V3<R> d;
+    const bool ok = chol_solve(A, R(-1) * gtot, d);
+    bool reject = !ok;
+    R alpha = R(1);
+    if (SAFE && ok) {
+        const R u = sizeof(R) == 8 ? R(1.1102230246251565e-16) : R(5.9604644775390625e-08);
+        R lin, quad;
+        if (MODEL == kNeo) {
+            // Along x_i + alpha d the Neo-Hookean energy of the incident tets
+            // is exactly quadratic: |F|^2 is quadratic and det F affine in x_i
+            // (a rank-one update), with Hessian sum V0 (mu |dN_i|^2 I + lhat
+            // c c^T); weak constraints are quadratic with Hessian s^2 K.
+            Sym<R> H = Aw;
+            sym_acc(H, Cm);
+            H.xx += S;
+            H.yy += S;
+            H.zz += S;
+            lin = dot(gt, d);
+            quad = dot(d, sym_mul(H, d));
+        } else {
+            lin = dot(gw - f, d);
+            quad = dot(d, sym_mul(Kw, d));
+        }
+        int h = 0;
+        for (;;) {
+            R dE = alpha * lin + R(0.5) * alpha * alpha * quad;
+            R ab = abs_(alpha * lin) + abs_(R(0.5) * alpha * alpha * quad);
+            if (WC) {
+                for (int q = pb; q < pe; ++q) {
+                    const R* pl = a.planes + 5 * q;
+                    const V3<R> n = mk(pl[0], pl[1], pl[2]);
+                    const R phi0 = dot(n, xi) - pl[3];
+                    const R phi1 = phi0 + alpha * dot(n, d);
+                    const R e0 = phi0 < R(0) ? R(0.5) * pl[4] * phi0 * phi0 : R(0);
+                    const R e1 = phi1 < R(0) ? R(0.5) * pl[4] * phi1 * phi1 : R(0);
+                    dE += e1 - e0;
+                    ab += e0 + e1;
+                }
+            }
+            if (MODEL == kCor) {
+                R E1 = R(0), E1a = R(0);
+                for (int k = kb + lane; k < ke; k += LANES) {
+                    Cols<R> F;
+                    V3<R> av;
+                    R vm, vl;
+                    load_visit(a, k, xi, F, av, vm, vl);
+                    const V3<R> ad = alpha * d;
+                    F.c0 = F.c0 + av.x * ad;
+                    F.c1 = F.c1 + av.y * ad;
+                    F.c2 = F.c2 + av.z * ad;
+                    const R J1 = dot(F.c0, cross(F.c1, F.c2));
+                    Polar<R> pol;
+                    polar(F, pol);
+                    const R e = corot_energy(pol, J1, vm, vl);
+                    E1 += e;
+                    E1a += abs_(e);
+                }
+                if (LANES > 1) {
+                    E1 = lsum<LANES>(E1);
+                    E1a = lsum<LANES>(E1a);
+                }
+                dE += E1 - E0;
+                ab += E0a + E1a;
+            }
+            if (dE <= R(8) * u * ab) break;
+            if (h >= a.max_halvings) {
+                reject = true;
+                break;
+            }
+            alpha *= R(0.5);
+            ++h;
+        }
+    }
+    const V3<R> xn = reject ? xi : xi + alpha * d;
+    if (lane == 0) {
+        if (reject) atomicAdd(a.rejected + inst, 1);
+        if (ACCEL) {
+            const V3<R> xp = xyz(a.P[v]);
+            const V3<R> b = a.omega * (a.gamma * (xn - xi) + xi - xp) + xp;
+            a.W[v] = pack4(xn);
+            a.P[v] = xw;
+            a.N[v] = pack4(b);
+        } else {
+            a.W[v] = pack4(xn);
+        }
+    }
+}
+
+template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool WC>
+static hipError_t launch_phase_t(const SweepArgs<R>& a, int vbeg, int vend, hipStream_t s)
+{
+    const int64_t threads = int64_t(vend - vbeg) * LANES;
+    if (threads <= 0) return hipSuccess;
+    const int blocks = int((threads + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_phase<R, MODEL, LANES, ACCEL, SAFE, WC>), dim3(blocks), dim3(kBlock), 0,
+                       s, a, vbeg, vend);
+    return hipGetLastError();
+}
+
+template <class R, int MODEL, int LANES>
+static hipError_t dispatch_flags(const SweepArgs<R>& a, bool accel, bool safe, bool wc, int vb,
+                                 int ve, hipStream_t s)
+{
+    const int code = (accel ? 4 : 0) | (safe ? 2 : 0) | (wc ? 1 : 0);
+    switch (code) {
+    case 0: return launch_phase_t<R, MODEL, LANES, false, false, false>(a, vb, ve, s);
+    case 1: return launch_phase_t<R, MODEL, LANES, false, false, true>(a, vb, ve, s);
+    case 2: return launch_phase_t<R, MODEL, LANES, false, true, false>(a, vb, ve, s);
+    case 3: return launch_phase_t<R, MODEL, LANES, false, true, true>(a, vb, ve, s);
+    case 4: return launch_phase_t<R, MODEL, LANES, true, false, false>(a, vb, ve, s);
+    case 5: return launch_phase_t<R, MODEL, LANES, true, false, true>(a, vb, ve, s);
+    case 6: return launch_phase_t<R, MODEL, LANES, true, true, false>(a, vb, ve, s);
+    default: return launch_phase_t<R, MODEL, LANES, true, true, true>(a, vb, ve, s);
+    }
+}
+
+template <class R, int MODEL>
+static hipError_t dispatch_lanes(const SweepArgs<R>& a, int lanes, bool accel, bool safe,
+                                 bool wc, int vb, int ve, hipStream_t s)
+{
+    switch (lanes) {
+    case 1: return dispatch_flags<R, MODEL, 1>(a, accel, safe, wc, vb, ve, s);
+    case 2: return dispatch_flags<R, MODEL, 2>(a, accel, safe, wc, vb, ve, s);
+    case 4: return dispatch_flags<R, MODEL, 4>(a, accel, safe, wc, vb, ve, s);
+    case 8: return dispatch_flags<R, MODEL, 8>(a, accel, safe, wc, vb, ve, s);
+    case 16: return dispatch_flags<R, MODEL, 16>(a, accel, safe, wc, vb, ve, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class R>
+hipError_t launch_phase(const SweepArgs<R>& a, int model, int lanes, bool accel, bool safe,
+                        bool wc, int vbeg, int vend, hipStream_t s)
+{
+    if (model == kNeo) return dispatch_lanes<R, kNeo>(a, lanes, accel, safe, wc, vbeg, vend, s);
+    return dispatch_lanes<R, kCor>(a, lanes, accel, safe, wc, vbeg, vend, s);
+}
+
+template hipError_t launch_phase<float>(const SweepArgs<float>&, int, int, bool, bool, bool, int,
+                                        int, hipStream_t);
+template hipError_t launch_phase<double>(const SweepArgs<double>&, int, int, bool, bool, bool,
+                                         int, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Adjoint: block Gauss-Seidel on the true Hessian H lam = b (Neo-Hookean).
+// (H lam)_i = sum_e V0 dP_e[Lam_e] dN_i + weak + active planes with
+// Lam_e = sum_j lam_j dN_j^T and, for the Neo-Hookean P = mu F + (lhat (J-1)
+// - mu) cof F,
+//   dP[L] = mu L + lhat (cof F : L) cof F + (lhat (J-1) - mu) dcof[L],
+//   dcof[L][:,k] = L[:,k+1] x F[:,k+2] + F[:,k+1] x L[:,k+2].
+// The diagonal block is H_ii = sum_e V0 (mu |dN_i|^2 I + lhat c c^T) + weak
+// + planes, c = cof F dN_i (along x_i alone the Neo-Hookean energy is
+// exactly quadratic).  Each update: lam_i += H_ii^{-1} (b_i - (H lam)_i).
+// ---------------------------------------------------------------------------
+template <class R, int LANES, bool ACCEL, bool WC>
+__global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R> a, int vbeg, int vend)
+{
+    using R4 = typename R4t<R>::T;
+    const int gid = blockIdx.x * kBlock + threadIdx.x;
+    const int v = vbeg + gid / LANES;
+    const int lane = gid & (LANES - 1);
+    if (v >= vend) return;
+    const int inst = a.vinst[v];
+    const V3<R> xi = xyz(a.X[v]);
+    const R4 lw = a.L[v];
+    const V3<R> li = xyz(lw);
+    V3<R> r = mk<R>(0, 0, 0);
+    R S = R(0);
+    Sym<R> Hc = sym_zero<R>();
+    const int kb = a.vptr[v], ke = a.vptr[v + 1];
+    for (int k = kb + lane; k < ke; k += LANES) {
+        const int i1 = a.j1[k], i2 = a.j2[k], i3 = a.j3[k];
+        R m[9];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) m[q] = a.m[q * a.nvis + k];
+        const R vm = a.vmu[k], vl = a.vlam[k];
+        const Cols<R> F = edge_F(xyz(a.X[i1]) - xi, xyz(a.X[i2]) - xi, xyz(a.X[i3]) - xi, m);
+        const Cols<R> Lm = edge_F(xyz(a.L[i1]) - li, xyz(a.L[i2]) - li, xyz(a.L[i3]) - li, m);
+        const V3<R> av = mk(-(m[0] + m[3] + m[6]), -(m[1] + m[4] + m[7]), -(m[2] + m[5] + m[8]));
+        const Cols<R> C = cofactor(F);
+        const R J = dot(F.c0, C.c0);
+        const V3<R> c = apply(C, av);
+        const R lh = vm + vl;
+        const R qq = lh * (J - R(1)) - vm;
+        const R cofL = dot(C.c0, Lm.c0) + dot(C.c1, Lm.c1) + dot(C.c2, Lm.c2);
+        const V3<R> dc0 = cross(Lm.c1, F.c2) + cross(F.c1, Lm.c2);
+        const V3<R> dc1 = cross(Lm.c2, F.c0) + cross(F.c2, Lm.c0);
+        const V3<R> dc2 = cross(Lm.c0, F.c1) + cross(F.c0, Lm.c1);
+        const V3<R> dca = comb(dc0, av.x, dc1, av.y, dc2, av.z);
+        r = r + vm * apply(Lm, av) + (lh * cofL) * c + qq * dca;
+        S += vm * dot(av, av);
+        sym_add_outer(Hc, lh, c);
+    }
+    if (WC) {
+        for (int k = a.wvptr[v] + lane; k < a.wvptr[v + 1]; k += LANES) {
+            const int cc = a.wv_c[k];
+            const R s = a.wv_s[k];
+            V3<R> Cl = mk<R>(0, 0, 0);
+            for (int j = a.wc_ptr[cc]; j < a.wc_ptr[cc + 1]; ++j)
+                Cl = Cl + a.wc_w[j] * xyz(a.L[a.wc_vert[j]]);
+            const R* K = a.wc_K + 6 * cc;
+            r = r + s * symK_mul(K, Cl);
+            sym_add_scaled(Hc, s * s, K);
+        }
+    }
+    if (LANES > 1) {
+        lsum3<LANES>(r);
+        S = lsum<LANES>(S);
+        lsum6<LANES>(Hc);
+    }
+    Hc.xx += S;
+    Hc.yy += S;
+    Hc.zz += S;
+    if (WC) {
+        for (int q = a.plane_ptr[inst]; q < a.plane_ptr[inst + 1]; ++q) {
+            const R* pl = a.planes + 5 * q;
+            const V3<R> n = mk(pl[0], pl[1], pl[2]);
+            if (dot(n, xi) - pl[3] < R(0)) {
+                r = r + (pl[4] * dot(n, li)) * n;
+                sym_add_outer(Hc, pl[4], n);
+            }
+        }
+    }
+    const V3<R> rho = xyz(a.B[v]) - r;
+    V3<R> dl;
+    if (!chol_solve(Hc, rho, dl)) dl = mk<R>(0, 0, 0);
+    const V3<R> ln = li + dl;
+    if (lane == 0) {
+        if (ACCEL) {
+            const V3<R> lp = xyz(a.P[v]);
+            const V3<R> b = a.omega * (a.gamma * (ln - li) + li - lp) + lp;
+            a.L[v] = pack4(ln);
+            a.P[v] = lw;
+            a.N[v] = pack4(b);
+        } else {
+            a.L[v] = pack4(ln);
+        }
+    }
+}
+
+template <class R, int LANES, bool ACCEL, bool WC>
+static hipError_t launch_adj_t(const AdjArgs<R>& a, int vb, int ve, hipStream_t s)
+{
+    const int64_t threads = int64_t(ve - vb) * LANES;
+    if (threads <= 0) return hipSuccess;
+    const int blocks = int((threads + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL((k_adj_phase<R, LANES, ACCEL, WC>), dim3(blocks), dim3(kBlock), 0, s, a,
+                       vb, ve);
+    return hipGetLastError();
+}
+
+template <class R, int LANES>
+static hipError_t adj_flags(const AdjArgs<R>& a, bool accel, bool wc, int vb, int ve,
+                            hipStream_t s)
+{
+    if (accel) {
+        return wc ? launch_adj_t<R, LANES, true, true>(a, vb, ve, s)
+                  : launch_adj_t<R, LANES, true, false>(a, vb, ve, s);
+    }
+    return wc ? launch_adj_t<R, LANES, false, true>(a, vb, ve, s)
+              : launch_adj_t<R, LANES, false, false>(a, vb, ve, s);
+}
+
+template <class R>
+hipError_t launch_adjoint_phase(const AdjArgs<R>& a, int lanes, bool accel, bool wc, int vbeg,
+                                int vend, hipStream_t s)
+{
+    switch (lanes) {
+    case 1: return adj_flags<R, 1>(a, accel, wc, vbeg, vend, s);
+    case 2: return adj_flags<R, 2>(a, accel, wc, vbeg, vend, s);
+    case 4: return adj_flags<R, 4>(a, accel, wc, vbeg, vend, s);
+    case 8: return adj_flags<R, 8>(a, accel, wc, vbeg, vend, s);
+    case 16: return adj_flags<R, 16>(a, accel, wc, vbeg, vend, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+template hipError_t launch_adjoint_phase<float>(const AdjArgs<float>&, int, bool, bool, int, int,
+                                                hipStream_t);
+template hipError_t launch_adjoint_phase<double>(const AdjArgs<double>&, int, bool, bool, int,
+                                                 int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// FP64 passes: residual r = f + fhat and energy (Eq. fem_qs, pe_hat), and
+// the adjoint assembly.  Tet-centric stress into a per-tet buffer, then a
+// vertex-centric gather in a fixed order: deterministic, no atomics.
+// ---------------------------------------------------------------------------
+template <class R4>
+__device__ __forceinline__ V3<double> x64(R4 p)
+{
+    return mk<double>(double(p.x), double(p.y), double(p.z));
+}
+
+__device__ __forceinline__ V3<double> grad_of_slot(const TetGeo& G, int slot)
+{
+    if (slot == 0)
+        return mk(-(G.dm[0] + G.dm[3] + G.dm[6]), -(G.dm[1] + G.dm[4] + G.dm[7]),
+                  -(G.dm[2] + G.dm[5] + G.dm[8]));
+    const double* r = G.dm + 3 * (slot - 1);
+    return mk(r[0], r[1], r[2]);
+}
+
+template <class R>
+__device__ __forceinline__ Cols<double> tet_F(const ResArgs<R>& a, int4 t, const TetGeo& G)
+{
+    const V3<double> x0 = x64(a.X[t.x]);
+    return edge_F(x64(a.X[t.y]) - x0, x64(a.X[t.z]) - x0, x64(a.X[t.w]) - x0, G.dm);
+}
+
+template <class R, int MODEL>
+__global__ __launch_bounds__(kBlock) void k_tet_stress(ResArgs<R> a)
+{
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= a.n_tets) return;
+    const int4 t = a.tet[e];
+    const TetGeo G = a.geo[e];
+    const Cols<double> F = tet_F(a, t, G);
+    const Cols<double> C = cofactor(F);
+    const double J = dot(F.c0, C.c0);
+    Cols<double> P;
+    double psi;
+    if (MODEL == kNeo) {
+        const double lh = G.mu + G.lam;
+        const double q = J - 1.0 - G.mu / lh;
+        P.c0 = G.mu * F.c0 + (lh * q) * C.c0;
+        P.c1 = G.mu * F.c1 + (lh * q) * C.c1;
+        P.c2 = G.mu * F.c2 + (lh * q) * C.c2;
+        psi = 0.5 * G.mu * frob2(F) + 0.5 * lh * q * q;
+    } else {
+        Polar<double> pol;
+        polar(F, pol);
+        const Cols<double> Rm = polar_matrix(pol);
+        const double w = G.lam * (J - 1.0);
+        P.c0 = (2.0 * G.mu) * (F.c0 - Rm.c0) + w * C.c0;
+        P.c1 = (2.0 * G.mu) * (F.c1 - Rm.c1) + w * C.c1;
+        P.c2 = (2.0 * G.mu) * (F.c2 - Rm.c2) + w * C.c2;
+        psi = corot_energy(pol, J, G.mu, G.lam);
+    }
+    double* o = a.vp + 9 * int64_t(e);
+    o[0] = G.V0 * P.c0.x; o[1] = G.V0 * P.c0.y; o[2] = G.V0 * P.c0.z;
+    o[3] = G.V0 * P.c1.x; o[4] = G.V0 * P.c1.y; o[5] = G.V0 * P.c1.z;
+    o[6] = G.V0 * P.c2.x; o[7] = G.V0 * P.c2.y; o[8] = G.V0 * P.c2.z;
+    a.ebuf[a.tet_eidx[e]] = G.V0 * psi;
+}
+
+// sum over visits of (per-tet 3x3 in vp, by columns) times dN_slot
+template <class R>
+__device__ __forceinline__ V3<double> gather_vp(const ResArgs<R>& a, int v)
+{
+    V3<double> s = mk(0.0, 0.0, 0.0);
+    for (int j = a.rvptr[v]; j < a.rvptr[v + 1]; ++j) {
+        const int e = a.rv[j] >> 2, slot = a.rv[j] & 3;
+        const V3<double> g = grad_of_slot(a.geo[e], slot);
+        const double* o = a.vp + 9 * int64_t(e);
+        s = s + comb(mk(o[0], o[1], o[2]), g.x, mk(o[3], o[4], o[5]), g.y, mk(o[6], o[7], o[8]),
+                     g.z);
+    }
+    return s;
+}
+
+template <class R>
+__device__ __forceinline__ V3<double> weak_force(const ResArgs<R>& a, int v,
+                                                 const typename R4t<R>::T* Y)
+{
+    V3<double> s = mk(0.0, 0.0, 0.0);
+    for (int k = a.wvptr[v]; k < a.wvptr[v + 1]; ++k) {
+        const int c = a.wv_c[k];
+        V3<double> C = mk(0.0, 0.0, 0.0);
+        for (int j = a.wc_ptr[c]; j < a.wc_ptr[c + 1]; ++j)
+            C = C + a.wc_w64[j] * x64(Y[a.wc_vert[j]]);
+        s = s + a.wv_s64[k] * symK_mul(a.wc_K64 + 6 * c, C);
+    }
+    return s;
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_vertex_residual(ResArgs<R> a, double* rsq,
+                                                            double* r_out)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= a.n_verts) return;
+    const int v = a.vorder[k];
+    const V3<double> xi = x64(a.X[v]);
+    const V3<double> f = mk(a.fext64[3 * v], a.fext64[3 * v + 1], a.fext64[3 * v + 2]);
+    double ev = -dot(xi, f);
+    V3<double> gp = mk(0.0, 0.0, 0.0);
+    const int inst = a.vinst_all[v];
+    for (int q = a.plane_ptr[inst]; q < a.plane_ptr[inst + 1]; ++q) {
+        const double* pl = a.planes64 + 5 * q;
+        const V3<double> n = mk(pl[0], pl[1], pl[2]);
+        const double phi = dot(n, xi) - pl[3];
+        if (phi < 0.0) {
+            ev += 0.5 * pl[4] * phi * phi;
+            gp = gp + (pl[4] * phi) * n;
+        }
+    }
+    a.ebuf[a.vert_eidx[k]] = ev;
+    V3<double> r = mk(0.0, 0.0, 0.0);
+    if (v < a.n_free) {
+        r = f - gp - gather_vp(a, v);
+        if (a.n_wc > 0) r = r - weak_force(a, v, a.X);
+    }
+    rsq[k] = dot(r, r);
+    if (r_out) {
+        double* o = r_out + 3 * int64_t(a.orig_of[v]);
+        o[0] = r.x; o[1] = r.y; o[2] = r.z;
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_wc_energy(ResArgs<R> a)
+{
+    const int c = blockIdx.x * kBlock + threadIdx.x;
+    if (c >= a.n_wc) return;
+    V3<double> C = mk(0.0, 0.0, 0.0);
+    for (int j = a.wc_ptr[c]; j < a.wc_ptr[c + 1]; ++j)
+        C = C + a.wc_w64[j] * x64(a.X[a.wc_vert[j]]);
+    a.ebuf[a.wc_eidx[c]] = 0.5 * dot(C, symK_mul(a.wc_K64 + 6 * c, C));
+}
+
+static inline int nblk(int64_t n) { return int((n + kBlock - 1) / kBlock); }
+
+template <class R>
+hipError_t launch_residual(const ResArgs<R>& a, double* rsq, double* r_out, hipStream_t s)
+{
+    if (a.n_tets > 0) {
+        if (a.model == kNeo)
+            hipLaunchKernelGGL((k_tet_stress<R, kNeo>), dim3(nblk(a.n_tets)), dim3(kBlock), 0, s, a);
+        else
+            hipLaunchKernelGGL((k_tet_stress<R, kCor>), dim3(nblk(a.n_tets)), dim3(kBlock), 0, s, a);
+    }
+    if (a.n_wc > 0) hipLaunchKernelGGL((k_wc_energy<R>), dim3(nblk(a.n_wc)), dim3(kBlock), 0, s, a);
+    if (a.n_verts > 0)
+        hipLaunchKernelGGL((k_vertex_residual<R>), dim3(nblk(a.n_verts)), dim3(kBlock), 0, s, a,
+                           rsq, r_out);
+    return hipGetLastError();
+}
+template hipError_t launch_residual<float>(const ResArgs<float>&, double*, double*, hipStream_t);
+template hipError_t launch_residual<double>(const ResArgs<double>&, double*, double*, hipStream_t);
+
+// Adjoint assembly in FP64: per tet V0 dP[Lam] (into vp) and the parameter
+// gradients; per vertex (H lam)_i, the adjoint residual b - H lam on free
+// vertices and dL/dx_D = -(H lam)_k on Dirichlet vertices.
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_tet_adjoint(ResArgs<R> a,
+                                                        const typename R4t<R>::T* L,
+                                                        double* dmu, double* dlam)
+{
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= a.n_tets) return;
+    const int4 t = a.tet[e];
+    const TetGeo G = a.geo[e];
+    const Cols<double> F = tet_F(a, t, G);
+    const V3<double> l0 = x64(L[t.x]);
+    const Cols<double> Lm = edge_F(x64(L[t.y]) - l0, x64(L[t.z]) - l0, x64(L[t.w]) - l0, G.dm);
+    const Cols<double> C = cofactor(F);
+    const double J = dot(F.c0, C.c0);
+    const double lh = G.mu + G.lam;
+    const double qq = lh * (J - 1.0) - G.mu;
+    const double cofL = dot(C.c0, Lm.c0) + dot(C.c1, Lm.c1) + dot(C.c2, Lm.c2);
+    const double FL = dot(F.c0, Lm.c0) + dot(F.c1, Lm.c1) + dot(F.c2, Lm.c2);
+    Cols<double> dP;
+    dP.c0 = G.mu * Lm.c0 + (lh * cofL) * C.c0 + qq * (cross(Lm.c1, F.c2) + cross(F.c1, Lm.c2));
+    dP.c1 = G.mu * Lm.c1 + (lh * cofL) * C.c1 + qq * (cross(Lm.c2, F.c0) + cross(F.c2, Lm.c0));
+    dP.c2 = G.mu * Lm.c2 + (lh * cofL) * C.c2 + qq * (cross(Lm.c0, F.c1) + cross(F.c0, Lm.c1));
+    double* o = a.vp + 9 * int64_t(e);
+    o[0] = G.V0 * dP.c0.x; o[1] = G.V0 * dP.c0.y; o[2] = G.V0 * dP.c0.z;
+    o[3] = G.V0 * dP.c1.x; o[4] = G.V0 * dP.c1.y; o[5] = G.V0 * dP.c1.z;
+    o[6] = G.V0 * dP.c2.x; o[7] = G.V0 * dP.c2.y; o[8] = G.V0 * dP.c2.z;
+    // dP/dmu = F + (J - 2) cof F, dP/dlambda = (J - 1) cof F
+    if (dmu) dmu[e] = -G.V0 * (FL + (J - 2.0) * cofL);
+    if (dlam) dlam[e] = -G.V0 * (J - 1.0) * cofL;
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_vertex_adjoint(ResArgs<R> a,
+                                                           const typename R4t<R>::T* L,
+                                                           const typename R4t<R>::T* B,
+                                                           double* rsq, double* dxd,
+                                                           const int* dir_pos)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= a.n_verts) return;
+    const int v = a.vorder[k];
+    V3<double> hl = gather_vp(a, v);
+    if (a.n_wc > 0) hl = hl + weak_force(a, v, L);
+    const V3<double> xi = x64(a.X[v]);
+    const V3<double> li = x64(L[v]);
+    const int inst = a.vinst_all[v];
+    for (int q = a.plane_ptr[inst]; q < a.plane_ptr[inst + 1]; ++q) {
+        const double* pl = a.planes64 + 5 * q;
+        const V3<double> n = mk(pl[0], pl[1], pl[2]);
+        if (dot(n, xi) - pl[3] < 0.0) hl = hl + (pl[4] * dot(n, li)) * n;
+    }
+    if (v < a.n_free) {
+        const V3<double> r = x64(B[v]) - hl;
+        rsq[k] = dot(r, r);
+    } else {
+        rsq[k] = 0.0;
+        if (dxd) {
+            double* o = dxd + 3 * int64_t(dir_pos[v - a.n_free]);
+            o[0] = -hl.x; o[1] = -hl.y; o[2] = -hl.z;
+        }
+    }
+}
+
+template <class R>
+hipError_t launch_adjoint_assembly(const ResArgs<R>& a, const typename R4t<R>::T* lam,
+                                   const typename R4t<R>::T* b, double* rsq, double* dmu,
+                                   double* dlam, double* dxd, const int* dir_pos, hipStream_t s)
+{
+    if (a.n_tets > 0)
+        hipLaunchKernelGGL((k_tet_adjoint<R>), dim3(nblk(a.n_tets)), dim3(kBlock), 0, s, a, lam,
+                           dmu, dlam);
+    if (a.n_verts > 0)
+        hipLaunchKernelGGL((k_vertex_adjoint<R>), dim3(nblk(a.n_verts)), dim3(kBlock), 0, s, a,
+                           lam, b, rsq, dxd, dir_pos);
+    return hipGetLastError();
+}
+template hipError_t launch_adjoint_assembly<float>(const ResArgs<float>&, const float4*,
+                                                   const float4*, double*, double*, double*,
+                                                   double*, const int*, hipStream_t);
+template hipError_t launch_adjoint_assembly<double>(const ResArgs<double>&, const double4*,
+                                                    const double4*, double*, double*, double*,
+                                                    double*, const int*, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Deterministic segmented sums: fixed per-thread strides and a fixed LDS
+// tree, first per chunk, then per instance over its chunks.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = kBlock / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+        __syncthreads();
+    }
+    return sh[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_chunk_sum(const double* vals, const int64_t* cb,
+                                                     const int64_t* ce, double* partial)
+{
+    __shared__ double sh[kBlock];
+    const int c = blockIdx.x;
+    double s = 0.0;
+    for (int64_t i = cb[c] + threadIdx.x; i < ce[c]; i += kBlock) s += vals[i];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) partial[c] = t;
+}
+
+__global__ __launch_bounds__(kBlock) void k_inst_sum(const double* partial, const int* qptr,
+                                                    double* out)
+{
+    __shared__ double sh[kBlock];
+    const int q = blockIdx.x;
+    double s = 0.0;
+    for (int i = qptr[q] + threadIdx.x; i < qptr[q + 1]; i += kBlock) s += partial[i];
+    const double t = block_sum(s, sh);
+    if (threadIdx.x == 0) out[q] = t;
+}
+
+hipError_t launch_segsum(const double* vals, const SegPlan& plan, int n_inst, double* out,
+                         hipStream_t s)
+{
+    if (plan.n_chunks > 0)
+        hipLaunchKernelGGL(k_chunk_sum, dim3(plan.n_chunks), dim3(kBlock), 0, s, vals, plan.cbeg,
+                           plan.cend, plan.partial);
+    hipLaunchKernelGGL(k_inst_sum, dim3(n_inst), dim3(kBlock), 0, s, plan.partial, plan.qptr, out);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Layout conversion and parameter updates
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_load(const R* x_user, const int* orig_of,
+                                                 const typename R4t<R>::T* xd_int,
+                                                 typename R4t<R>::T* d0, typename R4t<R>::T* d1,
+                                                 typename R4t<R>::T* d2, int n_free, int n_verts)
+{
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n_verts) return;
+    typename R4t<R>::T val;
+    if (v < n_free || xd_int == nullptr) {
+        const int64_t o = orig_of[v];
+        val = typename R4t<R>::T{x_user[3 * o], x_user[3 * o + 1], x_user[3 * o + 2], R(0)};
+    } else {
+        val = xd_int[v - n_free];
+    }
+    d0[v] = val;
+    if (d1) d1[v] = val;
+    if (d2) d2[v] = val;
+}
+
+template <class R>
+hipError_t launch_load(const R* x_user, const int* orig_of, const typename R4t<R>::T* xd_int,
+                       typename R4t<R>::T* d0, typename R4t<R>::T* d1, typename R4t<R>::T* d2,
+                       int n_free, int n_verts, hipStream_t s)
+{
+    if (n_verts > 0)
+        hipLaunchKernelGGL((k_load<R>), dim3(nblk(n_verts)), dim3(kBlock), 0, s, x_user, orig_of,
+                           xd_int, d0, d1, d2, n_free, n_verts);
+    return hipGetLastError();
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_load_vec(const R* v_user, const int* orig_of,
+                                                     typename R4t<R>::T* dst, int n_free,
+                                                     int n_verts)
+{
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n_verts) return;
+    typename R4t<R>::T val{R(0), R(0), R(0), R(0)};
+    if (v < n_free) {
+        const int64_t o = orig_of[v];
+        val = typename R4t<R>::T{v_user[3 * o], v_user[3 * o + 1], v_user[3 * o + 2], R(0)};
+    }
+    dst[v] = val;
+}
+
+template <class R>
+hipError_t launch_load_vec(const R* v_user, const int* orig_of, typename R4t<R>::T* dst,
+                           int n_free, int n_verts, hipStream_t s)
+{
+    if (n_verts > 0)
+        hipLaunchKernelGGL((k_load_vec<R>), dim3(nblk(n_verts)), dim3(kBlock), 0, s, v_user,
+                           orig_of, dst, n_free, n_verts);
+    return hipGetLastError();
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_store(const typename R4t<R>::T* src, const int* orig_of,
+                                                  R* x_user, int n_verts)
+{
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n_verts) return;
+    const typename R4t<R>::T p = src[v];
+    const int64_t o = orig_of[v];
+    x_user[3 * o] = p.x;
+    x_user[3 * o + 1] = p.y;
+    x_user[3 * o + 2] = p.z;
+}
+
+template <class R>
+hipError_t launch_store(const typename R4t<R>::T* src, const int* orig_of, R* x_user, int n_verts,
+                        hipStream_t s)
+{
+    if (n_verts > 0)
+        hipLaunchKernelGGL((k_store<R>), dim3(nblk(n_verts)), dim3(kBlock), 0, s, src, orig_of,
+                           x_user, n_verts);
+    return hipGetLastError();
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_store64(const typename R4t<R>::T* src,
+                                                    const int* orig_of, double* x_user,
+                                                    int n_verts)
+{
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n_verts) return;
+    const typename R4t<R>::T p = src[v];
+    const int64_t o = orig_of[v];
+    x_user[3 * o] = double(p.x);
+    x_user[3 * o + 1] = double(p.y);
+    x_user[3 * o + 2] = double(p.z);
+}
+
+template <class R>
+hipError_t launch_store64(const typename R4t<R>::T* src, const int* orig_of, double* x_user,
+                          int n_verts, hipStream_t s)
+{
+    if (n_verts > 0)
+        hipLaunchKernelGGL((k_store64<R>), dim3(nblk(n_verts)), dim3(kBlock), 0, s, src, orig_of,
+                           x_user, n_verts);
+    return hipGetLastError();
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_copy4(const typename R4t<R>::T* src,
+                                                  typename R4t<R>::T* dst, int n)
+{
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v < n) dst[v] = src[v];
+}
+
+template <class R>
+hipError_t launch_copy4(const typename R4t<R>::T* src, typename R4t<R>::T* dst, int n,
+                        hipStream_t s)
+{
+    if (n > 0) hipLaunchKernelGGL((k_copy4<R>), dim3(nblk(n)), dim3(kBlock), 0, s, src, dst, n);
+    return hipGetLastError();
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_set_geo(const double* mu, const double* lam,
+                                                    TetGeo* geo, int n_tets)
+{
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e >= n_tets) return;
+    geo[e].mu = mu[e];
+    geo[e].lam = lam[e];
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_set_visits(const TetGeo* geo, const int* rv, int n,
+                                                       R* vmu, R* vlam)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= n) return;
+    const TetGeo& G = geo[rv[k] >> 2];
+    vmu[k] = R(G.V0 * G.mu);
+    vlam[k] = R(G.V0 * G.lam);
+}
+
+template <class R>
+hipError_t launch_set_materials(const double* mu, const double* lam, TetGeo* geo, int n_tets,
+                                const int* rv, int n_vis_free, R* vmu, R* vlam, hipStream_t s)
+{
+    if (n_tets > 0)
+        hipLaunchKernelGGL((k_set_geo<R>), dim3(nblk(n_tets)), dim3(kBlock), 0, s, mu, lam, geo,
+                           n_tets);
+    if (n_vis_free > 0)
+        hipLaunchKernelGGL((k_set_visits<R>), dim3(nblk(n_vis_free)), dim3(kBlock), 0, s, geo, rv,
+                           n_vis_free, vmu, vlam);
+    return hipGetLastError();
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_set_dirichlet(const double* xd, const int* dir_internal,
+                                                          int nd, int n_free,
+                                                          typename R4t<R>::T* xd_int)
+{
+    const int k = blockIdx.x * kBlock + threadIdx.x;
+    if (k >= nd) return;
+    xd_int[dir_internal[k] - n_free] =
+        typename R4t<R>::T{R(xd[3 * k]), R(xd[3 * k + 1]), R(xd[3 * k + 2]), R(0)};
+}
+
+template <class R>
+hipError_t launch_set_dirichlet(const double* xd, const int* dir_internal, int nd, int n_free,
+                                typename R4t<R>::T* xd_int, hipStream_t s)
+{
+    if (nd > 0)
+        hipLaunchKernelGGL((k_set_dirichlet<R>), dim3(nblk(nd)), dim3(kBlock), 0, s, xd,
+                           dir_internal, nd, n_free, xd_int);
+    return hipGetLastError();
+}
+
+#define PBNG_INST(R)                                                                              \
+    template hipError_t launch_load<R>(const R*, const int*, const R4t<R>::T*, R4t<R>::T*,       \
+                                       R4t<R>::T*, R4t<R>::T*, int, int, hipStream_t);           \
+    template hipError_t launch_load_vec<R>(const R*, const int*, R4t<R>::T*, int, int,           \
+                                           hipStream_t);                                          \
+    template hipError_t launch_store<R>(const R4t<R>::T*, const int*, R*, int, hipStream_t);     \
+    template hipError_t launch_copy4<R>(const R4t<R>::T*, R4t<R>::T*, int, hipStream_t);         \
+    template hipError_t launch_store64<R>(const R4t<R>::T*, const int*, double*, int,            \
+                                          hipStream_t);                                           \
+    template hipError_t launch_set_materials<R>(const double*, const double*, TetGeo*, int,      \
+                                                const int*, int, R*, R*, hipStream_t);            \
+    template hipError_t launch_set_dirichlet<R>(const double*, const int*, int, int, R4t<R>::T*, \
+                                                hipStream_t);
+PBNG_INST(float)
+PBNG_INST(double)
+
+}  // namespace pbng

@@ -1,0 +1,128 @@
+"""Host-side checks of libpbng that need no GPU: the library loads and
+exports every symbol include/pbng.h declares, its node colouring matches the
+oracle's bit for bit, the Lame conversion matches Eq. (lame), and invalid
+problems are rejected with the documented status before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2306_09021_amd import pbng
+from paper_2306_09021_amd import scenarios as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    with open(os.path.join(ROOT, "include", "pbng.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*(?:int32_t|const char\*)\s+(pbng_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = ctypes.CDLL(pbng.LIB_PATH)
+    names = header_functions()
+    assert len(names) >= 19
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(pbng.exported_symbols()) == names
+    assert pbng.lib().pbng_version() == 1
+
+
+def test_lame_matches_paper_formula_and_oracle():
+    E = np.array([1e3, 1e4, 1e5, 3.3e4])
+    nu = np.array([0.3, 0.3, 0.45, 0.48])
+    mu, lam = pbng.lame(E, nu)
+    mo, lo = O.lame(E, nu)
+    assert np.array_equal(mu, mo) and np.array_equal(lam, lo)
+    with pytest.raises(pbng.PBNGError) as e:
+        pbng.lame(1e4, 0.5)
+    assert e.value.code == -1
+
+
+def _colors_both(sc):
+    hp = pbng.problem_from_scenario(sc)
+    c1, n1 = pbng.color(hp)
+    c2, n2 = O.color(O.make_problem(sc))
+    return c1, n1, c2, n2
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: S.config_plain_f64(),
+    lambda: S.gravity_beam(24, 8, 8, 1.0 / 7),
+    lambda: S.twist_box(7, "nh"),
+])
+def test_color_bit_exact_vs_oracle(maker):
+    c1, n1, c2, n2 = _colors_both(maker())
+    assert n1 == n2 == 5
+    assert np.array_equal(c1, c2)
+
+
+def test_color_with_weak_constraints_bit_exact():
+    from tests.test_oracle_solve import with_extras, small_twist
+    sc = with_extras(small_twist(5))
+    c1, n1, c2, n2 = _colors_both(sc)
+    assert n1 == n2 and np.array_equal(c1, c2)
+
+
+def test_color_batched_instances_are_independent():
+    scs = S.config_batched(6, seed=4, n_lo=4, n_hi=8)
+    for sc in scs:
+        c1, n1, c2, n2 = _colors_both(sc)
+        assert np.array_equal(c1, c2)
+
+
+def test_color_rejects_bad_index():
+    sc = S.twist_box(3, "nh")
+    hp = pbng.problem_from_scenario(sc)
+    hp.tets[0, 0] = 10 ** 6
+    with pytest.raises(pbng.PBNGError) as e:
+        pbng.color(hp)
+    assert e.value.code == -2
+
+
+def _create_err(hp, colors=None, real="f32"):
+    with pytest.raises(pbng.PBNGError) as e:
+        pbng.Workspace([hp], colors=colors, real=real)
+    return e.value.code
+
+
+def test_workspace_rejects_invalid_problems_before_device_work():
+    def fresh():
+        return pbng.problem_from_scenario(S.twist_box(4, "nh"))
+    hp = fresh()
+    hp.tets[0, [1, 2]] = hp.tets[0, [2, 1]]          # inverted rest tet
+    assert _create_err(hp) == -2
+    hp = fresh()
+    hp.tets[3, 1] = hp.tets[3, 0]                    # repeated vertex
+    assert _create_err(hp) == -2
+    hp = fresh()
+    hp.mu = -1.0                                      # mu <= 0
+    assert _create_err(hp) == -3
+    hp = fresh()
+    hp.rest_pos[5, 1] = np.nan                        # non-finite input
+    assert _create_err(hp) == -5
+    hp = fresh()
+    col, _ = pbng.color(hp)
+    col = col.copy()
+    t = hp.tets[0]
+    free = [v for v in t if col[v] >= 0]
+    col[free[1]] = col[free[0]]                       # two same-coloured vertices in one tet
+    assert _create_err(hp, colors=col) == -4
+    hp = fresh()
+    hp.dirichlet_idx = np.concatenate([hp.dirichlet_idx, hp.dirichlet_idx[:1]]).astype(np.int32)
+    hp.dirichlet_x = np.concatenate([hp.dirichlet_x, hp.dirichlet_x[:1]])
+    assert _create_err(hp) == -1                      # repeated Dirichlet index
+    hp = fresh()
+    assert _create_err(hp, real="f32") in (-6, -7) or torch_has_gpu()
+
+
+def torch_has_gpu():
+    try:
+        import torch
+        return torch.cuda.is_available()
+    except Exception:
+        return False
