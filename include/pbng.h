@@ -136,7 +136,8 @@ typedef struct pbng_problem {
  *  safeguard       PBNG_SAFEGUARD_*; max_halvings step halvings at most
  *                  (a vertex whose step never passes keeps its position)
  *  lanes           lanes of a 64-wide wavefront per vertex (1, 2, 4, 8,
- *                  16); 0 = choose automatically
+ *                  16, 32, 64); 0 = per colour, the power of two covering
+ *                  half the colour's mean number of incident tets
  *  sweeps_per_graph  >0: capture that many steady-state sweeps in one HIP
  *                  graph and replay it; 0 = plain launches
  *  resume          1: continue the acceleration state (x^{l-1}, l,
@@ -280,9 +281,9 @@ int32_t pbng_residual(pbng_workspace* ws, const void* x, double* res_norm, doubl
  * block Gauss-Seidel over the same colouring, then assemble
  *   dL/dmu_e     = -V0_e < F_e + (J_e - 2) cof F_e , Lam_e >
  *   dL/dlambda_e = -V0_e < (J_e - 1) cof F_e , Lam_e >
- *   dL/dx_k      = -(H lam)_k  for Dirichlet vertices k,
- * Lam_e = sum_j lam_j dN_j^T.  dL_dx: device [sum n_verts][3] (workspace
- * real type; Dirichlet rows ignored).  Outputs (device, double, any may be
+ *   dL/dx_k      = (dL/dx)_k - (H lam)_k  for Dirichlet vertices k
+ * (the first term because x*_k = x_D,k), Lam_e = sum_j lam_j dN_j^T.
+ * dL_dx: device [sum n_verts][3] (workspace real type).  Outputs (device, double, any may be
  * NULL): dL_dxD [sum n_dirichlet][3] in creation order, dL_dmu and
  * dL_dlambda [sum n_tets], lam_out [sum n_verts][3] (zero on Dirichlet
  * rows).  stats [n_instances] (host, may be NULL): sweeps, residuals of
@@ -293,9 +294,11 @@ int32_t pbng_adjoint(pbng_workspace* ws, const void* x_eq, const void* dL_dx, do
                      const pbng_adjoint_opts* o, pbng_stats* stats, void* hip_stream);
 
 /*
- * Launch-level access for measurement: run n_sweeps plain sweeps on the
- * workspace's internal iterate (no acceleration, no residual), or a single
- * colour phase, on hip_stream without synchronising.  The internal iterate
+ * Launch-level access for measurement: run n_sweeps sweeps (with the
+ * blend of o->accel, no residual) on the workspace's internal iterate, or a
+ * single colour phase (the same kernel the solve launches for o; with
+ * acceleration it blends with omega = gamma = 1 and does not advance the
+ * iteration), on hip_stream without synchronising.  The internal iterate
  * is loaded from x (device) by pbng_load, and written back by pbng_store.
  * Algorithmic bytes of one colour phase are reported by
  * pbng_phase_bytes (sum over its visits of the 56-byte visit record and

@@ -336,6 +336,7 @@ struct pbng_workspace {
     std::vector<int> ncol_inst;
     std::vector<int64_t> nfree_inst;
     std::vector<int64_t> phase_bytes, phase_verts, phase_visits;
+    std::vector<int> phase_lanes;          // automatic lanes per vertex of each colour
     double mean_valence = 0.0;
 
     // sweep data
@@ -560,6 +561,16 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
             ws->phase_verts[c] = ws->col_ptr[c + 1] - ws->col_ptr[c];
             ws->phase_bytes[c] = vis * 60 + ws->phase_verts[c] * 24 + uniq * 12;
         }
+    }
+    // lanes per vertex of a colour: the power of two covering half the mean
+    // number of visits, so that a lane takes about two visits (measured best
+    // on MI355X for valence 8 and 32 grids)
+    ws->phase_lanes.assign(ws->ncol, 1);
+    for (int c = 0; c < ws->ncol; ++c) {
+        const double mv = ws->phase_verts[c] ? double(ws->phase_visits[c]) / ws->phase_verts[c] : 1.0;
+        int L = 1;
+        while (L < 64 && 2 * L < mv) L *= 2;
+        ws->phase_lanes[c] = L;
     }
 
     // per-vertex arrays in internal order
@@ -799,15 +810,15 @@ void residual_internal(pbng_workspace* ws, const void* X, double* r_out, hipStre
     for (int q = 0; q < ws->n_inst; ++q) ws->hbuf[q] = std::sqrt(ws->hbuf[q]);
 }
 
-int pick_lanes(const pbng_workspace* ws, int requested)
+// Lanes per vertex for colour c: the requested power of two, or (0) the
+// workspace's automatic choice for that colour.
+int pick_lanes(const pbng_workspace* ws, int requested, int c)
 {
-    if (requested == 1 || requested == 2 || requested == 4 || requested == 8 || requested == 16) return requested;
-    if (requested != 0) fail(PBNG_EINVAL, "lanes must be 0, 1, 2, 4, 8 or 16");
-    const double mv = ws->mean_valence;
-    if (mv >= 24) return 8;
-    if (mv >= 10) return 4;
-    if (mv >= 4) return 2;
-    return 1;
+    if (requested == 0) return c >= 0 && c < ws->ncol ? ws->phase_lanes[c] : 8;
+    if (requested == 1 || requested == 2 || requested == 4 || requested == 8 || requested == 16 ||
+        requested == 32 || requested == 64)
+        return requested;
+    fail(PBNG_EINVAL, "lanes must be 0, 1, 2, 4, 8, 16, 32 or 64");
 }
 
 void check_solve_opts(const pbng_solve_opts* o)
@@ -841,14 +852,14 @@ void ensure_ring(pbng_workspace* ws)
 }
 
 template <class R>
-void launch_sweep(pbng_workspace* ws, const pbng_solve_opts* o, int lanes, double omega,
-                  double gamma, hipStream_t s)
+void launch_sweep(pbng_workspace* ws, const pbng_solve_opts* o, double omega, double gamma, hipStream_t s)
 {
     const bool accel = o->accel != PBNG_ACCEL_NONE;
     const SweepArgs<R> a = sweep_args<R>(ws, omega, gamma, o->max_halvings);
     for (int c = 0; c < ws->ncol; ++c)
-        hipchk(launch_phase<R>(a, ws->model, lanes, accel, o->safeguard == PBNG_SAFEGUARD_BACKTRACK,
-                               ws->any_wc, ws->col_ptr[c], ws->col_ptr[c + 1], s),
+        hipchk(launch_phase<R>(a, ws->model, pick_lanes(ws, o->lanes, c), accel,
+                               o->safeguard == PBNG_SAFEGUARD_BACKTRACK, ws->any_wc, ws->col_ptr[c],
+                               ws->col_ptr[c + 1], s),
                "sweep launch");
     if (accel) std::swap(ws->W.p, ws->N.p);
 }
@@ -859,7 +870,7 @@ int32_t solve_t(pbng_workspace* ws, void* x, const pbng_solve_opts* o, pbng_stat
     using R4 = typename R4t<R>::T;
     const int n = ws->n_inst;
     const bool accel = o->accel != PBNG_ACCEL_NONE;
-    const int lanes = pick_lanes(ws, o->lanes);
+    pick_lanes(ws, o->lanes, 0);
     if (accel) ensure_ring<R>(ws);
     const bool resume = o->resume && ws->ring_valid;
     if (!resume) {
@@ -906,7 +917,7 @@ int32_t solve_t(pbng_workspace* ws, void* x, const pbng_solve_opts* o, pbng_stat
         } else if (o->accel == PBNG_ACCEL_SOR) {
             omega = o->omega;
         }
-        launch_sweep<R>(ws, o, lanes, omega, gamma, s);
+        launch_sweep<R>(ws, o, omega, gamma, s);
         ws->omega_l = omega;
         ws->sweep_l++;
         for (int q = 0; q < n; ++q) sweeps[q] += act[q];
@@ -1019,7 +1030,7 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
     using R4 = typename R4t<R>::T;
     const int n = ws->n_inst;
     const bool accel = o->accel == PBNG_ACCEL_CHEBYSHEV;
-    const int lanes = pick_lanes(ws, o->lanes);
+    pick_lanes(ws, o->lanes, 0);
     if (!ws->L.p) ws->L.alloc(ws->nv * ws->r4());
     if (!ws->B.p) ws->B.alloc(ws->nv * ws->r4());
     if (accel) {
@@ -1057,7 +1068,8 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
         omega_prev = omega;
         const AdjArgs<R> a = adj_args<R>(ws, omega, accel ? o->gamma : 1.0);
         for (int c = 0; c < ws->ncol; ++c)
-            hipchk(launch_adjoint_phase<R>(a, lanes, accel, ws->any_wc, ws->col_ptr[c], ws->col_ptr[c + 1], s),
+            hipchk(launch_adjoint_phase<R>(a, pick_lanes(ws, o->lanes, c), accel, ws->any_wc, ws->col_ptr[c],
+                                           ws->col_ptr[c + 1], s),
                    "adjoint launch");
         if (accel) std::swap(ws->L.p, ws->LN.p);
         for (int q = 0; q < n; ++q) sweeps[q] += act[q];
@@ -1382,7 +1394,7 @@ int32_t pbng_sweeps(pbng_workspace* ws, int32_t n_sweeps, const pbng_solve_opts*
         check_solve_opts(o);
         if (!ws->ring_valid) fail(PBNG_EINVAL, "call pbng_load first");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        const int lanes = pick_lanes(ws, o->lanes);
+        pick_lanes(ws, o->lanes, 0);
         for (int k = 0; k < n_sweeps; ++k) {
             double omega = 1.0, gamma = 1.0;
             if (o->accel == PBNG_ACCEL_CHEBYSHEV) {
@@ -1391,8 +1403,8 @@ int32_t pbng_sweeps(pbng_workspace* ws, int32_t n_sweeps, const pbng_solve_opts*
             } else if (o->accel == PBNG_ACCEL_SOR) {
                 omega = o->omega;
             }
-            if (ws->real == PBNG_F64) launch_sweep<double>(ws, o, lanes, omega, gamma, s);
-            else launch_sweep<float>(ws, o, lanes, omega, gamma, s);
+            if (ws->real == PBNG_F64) launch_sweep<double>(ws, o, omega, gamma, s);
+            else launch_sweep<float>(ws, o, omega, gamma, s);
             ws->omega_l = omega;
             ws->sweep_l++;
         }
@@ -1407,16 +1419,18 @@ int32_t pbng_phase(pbng_workspace* ws, int32_t color, const pbng_solve_opts* o, 
         check_solve_opts(o);
         if (!ws->ring_valid) fail(PBNG_EINVAL, "call pbng_load first");
         if (color < 0 || color >= ws->ncol) fail(PBNG_EINVAL, "colour out of range");
-        if (o->accel != PBNG_ACCEL_NONE) fail(PBNG_EINVAL, "pbng_phase runs unaccelerated phases only");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        const int lanes = pick_lanes(ws, o->lanes);
+        const int lanes = pick_lanes(ws, o->lanes, color);
         const bool safe = o->safeguard == PBNG_SAFEGUARD_BACKTRACK;
+        const bool accel = o->accel != PBNG_ACCEL_NONE;
+        // with acceleration the phase blends with omega = 1 and gamma = 1 and
+        // does not advance the ring (measurement of the fused kernel only)
         if (ws->real == PBNG_F64)
-            hipchk(launch_phase<double>(sweep_args<double>(ws, 1.0, 1.0, o->max_halvings), ws->model, lanes, false,
+            hipchk(launch_phase<double>(sweep_args<double>(ws, 1.0, 1.0, o->max_halvings), ws->model, lanes, accel,
                                         safe, ws->any_wc, ws->col_ptr[color], ws->col_ptr[color + 1], s),
                    "phase");
         else
-            hipchk(launch_phase<float>(sweep_args<float>(ws, 1.0, 1.0, o->max_halvings), ws->model, lanes, false,
+            hipchk(launch_phase<float>(sweep_args<float>(ws, 1.0, 1.0, o->max_halvings), ws->model, lanes, accel,
                                        safe, ws->any_wc, ws->col_ptr[color], ws->col_ptr[color + 1], s),
                    "phase");
         return PBNG_OK;

@@ -346,6 +346,8 @@ static hipError_t dispatch_lanes(const SweepArgs<R>& a, int lanes, bool accel, b
     case 4: return dispatch_flags<R, MODEL, 4>(a, accel, safe, wc, vb, ve, s);
     case 8: return dispatch_flags<R, MODEL, 8>(a, accel, safe, wc, vb, ve, s);
     case 16: return dispatch_flags<R, MODEL, 16>(a, accel, safe, wc, vb, ve, s);
+    case 32: return dispatch_flags<R, MODEL, 32>(a, accel, safe, wc, vb, ve, s);
+    case 64: return dispatch_flags<R, MODEL, 64>(a, accel, safe, wc, vb, ve, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -493,6 +495,8 @@ hipError_t launch_adjoint_phase(const AdjArgs<R>& a, int lanes, bool accel, bool
     case 4: return adj_flags<R, 4>(a, accel, wc, vbeg, vend, s);
     case 8: return adj_flags<R, 8>(a, accel, wc, vbeg, vend, s);
     case 16: return adj_flags<R, 16>(a, accel, wc, vbeg, vend, s);
+    case 32: return adj_flags<R, 32>(a, accel, wc, vbeg, vend, s);
+    case 64: return adj_flags<R, 64>(a, accel, wc, vbeg, vend, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -717,10 +721,12 @@ __global__ __launch_bounds__(kBlock) void k_vertex_adjoint(ResArgs<R> a,
         const V3<double> r = x64(B[v]) - hl;
         rsq[k] = dot(r, r);
     } else {
+        // x*_D = x_D, so dL/dx_D = (dL/dx)_D - (H lam)_D
         rsq[k] = 0.0;
         if (dxd) {
+            const V3<double> g = x64(B[v]) - hl;
             double* o = dxd + 3 * int64_t(dir_pos[v - a.n_free]);
-            o[0] = -hl.x; o[1] = -hl.y; o[2] = -hl.z;
+            o[0] = g.x; o[1] = g.y; o[2] = g.z;
         }
     }
 }
@@ -833,12 +839,9 @@ __global__ __launch_bounds__(kBlock) void k_load_vec(const R* v_user, const int*
 {
     const int v = blockIdx.x * kBlock + threadIdx.x;
     if (v >= n_verts) return;
-    typename R4t<R>::T val{R(0), R(0), R(0), R(0)};
-    if (v < n_free) {
-        const int64_t o = orig_of[v];
-        val = typename R4t<R>::T{v_user[3 * o], v_user[3 * o + 1], v_user[3 * o + 2], R(0)};
-    }
-    dst[v] = val;
+    (void)n_free;
+    const int64_t o = orig_of[v];
+    dst[v] = typename R4t<R>::T{v_user[3 * o], v_user[3 * o + 1], v_user[3 * o + 2], R(0)};
 }
 
 template <class R>

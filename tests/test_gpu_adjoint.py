@@ -1,0 +1,202 @@
+"""GPU adjoint (pbng_adjoint and the autograd wrapper) against the FP64
+oracle: dense adjoint solves and gradient assembly on tiny meshes, FP64
+central differences of the loss on 20 random directions, and properties of
+the full 32^3 differentiable instance (FP64 adjoint residual, exact
+gradient assembly) that hold at any size.
+
+Tolerances: FP64 workspaces 1e-8 (dense solve vs Gauss-Seidel to 1e-12);
+FP32 workspaces 1e-4 relative (the method's FP32 adjoint target against
+finite differences)."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import dense as D
+from paper_2306_09021_amd import pbng
+from paper_2306_09021_amd import scenarios as S
+
+from .gpu_util import announce, dev_x, host, require_gpu, torch, workspace
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def tiny_case(seed=11, n=4):
+    rng = np.random.default_rng(seed)
+    sc = S.random_cube(rng, n, "nh", 1e4, 0.3, 15.0, 0.9, 1.1, "adj")
+    sc.E = 1e4 * np.exp(0.3 * rng.normal(size=sc.n_tets))
+    sc.nu = rng.uniform(0.25, 0.42, size=sc.n_tets)
+    target = sc.rest_pos + 0.05 * rng.normal(size=sc.rest_pos.shape)
+    return sc, target
+
+
+def loss_grad(x, target, op):
+    free = (op.is_dir == 0)[:, None]
+    return float((((x - target) * free) ** 2).sum()), 2.0 * (x - target) * free
+
+
+def gpu_adjoint(sc, x, dLdx, real, **kw):
+    ws = workspace([sc], real)
+    o = pbng.adjoint_opts(**kw)
+    rc, out, st = ws.adjoint(dev_x(x, real), dev_x(dLdx, real), o)
+    return {k: host(v) for k, v in out.items()}, st[0], rc
+
+
+@pytest.mark.parametrize("real,tol", [("f64", 1e-8), ("f32", 1e-4)])
+def test_adjoint_matches_dense_solve(real, tol):
+    sc, target = tiny_case()
+    op = O.make_problem(sc)
+    x, it, rel = D.newton(op, sc.initial_iterate(), tol=1e-14)
+    if real == "f32":
+        x = x.astype(np.float32).astype(np.float64)
+    L0, g = loss_grad(x, target, op)
+    g = g.copy()
+    g[op.dirichlet_idx] = 0.3          # a direct dependence on the Dirichlet rows
+    lam_d = D.adjoint_dense(op, x, g)
+    dmu, dla, dxd = O.adjoint_gradients(op, x, lam_d)
+    dxd = dxd[op.dirichlet_idx] + g[op.dirichlet_idx]
+    announce("adjoint dense parity %s" % real)
+    out, st, rc = gpu_adjoint(sc, x, g, real, rel_tol=1e-12 if real == "f64" else 1e-6,
+                              max_sweeps=20000, check_every=20, accel="chebyshev", rho=0.9,
+                              gamma=1.0)
+    assert st["rel_residual"] <= (1e-11 if real == "f64" else 2e-6)
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert rel(out["lam_vec"], lam_d) <= tol
+    assert rel(out["mu"], dmu) <= tol
+    assert rel(out["lam"], dla) <= tol
+    assert rel(out["xd"], dxd) <= tol
+
+
+def test_fp32_adjoint_against_central_differences():
+    """FP32 forward (to 1e-6) and FP32 adjoint on the GPU against FP64
+    central differences (step 1e-6, dense Newton re-solves) on 20 random
+    directions in (x_D, log mu, log lambda): relative error <= 1e-4."""
+    sc, target = tiny_case(seed=3)
+    op = O.make_problem(sc)
+    announce("adjoint fp32 vs central differences, 20 directions")
+    ws = workspace([sc], "f32")
+    x = dev_x(sc.initial_iterate(), "f32")
+    rc, st = ws.solve(x, max_sweeps=20000, rel_tol=1e-6, check_every=10, accel="chebyshev",
+                      rho=0.9, gamma=1.0)
+    print("forward", st[0])
+    # FP32 positions put a floor under the FP64 residual of a tiny mesh
+    assert st[0]["rel_residual"] <= 1e-5
+    xs = host(x)
+    _, g = loss_grad(xs, target, op)
+    rc, out, sta = ws.adjoint(x, dev_x(g, "f32"), pbng.adjoint_opts(rel_tol=1e-6, max_sweeps=20000))
+    dxd, dmu, dla = host(out["xd"]), host(out["mu"]), host(out["lam"])
+
+    def L_of(mu, lam, xd):
+        op2 = O.OracleProblem(**{**op.__dict__, "mu": np.ascontiguousarray(mu),
+                                 "lam": np.ascontiguousarray(lam),
+                                 "dirichlet_x": np.ascontiguousarray(xd)})
+        xx, _, _ = D.newton(op2, sc.initial_iterate(), tol=1e-14)
+        return loss_grad(xx, target, op)[0]
+
+    rng = np.random.default_rng(7)
+    h = 1e-6
+    worst = 0.0
+    for _ in range(20):
+        vx = rng.normal(size=op.dirichlet_x.shape)
+        vm = rng.normal(size=op.nt)
+        vl = rng.normal(size=op.nt)
+        s = np.sqrt((vx ** 2).sum() + (vm ** 2).sum() + (vl ** 2).sum())
+        vx, vm, vl = vx / s, vm / s, vl / s
+        Lp = L_of(op.mu * np.exp(h * vm), op.lam * np.exp(h * vl), op.dirichlet_x + h * vx)
+        Lm = L_of(op.mu * np.exp(-h * vm), op.lam * np.exp(-h * vl), op.dirichlet_x - h * vx)
+        fd = (Lp - Lm) / (2 * h)
+        an = float((dxd * vx).sum() + (dmu * op.mu * vm).sum() + (dla * op.lam * vl).sum())
+        err = abs(an - fd) / max(abs(fd), 1e-12)
+        worst = max(worst, err)
+    print("worst relative error over 20 directions", worst)
+    assert worst <= 1e-4
+
+
+def test_autograd_function_matches_oracle():
+    from paper_2306_09021_amd.autograd import Equilibrium
+    sc, target = tiny_case(seed=21)
+    op = O.make_problem(sc)
+    announce("autograd Equilibrium f64")
+    ws = workspace([sc], "f64")
+    xd = torch.tensor(sc.dirichlet_x, dtype=torch.float64, device="cuda", requires_grad=True)
+    mu = torch.tensor(op.mu, dtype=torch.float64, device="cuda", requires_grad=True)
+    lam = torch.tensor(op.lam, dtype=torch.float64, device="cuda", requires_grad=True)
+    x0 = dev_x(sc.initial_iterate(), "f64")
+    so = pbng.solve_opts(max_sweeps=20000, rel_tol=1e-13, check_every=10, accel="chebyshev",
+                         rho=0.9, gamma=1.0)
+    ao = pbng.adjoint_opts(rel_tol=1e-12, max_sweeps=20000)
+    x = Equilibrium.apply(xd, mu, lam, ws, x0, so, ao)
+    T = torch.tensor(target, dtype=torch.float64, device="cuda")
+    free = torch.tensor((op.is_dir == 0)[:, None].astype(np.float64), device="cuda")
+    L = (((x - T) * free) ** 2).sum()
+    L.backward()
+    xs = host(x)
+    xn, _, _ = D.newton(op, sc.initial_iterate(), tol=1e-14)
+    assert np.linalg.norm(xs - xn) / np.linalg.norm(xn) <= 1e-10
+    _, g = loss_grad(xn, target, op)
+    lam_d = D.adjoint_dense(op, xn, g)
+    dmu, dla, dxd = O.adjoint_gradients(op, xn, lam_d)
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert rel(host(mu.grad), dmu) <= 1e-8
+    assert rel(host(lam.grad), dla) <= 1e-8
+    assert rel(host(xd.grad), dxd[op.dirichlet_idx]) <= 1e-8
+
+
+def test_batched_adjoint_instances_independent():
+    cases = [tiny_case(seed=s) for s in (31, 32, 33)]
+    scs = [c[0] for c in cases]
+    announce("batched adjoint 3 instances f64")
+    xs, gs, refs = [], [], []
+    for sc, target in cases:
+        op = O.make_problem(sc)
+        x, _, _ = D.newton(op, sc.initial_iterate(), tol=1e-14)
+        _, g = loss_grad(x, target, op)
+        lam_d = D.adjoint_dense(op, x, g)
+        refs.append(O.adjoint_gradients(op, x, lam_d))
+        xs.append(x)
+        gs.append(g)
+    ws = workspace(scs, "f64")
+    rc, out, st = ws.adjoint(dev_x(np.concatenate(xs), "f64"), dev_x(np.concatenate(gs), "f64"),
+                             pbng.adjoint_opts(rel_tol=1e-12, max_sweeps=20000))
+    dmu = host(out["mu"])
+    off = 0
+    for (sc, _), ref in zip(cases, refs):
+        seg = dmu[off:off + sc.n_tets]
+        assert np.linalg.norm(seg - ref[0]) <= 1e-8 * np.linalg.norm(ref[0])
+        off += sc.n_tets
+
+
+def test_full_size_differentiable_instance_properties():
+    """One 32^3 instance of the differentiable workload (148,955 tets), FP32
+    forward and adjoint on the GPU.  Checked at full size: the FP64 residual
+    of the adjoint system b - H lam evaluated by the oracle, and the
+    oracle's gradient assembly from the same (x, lam)."""
+    sc = S.config_differentiable(1)[0]
+    announce("full 32^3 differentiable instance f32 forward + adjoint")
+    ws = workspace([sc], "f32")
+    x = dev_x(sc.initial_iterate(), "f32")
+    rc, st = ws.solve(x, max_sweeps=20000, rel_tol=1e-6, check_every=50, accel="chebyshev",
+                      rho=0.95, gamma=1.7)
+    print("forward", st[0])
+    xs = host(x)
+    op = O.make_problem(sc)
+    free = (op.is_dir == 0)[:, None]
+    g = 2.0 * (xs - sc.loss_target) * free
+    g32 = g.astype(np.float32).astype(np.float64)
+    rc, out, sta = ws.adjoint(x, dev_x(g32, "f32"), pbng.adjoint_opts(rel_tol=1e-6, max_sweeps=20000))
+    print("adjoint", sta[0])
+    lam_g = host(out["lam_vec"])
+    Hl = O.hvp(op, xs, lam_g)
+    r = (g32 - Hl) * free
+    rel = np.linalg.norm(r) / np.linalg.norm(g32 * free)
+    print("FP64 adjoint residual of the GPU solution", rel)
+    assert rel <= 5e-5
+    dmu, dla, dxd = O.adjoint_gradients(op, xs, lam_g)
+    assert np.linalg.norm(host(out["mu"]) - dmu) <= 1e-9 * np.linalg.norm(dmu)
+    assert np.linalg.norm(host(out["lam"]) - dla) <= 1e-9 * np.linalg.norm(dla)
+    ref_xd = dxd[op.dirichlet_idx] + g32[op.dirichlet_idx]
+    assert np.linalg.norm(host(out["xd"]) - ref_xd) <= 1e-9 * np.linalg.norm(ref_xd)

@@ -52,7 +52,7 @@ def test_plain_f64_corotated_cube10_parity():
 
 
 @pytest.mark.parametrize("model", ["nh", "corotated"])
-@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("lanes", [0, 1, 2, 4, 8, 16, 32, 64])
 def test_f32_parity_all_lanes(model, lanes):
     sc = S.twist_box(6, model, 1e4, 0.3, 60.0, 1.2, 0.01, seed=2)
     announce("f32 twist6 %s lanes=%d" % (model, lanes))
