@@ -30,25 +30,34 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every source and link libpbng.so; always recompiles."""
+def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
+    """Compile every source and link libpbng.so (or `out`); always
+    recompiles.  `extra` adds compiler flags (e.g. -D switches)."""
     objs = []
-    bdir = os.path.join(HERE, "_build")
+    bdir = os.path.join(HERE, "_build", os.path.basename(out))
     os.makedirs(bdir, exist_ok=True)
     for src in SOURCES:
         obj = os.path.join(bdir, src + ".o")
         cmd = ["hipcc", "-c"] + (["-x", "hip"] if src.endswith(".hip") else [])
-        cmd += [os.path.join(CSRC, src), "-o", obj] + COMMON
+        cmd += [os.path.join(CSRC, src), "-o", obj] + COMMON + list(extra)
         cmd += DEVICE if src.endswith(".hip") else ["-D__HIP_PLATFORM_AMD__"]
-        out = _run(cmd)
-        if verbose and out.strip():
-            print(out)
+        log = _run(cmd)
+        if verbose and log.strip():
+            print(log)
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = out + ".tmp%d" % os.getpid()
     _run(["hipcc", "-shared", "-o", tmp] + objs + DEVICE + ["-lamdhip64"])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    args = [a for a in sys.argv[1:] if a != "-v"]
+    out = LIB
+    extra = []
+    for a in args:
+        if a.startswith("--out="):
+            out = os.path.abspath(a[len("--out="):])
+        else:
+            extra.append(a)
+    print(build(verbose="-v" in sys.argv, out=out, extra=extra))

@@ -330,6 +330,8 @@ struct pbng_workspace {
     int ncol = 0;
     int n_wc = 0, n_planes = 0, nd = 0;
     bool any_wc = false;
+    // general sweep kernel: batched instances, weak constraints or planes
+    bool general() const { return any_wc || n_inst > 1; }
     int device = 0;
     std::vector<int> col_ptr;              // internal free-vertex range of each colour
     std::vector<int64_t> v_off, t_off;     // per instance
@@ -694,7 +696,7 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     upR(ws->planes, planes);
     ws->tet.upload(tet);
     ws->geo.upload(geo);
-    ws->vp.alloc(std::max<int64_t>(1, nt) * 9 * sizeof(double));
+    ws->vp.alloc(std::max<int64_t>(1, nt) * 12 * sizeof(double));
     ws->ebuf.alloc(std::max<int64_t>(1, nt + nv + ws->n_wc) * sizeof(double));
     ws->tet_eidx.upload(tet_eidx);
     ws->vorder.upload(vorder);
@@ -858,7 +860,7 @@ void launch_sweep(pbng_workspace* ws, const pbng_solve_opts* o, double omega, do
     const SweepArgs<R> a = sweep_args<R>(ws, omega, gamma, o->max_halvings);
     for (int c = 0; c < ws->ncol; ++c)
         hipchk(launch_phase<R>(a, ws->model, pick_lanes(ws, o->lanes, c), accel,
-                               o->safeguard == PBNG_SAFEGUARD_BACKTRACK, ws->any_wc, ws->col_ptr[c],
+                               o->safeguard == PBNG_SAFEGUARD_BACKTRACK, ws->general(), ws->col_ptr[c],
                                ws->col_ptr[c + 1], s),
                "sweep launch");
     if (accel) std::swap(ws->W.p, ws->N.p);
@@ -1427,11 +1429,11 @@ int32_t pbng_phase(pbng_workspace* ws, int32_t color, const pbng_solve_opts* o, 
         // does not advance the ring (measurement of the fused kernel only)
         if (ws->real == PBNG_F64)
             hipchk(launch_phase<double>(sweep_args<double>(ws, 1.0, 1.0, o->max_halvings), ws->model, lanes, accel,
-                                        safe, ws->any_wc, ws->col_ptr[color], ws->col_ptr[color + 1], s),
+                                        safe, ws->general(), ws->col_ptr[color], ws->col_ptr[color + 1], s),
                    "phase");
         else
             hipchk(launch_phase<float>(sweep_args<float>(ws, 1.0, 1.0, o->max_halvings), ws->model, lanes, accel,
-                                       safe, ws->any_wc, ws->col_ptr[color], ws->col_ptr[color + 1], s),
+                                       safe, ws->general(), ws->col_ptr[color], ws->col_ptr[color + 1], s),
                    "phase");
         return PBNG_OK;
     });

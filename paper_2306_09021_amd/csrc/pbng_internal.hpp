@@ -77,7 +77,7 @@ struct ResArgs {
     const R4* X;            // positions, internal order
     const int4* tet;        // [n_tets] internal vertex indices
     const TetGeo* geo;      // [n_tets]
-    double* vp;             // [n_tets][9] scratch: V0 P(F) or V0 dP[Lam]
+    double* vp;             // [n_tets][4][3] scratch: V0 P dN_j or V0 dP[Lam] dN_j
     double* ebuf;           // energy summands
     const int* tet_eidx;    // [n_tets] slot of each tet energy in ebuf
     const int* vorder;      // [n_verts] internal vertex at instance-major position k
@@ -117,9 +117,10 @@ struct SegPlan {
 // ---- launchers (pbng_kernels.hip) -------------------------------------
 // launch_load: free vertices from the caller array, Dirichlet vertices from
 // xd_int (or, when xd_int is null, also from the caller array).
+// gen: the general variant (batched instances, weak constraints, planes)
 template <class R>
 hipError_t launch_phase(const SweepArgs<R>& a, int model, int lanes, bool accel, bool safe,
-                        bool wc, int vbeg, int vend, hipStream_t s);
+                        bool gen, int vbeg, int vend, hipStream_t s);
 template <class R>
 hipError_t launch_load(const R* x_user, const int* orig_of, const typename R4t<R>::T* xd_int,
                        typename R4t<R>::T* d0, typename R4t<R>::T* d1, typename R4t<R>::T* d2,

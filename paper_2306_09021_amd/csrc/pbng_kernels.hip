@@ -115,59 +115,129 @@ __device__ __forceinline__ R corot_energy(const Polar<R>& P, R J, R vm, R vl)
     return vm * (d0 * d0 + d1 * d1 + d2 * d2) + R(0.5) * vl * (J - R(1)) * (J - R(1));
 }
 
-template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool WC>
+// Raw record of one visit (loaded before any arithmetic so that the loads of
+// several visits are in flight together).
+template <class R>
+struct VisitRaw {
+    int i1, i2, i3;
+    R m[9];
+    R vm, vl;
+};
+
+template <class R, class A>
+__device__ __forceinline__ VisitRaw<R> load_raw(const A& a, int k)
+{
+    VisitRaw<R> r;
+    r.i1 = a.j1[k];
+    r.i2 = a.j2[k];
+    r.i3 = a.j3[k];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) r.m[q] = a.m[q * a.nvis + k];
+    r.vm = a.vmu[k];
+    r.vl = a.vlam[k];
+    return r;
+}
+
+// Per-vertex accumulators of the local gradient and Hessian pieces.
+template <class R>
+struct Acc {
+    V3<R> g;     // elastic + weak-constraint gradient
+    R S;         // sum V0 mu |dN_i|^2
+    Sym<R> Aw;   // sum V0 lambda c c^T + sum s^2 K
+    Sym<R> Cm;   // Neo-Hookean safeguard: sum V0 mu c c^T
+    V3<R> gw;    // corotated safeguard: weak-constraint part of g
+    Sym<R> Kw;   // corotated safeguard: sum s^2 K
+    R E0, E0a;   // corotated safeguard: elastic energy and sum of |terms|
+};
+
+template <class R, int MODEL, bool SAFE>
+__device__ __forceinline__ void visit_accumulate(Acc<R>& q, const VisitRaw<R>& r, V3<R> e1, V3<R> e2,
+                                                 V3<R> e3)
+{
+    const Cols<R> F = edge_F(e1, e2, e3, r.m);
+    const V3<R> av = mk(-(r.m[0] + r.m[3] + r.m[6]), -(r.m[1] + r.m[4] + r.m[7]),
+                        -(r.m[2] + r.m[5] + r.m[8]));
+    const Cols<R> C = cofactor(F);
+    const R J = dot(F.c0, C.c0);
+    const V3<R> c = apply(C, av);   // cof(F) dN_i
+    const V3<R> p = apply(F, av);   // F dN_i
+    const R vm = r.vm, vl = r.vl;
+    q.S += vm * dot(av, av);
+    sym_add_outer(q.Aw, vl, c);
+    if (MODEL == kNeo) {
+        // V0 P dN_i, P = mu F + (lhat (J - 1) - mu) cof F, lhat = mu + lambda
+        q.g = q.g + vm * p + ((vm + vl) * (J - R(1)) - vm) * c;
+        if (SAFE) sym_add_outer(q.Cm, vm, c);
+    } else {
+        // V0 P dN_i, P = 2 mu (F - R) + lambda (J - 1) cof F
+        Polar<R> pol;
+        polar(F, pol);
+        const V3<R> ra = polar_apply(pol, av);
+        q.g = q.g + (R(2) * vm) * (p - ra) + (vl * (J - R(1))) * c;
+        if (SAFE) {
+            const R e = corot_energy(pol, J, vm, vl);
+            q.E0 += e;
+            q.E0a += abs_(e);
+        }
+    }
+}
+
+// GEN = false: one instance without weak constraints or planes (no
+// per-vertex instance lookup); GEN = true: batched instances with per-
+// instance activity flags, weak constraints and contact planes.
+template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool GEN>
 __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int vend)
 {
     using R4 = typename R4t<R>::T;
+    constexpr bool WC = GEN;
     const int gid = blockIdx.x * kBlock + threadIdx.x;
     const int v = vbeg + gid / LANES;
     const int lane = gid & (LANES - 1);
     if (v >= vend) return;
-    const int inst = a.vinst[v];
+    const int kb = a.vptr[v], ke = a.vptr[v + 1];
     const R4 xw = a.W[v];
-    if (!a.active[inst]) {
-        if (ACCEL && lane == 0) a.N[v] = xw;
-        return;
+    int inst = 0;
+    if (GEN) {
+        inst = a.vinst[v];
+        if (!a.active[inst]) {
+            if (ACCEL && lane == 0) a.N[v] = xw;
+            return;
+        }
     }
     const V3<R> xi = xyz(xw);
 
-    V3<R> g = mk<R>(0, 0, 0);   // elastic + weak-constraint gradient
-    R S = R(0);                 // sum V0 mu |dN_i|^2
-    Sym<R> Aw = sym_zero<R>();  // sum V0 lambda c c^T + sum s^2 K
-    Sym<R> Cm = sym_zero<R>();  // Neo-Hookean safeguard: sum V0 mu c c^T
-    V3<R> gw = mk<R>(0, 0, 0);  // corotated safeguard: weak-constraint part of g
-    Sym<R> Kw = sym_zero<R>();  // corotated safeguard: sum s^2 K
-    R E0 = R(0), E0a = R(0);    // corotated safeguard: elastic energy, sum |.|
+    Acc<R> q;
+    q.g = mk<R>(0, 0, 0);
+    q.S = R(0);
+    q.Aw = sym_zero<R>();
+    q.Cm = sym_zero<R>();
+    q.gw = mk<R>(0, 0, 0);
+    q.Kw = sym_zero<R>();
+    q.E0 = R(0);
+    q.E0a = R(0);
 
-    const int kb = a.vptr[v], ke = a.vptr[v + 1];
-    for (int k = kb + lane; k < ke; k += LANES) {
-        Cols<R> F;
-        V3<R> av;
-        R vm, vl;
-        load_visit(a, k, xi, F, av, vm, vl);
-        const Cols<R> C = cofactor(F);
-        const R J = dot(F.c0, C.c0);
-        const V3<R> c = apply(C, av);   // cof(F) dN_i
-        const V3<R> p = apply(F, av);   // F dN_i
-        S += vm * dot(av, av);
-        sym_add_outer(Aw, vl, c);
-        if (MODEL == kNeo) {
-            // V0 P dN_i, P = mu F + (lhat (J - 1) - mu) cof F, lhat = mu + lambda
-            g = g + vm * p + ((vm + vl) * (J - R(1)) - vm) * c;
-            if (SAFE) sym_add_outer(Cm, vm, c);
-        } else {
-            // V0 P dN_i, P = 2 mu (F - R) + lambda (J - 1) cof F
-            Polar<R> pol;
-            polar(F, pol);
-            const V3<R> ra = polar_apply(pol, av);
-            g = g + (R(2) * vm) * (p - ra) + (vl * (J - R(1))) * c;
-            if (SAFE) {
-                const R e = corot_energy(pol, J, vm, vl);
-                E0 += e;
-                E0a += abs_(e);
-            }
-        }
+    int k = kb + lane;
+    for (; k + LANES < ke; k += 2 * LANES) {
+        const VisitRaw<R> r0 = load_raw<R>(a, k);
+        const VisitRaw<R> r1 = load_raw<R>(a, k + LANES);
+        const V3<R> p01 = xyz(a.W[r0.i1]), p02 = xyz(a.W[r0.i2]), p03 = xyz(a.W[r0.i3]);
+        const V3<R> p11 = xyz(a.W[r1.i1]), p12 = xyz(a.W[r1.i2]), p13 = xyz(a.W[r1.i3]);
+        visit_accumulate<R, MODEL, SAFE>(q, r0, p01 - xi, p02 - xi, p03 - xi);
+        visit_accumulate<R, MODEL, SAFE>(q, r1, p11 - xi, p12 - xi, p13 - xi);
     }
+    if (k < ke) {
+        const VisitRaw<R> r0 = load_raw<R>(a, k);
+        visit_accumulate<R, MODEL, SAFE>(q, r0, xyz(a.W[r0.i1]) - xi, xyz(a.W[r0.i2]) - xi,
+                                         xyz(a.W[r0.i3]) - xi);
+    }
+    V3<R>& g = q.g;
+    R& S = q.S;
+    Sym<R>& Aw = q.Aw;
+    Sym<R>& Cm = q.Cm;
+    V3<R>& gw = q.gw;
+    Sym<R>& Kw = q.Kw;
+    R& E0 = q.E0;
+    R& E0a = q.E0a;
     if (WC) {
         for (int k = a.wvptr[v] + lane; k < a.wvptr[v + 1]; k += LANES) {
             const int cc = a.wv_c[k];
@@ -227,6 +297,38 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int 
     if (SAFE && ok) {
         const R u = sizeof(R) == 8 ? R(1.1102230246251565e-16) : R(5.9604644775390625e-08);
         R lin, quad;
+        // Corotated: for any rotation Q, mu |F' - R(F')|^2 <= mu |F' - Q|^2
+        // (R(F') is the closest rotation), so with Q = R(F) the local energy
+        // is majorised by a quadratic in x_i whose gradient is g and whose
+        // Hessian is the modified Hessian A (without planes).  The exact
+        // evaluation below runs only when this bound does not already show
+        // that the step decreases the energy.
+        bool bound_ok = false;
+        if (MODEL == kCor) {
+            Sym<R> Ab = Aw;
+            Ab.xx += R(2) * S;
+            Ab.yy += R(2) * S;
+            Ab.zz += R(2) * S;
+            const R bl = dot(gt, d), bq = dot(d, sym_mul(Ab, d));
+            R dE = bl + R(0.5) * bq;
+            R ab = abs_(bl) + abs_(R(0.5) * bq);
+            if (WC) {
+                for (int q2 = pb; q2 < pe; ++q2) {
+                    const R* pl = a.planes + 5 * q2;
+                    const V3<R> n = mk(pl[0], pl[1], pl[2]);
+                    const R phi0 = dot(n, xi) - pl[3];
+                    const R phi1 = phi0 + dot(n, d);
+                    const R e0 = phi0 < R(0) ? R(0.5) * pl[4] * phi0 * phi0 : R(0);
+                    const R e1 = phi1 < R(0) ? R(0.5) * pl[4] * phi1 * phi1 : R(0);
+                    // active planes are inside the quadratic; only the change
+                    // of the penalty beyond it counts here
+                    const R quad_pl = phi0 < R(0) ? R(0.5) * pl[4] * (phi1 * phi1 - phi0 * phi0) : R(0);
+                    dE += (e1 - e0) - quad_pl;
+                    ab += e0 + e1 + abs_(quad_pl);
+                }
+            }
+            bound_ok = dE <= R(8) * u * ab;
+        }
         if (MODEL == kNeo) {
             // Along x_i + alpha d the Neo-Hookean energy of the incident tets
             // is exactly quadratic: |F|^2 is quadratic and det F affine in x_i
@@ -244,7 +346,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int 
             quad = dot(d, sym_mul(Kw, d));
         }
         int h = 0;
-        for (;;) {
+        for (; !bound_ok;) {
             R dE = alpha * lin + R(0.5) * alpha * alpha * quad;
             R ab = abs_(alpha * lin) + abs_(R(0.5) * alpha * alpha * quad);
             if (WC) {
@@ -308,13 +410,13 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int 
     }
 }
 
-template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool WC>
+template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool GEN>
 static hipError_t launch_phase_t(const SweepArgs<R>& a, int vbeg, int vend, hipStream_t s)
 {
     const int64_t threads = int64_t(vend - vbeg) * LANES;
     if (threads <= 0) return hipSuccess;
     const int blocks = int((threads + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_phase<R, MODEL, LANES, ACCEL, SAFE, WC>), dim3(blocks), dim3(kBlock), 0,
+    hipLaunchKernelGGL((k_phase<R, MODEL, LANES, ACCEL, SAFE, GEN>), dim3(blocks), dim3(kBlock), 0,
                        s, a, vbeg, vend);
     return hipGetLastError();
 }
@@ -525,6 +627,34 @@ __device__ __forceinline__ V3<double> grad_of_slot(const TetGeo& G, int slot)
     return mk(r[0], r[1], r[2]);
 }
 
+// V0 P dN_j of a tet for its four vertices j (12 doubles, slot-major), so
+// that a vertex gathers 3 doubles per incident tet.
+__device__ __forceinline__ void store_slot_forces(double* o, const TetGeo& G, const Cols<double>& P)
+{
+#pragma unroll
+    for (int slot = 0; slot < 4; ++slot) {
+        const V3<double> f = G.V0 * apply(P, grad_of_slot(G, slot));
+        o[3 * slot] = f.x;
+        o[3 * slot + 1] = f.y;
+        o[3 * slot + 2] = f.z;
+    }
+}
+
+// sum over the visits of vertex v of the per-slot vectors in vp (rv = tet *
+// 4 + slot indexes them directly), in a fixed order
+template <class R>
+__device__ __forceinline__ V3<double> gather_vp(const ResArgs<R>& a, int v)
+{
+    V3<double> s = mk(0.0, 0.0, 0.0);
+    const int jb = a.rvptr[v], je = a.rvptr[v + 1];
+#pragma unroll 4
+    for (int j = jb; j < je; ++j) {
+        const double* o = a.vp + 3 * int64_t(a.rv[j]);
+        s = s + mk(o[0], o[1], o[2]);
+    }
+    return s;
+}
+
 template <class R>
 __device__ __forceinline__ Cols<double> tet_F(const ResArgs<R>& a, int4 t, const TetGeo& G)
 {
@@ -561,26 +691,8 @@ __global__ __launch_bounds__(kBlock) void k_tet_stress(ResArgs<R> a)
         P.c2 = (2.0 * G.mu) * (F.c2 - Rm.c2) + w * C.c2;
         psi = corot_energy(pol, J, G.mu, G.lam);
     }
-    double* o = a.vp + 9 * int64_t(e);
-    o[0] = G.V0 * P.c0.x; o[1] = G.V0 * P.c0.y; o[2] = G.V0 * P.c0.z;
-    o[3] = G.V0 * P.c1.x; o[4] = G.V0 * P.c1.y; o[5] = G.V0 * P.c1.z;
-    o[6] = G.V0 * P.c2.x; o[7] = G.V0 * P.c2.y; o[8] = G.V0 * P.c2.z;
+    store_slot_forces(a.vp + 12 * int64_t(e), G, P);
     a.ebuf[a.tet_eidx[e]] = G.V0 * psi;
-}
-
-// sum over visits of (per-tet 3x3 in vp, by columns) times dN_slot
-template <class R>
-__device__ __forceinline__ V3<double> gather_vp(const ResArgs<R>& a, int v)
-{
-    V3<double> s = mk(0.0, 0.0, 0.0);
-    for (int j = a.rvptr[v]; j < a.rvptr[v + 1]; ++j) {
-        const int e = a.rv[j] >> 2, slot = a.rv[j] & 3;
-        const V3<double> g = grad_of_slot(a.geo[e], slot);
-        const double* o = a.vp + 9 * int64_t(e);
-        s = s + comb(mk(o[0], o[1], o[2]), g.x, mk(o[3], o[4], o[5]), g.y, mk(o[6], o[7], o[8]),
-                     g.z);
-    }
-    return s;
 }
 
 template <class R>
@@ -688,10 +800,7 @@ __global__ __launch_bounds__(kBlock) void k_tet_adjoint(ResArgs<R> a,
     dP.c0 = G.mu * Lm.c0 + (lh * cofL) * C.c0 + qq * (cross(Lm.c1, F.c2) + cross(F.c1, Lm.c2));
     dP.c1 = G.mu * Lm.c1 + (lh * cofL) * C.c1 + qq * (cross(Lm.c2, F.c0) + cross(F.c2, Lm.c0));
     dP.c2 = G.mu * Lm.c2 + (lh * cofL) * C.c2 + qq * (cross(Lm.c0, F.c1) + cross(F.c0, Lm.c1));
-    double* o = a.vp + 9 * int64_t(e);
-    o[0] = G.V0 * dP.c0.x; o[1] = G.V0 * dP.c0.y; o[2] = G.V0 * dP.c0.z;
-    o[3] = G.V0 * dP.c1.x; o[4] = G.V0 * dP.c1.y; o[5] = G.V0 * dP.c1.z;
-    o[6] = G.V0 * dP.c2.x; o[7] = G.V0 * dP.c2.y; o[8] = G.V0 * dP.c2.z;
+    store_slot_forces(a.vp + 12 * int64_t(e), G, dP);
     // dP/dmu = F + (J - 2) cof F, dP/dlambda = (J - 1) cof F
     if (dmu) dmu[e] = -G.V0 * (FL + (J - 2.0) * cofL);
     if (dlam) dlam[e] = -G.V0 * (J - 1.0) * cofL;

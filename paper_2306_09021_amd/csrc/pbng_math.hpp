@@ -38,9 +38,13 @@ __device__ __forceinline__ V3<R> comb(V3<R> a, R s, V3<R> b, R t, V3<R> c, R u)
     return {a.x * s + b.x * t + c.x * u, a.y * s + b.y * t + c.y * u, a.z * s + b.z * t + c.z * u};
 }
 
+// Single-instruction reciprocal, reciprocal square root and square root in
+// float (about 1 ulp); correctly rounded operations in double.
 __device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
 __device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
-__device__ __forceinline__ float sqrt_(float x) { return __builtin_sqrtf(x); }
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float sqrt_(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double sqrt_(double x) { return sqrt(x); }
 __device__ __forceinline__ float abs_(float x) { return __builtin_fabsf(x); }
 __device__ __forceinline__ double abs_(double x) { return fabs(x); }
@@ -160,9 +164,16 @@ template <class R>
 __device__ __forceinline__ void jacobi_rot(R& app, R& aqq, R& apq, R& arp, R& arq, V3<R>& vp,
                                            V3<R>& vq)
 {
-    if (apq == R(0)) return;
-    R tau = (aqq - app) / (R(2) * apq);
-    R t = (tau >= R(0) ? R(1) : R(-1)) / (abs_(tau) + sqrt_(R(1) + tau * tau));
+    // Rotation angle from cot(2 theta) = (aqq - app) / (2 apq), written as
+    // t = tan(theta) = sgn(d) h / (|d| + sqrt(d^2 + h^2)), d = aqq - app,
+    // h = 2 apq: no division by a small apq.  Off-diagonal entries below
+    // working precision relative to the diagonal are left alone.
+    constexpr bool dbl = sizeof(R) == 8;
+    const R rel = dbl ? R(1e-22) : R(1e-12);
+    const R tiny = dbl ? R(1e-150) : R(1e-18);
+    if (!(abs_(apq) > rel * (abs_(app) + abs_(aqq))) || !(abs_(apq) > tiny)) return;
+    const R d = aqq - app, h = R(2) * apq;
+    R t = (d >= R(0) ? h : -h) * rcp(abs_(d) + sqrt_(d * d + h * h));
     R c = rsq(R(1) + t * t);
     R s = t * c;
     app -= t * apq;

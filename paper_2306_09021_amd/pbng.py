@@ -15,7 +15,7 @@ from typing import List, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpbng.so")
+LIB_PATH = os.environ.get("PBNG_LIBRARY") or os.path.join(_HERE, "libpbng.so")
 
 OK, NOT_CONVERGED = 0, 1
 ERRORS = {-1: "EINVAL", -2: "EMESH", -3: "EMATERIAL", -4: "ECOLOR", -5: "ENAN", -6: "EHIP",
