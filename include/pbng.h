@@ -24,9 +24,10 @@
  *    device allocations on the current device (e.g. torch cuda tensors).
  *  - The caller owns every buffer it passes.  The library keeps no caller
  *    pointer after a call returns; a workspace copies what it needs.
- *  - Positions are row-major [n][3] arrays of the workspace's real type
- *    (float for PBNG_F32, double for PBNG_F64), in the caller's vertex
- *    order; batched problems are concatenated instance after instance.
+ *  - Positions are row-major [n][3] arrays of the workspace's position type
+ *    (float for PBNG_F32, double for PBNG_F64 and PBNG_MIXED), in the
+ *    caller's vertex order; batched problems are concatenated instance
+ *    after instance.
  *  - hip_stream may be NULL (the null stream).  Calls that return host
  *    results (stats, norms) synchronise that stream before returning.
  */
@@ -59,8 +60,11 @@ extern "C" {
 #define PBNG_NEOHOOKEAN 0   /* Eq. nh: 1/2 mu |F|^2 + lhat/2 (J - 1 - mu/lhat)^2, lhat = mu + lambda */
 #define PBNG_COROTATED 1    /* Eq. cor: mu |F - R(F)|^2 + lambda/2 (J - 1)^2 */
 
-#define PBNG_F32 0
-#define PBNG_F64 1
+#define PBNG_F32 0    /* positions and sweep arithmetic in float             */
+#define PBNG_F64 1    /* positions and sweep arithmetic in double            */
+#define PBNG_MIXED 2  /* positions in double (an FP64 master copy of the    */
+                      /* iterate), sweep arithmetic in float on edge vectors */
+                      /* x_j - x_i formed in double                          */
 
 #define PBNG_ACCEL_NONE 0
 #define PBNG_ACCEL_CHEBYSHEV 1  /* x^{l+1} = w_{l+1}(gamma (x_P - x^l) + x^l - x^{l-1}) + x^{l-1} */
@@ -224,8 +228,8 @@ int32_t pbng_color(const pbng_problem* p, int32_t* colors_out, int32_t* n_colors
  * vertex order and per-visit records.  colors (host, concatenated
  * [sum n_verts], -1 on Dirichlet vertices) may be NULL to colour with
  * pbng_color; a supplied colouring is checked (no two same-coloured
- * vertices may share a tet or weak constraint).  real = PBNG_F32 or
- * PBNG_F64 selects the sweep arithmetic and the type of position buffers.
+ * vertices may share a tet or weak constraint).  real = PBNG_F32, PBNG_F64
+ * or PBNG_MIXED selects the sweep arithmetic and the position type.
  * Allocates device memory on the current device; *ws_out receives the
  * handle.  Errors: PBNG_EINVAL, PBNG_EMESH, PBNG_EMATERIAL, PBNG_ECOLOR,
  * PBNG_ENAN, PBNG_EHIP, PBNG_ENOMEM.

@@ -12,7 +12,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpbng.so")
-SOURCES = ["pbng_kernels.hip", "pbng_host.cpp"]
+# (source, extra defines, object name): the kernel file is compiled once per
+# instantiation set, in parallel
+UNITS = [("pbng_kernels.hip", ["-DPBNG_KERNEL_SET=0"], "kernels_f32.o"),
+         ("pbng_kernels.hip", ["-DPBNG_KERNEL_SET=1"], "kernels_f64.o"),
+         ("pbng_kernels.hip", ["-DPBNG_KERNEL_SET=2"], "kernels_mixed.o"),
+         ("pbng_host.cpp", [], "host.o")]
 ARCH = os.environ.get("PBNG_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -33,18 +38,22 @@ def _run(cmd):
 def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
     """Compile every source and link libpbng.so (or `out`); always
     recompiles.  `extra` adds compiler flags (e.g. -D switches)."""
+    from concurrent.futures import ThreadPoolExecutor
     objs = []
+    cmds = []
     bdir = os.path.join(HERE, "_build", os.path.basename(out))
     os.makedirs(bdir, exist_ok=True)
-    for src in SOURCES:
-        obj = os.path.join(bdir, src + ".o")
+    for src, defs, oname in UNITS:
+        obj = os.path.join(bdir, oname)
         cmd = ["hipcc", "-c"] + (["-x", "hip"] if src.endswith(".hip") else [])
-        cmd += [os.path.join(CSRC, src), "-o", obj] + COMMON + list(extra)
+        cmd += [os.path.join(CSRC, src), "-o", obj] + COMMON + defs + list(extra)
         cmd += DEVICE if src.endswith(".hip") else ["-D__HIP_PLATFORM_AMD__"]
-        log = _run(cmd)
-        if verbose and log.strip():
-            print(log)
+        cmds.append(cmd)
         objs.append(obj)
+    with ThreadPoolExecutor(max_workers=min(4, os.cpu_count() or 1)) as ex:
+        for log in ex.map(_run, cmds):
+            if verbose and log.strip():
+                print(log)
     tmp = out + ".tmp%d" % os.getpid()
     _run(["hipcc", "-shared", "-o", tmp] + objs + DEVICE + ["-lamdhip64"])
     os.replace(tmp, out)

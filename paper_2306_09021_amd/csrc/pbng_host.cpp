@@ -367,8 +367,11 @@ struct pbng_workspace {
         if (hbuf) (void)hipHostFree(hbuf);
         if (hact) (void)hipHostFree(hact);
     }
-    size_t r4() const { return real == PBNG_F64 ? 32 : 16; }
-    size_t rs() const { return real == PBNG_F64 ? 8 : 4; }
+    // positions in FP64 (PBNG_F64, PBNG_MIXED); sweep arithmetic in FP64
+    // only for PBNG_F64
+    bool pos64() const { return real != PBNG_F32; }
+    bool math64() const { return real == PBNG_F64; }
+    size_t r4() const { return pos64() ? 32 : 16; }
 };
 
 namespace {
@@ -667,9 +670,12 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
 
     // upload (the first HIP call: everything above is host-side validation and packing)
     hipchk(hipGetDevice(&ws->device), "hipGetDevice");
-    const bool f64 = ws->real == PBNG_F64;
     auto upR = [&](Dev& d, const std::vector<double>& v) {
-        if (f64) upload_real<double>(d, v);
+        if (ws->math64()) upload_real<double>(d, v);
+        else upload_real<float>(d, v);
+    };
+    auto upP = [&](Dev& d, const std::vector<double>& v) {
+        if (ws->pos64()) upload_real<double>(d, v);
         else upload_real<float>(d, v);
     };
     std::vector<int> vptr_free(rvptr.begin(), rvptr.begin() + nfree + 1);
@@ -712,7 +718,7 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     ws->planes64.upload(planes);
     ws->orig_of.upload(orig_of);
     ws->rsq.alloc(std::max<int64_t>(1, nv) * sizeof(double));
-    upR(ws->xd_int, xd_int);
+    upP(ws->xd_int, xd_int);
     ws->dir_internal.upload(dir_internal);
     ws->dir_pos.upload(dir_pos);
     ws->plan_r = make_plan(seg_r, ws->seg_r_cb, ws->seg_r_ce, ws->seg_r_q, ws->seg_r_part);
@@ -726,14 +732,15 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     hipchk(hipDeviceSynchronize(), "upload");
 }
 
-template <class R>
-SweepArgs<R> sweep_args(pbng_workspace* ws, double omega, double gamma, int max_halvings)
+template <class R, class PR>
+SweepArgs<R, PR> sweep_args(pbng_workspace* ws, double omega, double gamma, int max_halvings)
 {
     using R4 = typename R4t<R>::T;
-    SweepArgs<R> a;
-    a.W = ws->W.as<R4>();
-    a.P = ws->P.as<R4>();
-    a.N = ws->N.as<R4>();
+    using P4 = typename R4t<PR>::T;
+    SweepArgs<R, PR> a;
+    a.W = ws->W.as<P4>();
+    a.P = ws->P.as<P4>();
+    a.N = ws->N.as<P4>();
     a.vptr = ws->vptr.as<int>();
     a.j1 = ws->j1.as<int>();
     a.j2 = ws->j2.as<int>();
@@ -755,8 +762,8 @@ SweepArgs<R> sweep_args(pbng_workspace* ws, double omega, double gamma, int max_
     a.plane_ptr = ws->plane_ptr.as<int>();
     a.planes = ws->planes.as<R>();
     a.rejected = ws->rejected.as<int>();
-    a.omega = R(omega);
-    a.gamma = R(gamma);
+    a.omega = PR(omega);
+    a.gamma = PR(gamma);
     a.max_halvings = max_halvings;
     return a;
 }
@@ -846,50 +853,49 @@ double chebyshev_next(int64_t l, double rho, double prev)
     return 4.0 / (4.0 - rho * rho * prev);
 }
 
-template <class R>
 void ensure_ring(pbng_workspace* ws)
 {
     if (!ws->P.p) ws->P.alloc(ws->nv * ws->r4());
     if (!ws->N.p) ws->N.alloc(ws->nv * ws->r4());
 }
 
-template <class R>
+template <class R, class PR>
 void launch_sweep(pbng_workspace* ws, const pbng_solve_opts* o, double omega, double gamma, hipStream_t s)
 {
     const bool accel = o->accel != PBNG_ACCEL_NONE;
-    const SweepArgs<R> a = sweep_args<R>(ws, omega, gamma, o->max_halvings);
+    const SweepArgs<R, PR> a = sweep_args<R, PR>(ws, omega, gamma, o->max_halvings);
     for (int c = 0; c < ws->ncol; ++c)
-        hipchk(launch_phase<R>(a, ws->model, pick_lanes(ws, o->lanes, c), accel,
+        hipchk(launch_phase<R, PR>(a, ws->model, pick_lanes(ws, o->lanes, c), accel,
                                o->safeguard == PBNG_SAFEGUARD_BACKTRACK, ws->general(), ws->col_ptr[c],
                                ws->col_ptr[c + 1], s),
                "sweep launch");
     if (accel) std::swap(ws->W.p, ws->N.p);
 }
 
-template <class R>
+template <class R, class PR>
 int32_t solve_t(pbng_workspace* ws, void* x, const pbng_solve_opts* o, pbng_stats* st, hipStream_t s)
 {
-    using R4 = typename R4t<R>::T;
+    using R4 = typename R4t<PR>::T;
     const int n = ws->n_inst;
     const bool accel = o->accel != PBNG_ACCEL_NONE;
     pick_lanes(ws, o->lanes, 0);
-    if (accel) ensure_ring<R>(ws);
+    if (accel) ensure_ring(ws);
     const bool resume = o->resume && ws->ring_valid;
     if (!resume) {
-        hipchk(launch_load<R>(static_cast<const R*>(x), ws->orig_of.as<int>(), ws->xd_int.as<R4>(),
+        hipchk(launch_load<PR>(static_cast<const PR*>(x), ws->orig_of.as<int>(), ws->xd_int.as<R4>(),
                               ws->W.as<R4>(), accel ? ws->P.as<R4>() : nullptr,
                               accel ? ws->N.as<R4>() : nullptr, int(ws->nfree), int(ws->nv), s),
                "load");
         ws->sweep_l = 0;
         ws->omega_l = 1.0;
     } else {
-        hipchk(launch_load<R>(static_cast<const R*>(x), ws->orig_of.as<int>(), ws->xd_int.as<R4>(),
+        hipchk(launch_load<PR>(static_cast<const PR*>(x), ws->orig_of.as<int>(), ws->xd_int.as<R4>(),
                               ws->W.as<R4>(), nullptr, nullptr, int(ws->nfree), int(ws->nv), s),
                "load");
     }
     ws->ring_valid = accel;
     hipchk(hipMemsetAsync(ws->rejected.p, 0, n * sizeof(int), s), "memset");
-    residual_internal<R>(ws, ws->W.p, nullptr, s);
+    residual_internal<PR>(ws, ws->W.p, nullptr, s);
     std::vector<double> r0(ws->hbuf, ws->hbuf + n), rr(r0), en(ws->hbuf + n, ws->hbuf + 2 * n);
     std::vector<int> act(n, 1), sweeps(n, 0), conv(n, 0);
     std::vector<double> ttol(n, -1.0);
@@ -919,12 +925,12 @@ int32_t solve_t(pbng_workspace* ws, void* x, const pbng_solve_opts* o, pbng_stat
         } else if (o->accel == PBNG_ACCEL_SOR) {
             omega = o->omega;
         }
-        launch_sweep<R>(ws, o, omega, gamma, s);
+        launch_sweep<R, PR>(ws, o, omega, gamma, s);
         ws->omega_l = omega;
         ws->sweep_l++;
         for (int q = 0; q < n; ++q) sweeps[q] += act[q];
         if ((sw + 1) % o->check_every == 0 || sw + 1 == o->max_sweeps) {
-            residual_internal<R>(ws, ws->W.p, nullptr, s);
+            residual_internal<PR>(ws, ws->W.p, nullptr, s);
             const double t = now_ms() - t0;
             bool changed = false;
             for (int q = 0; q < n; ++q) {
@@ -951,7 +957,7 @@ int32_t solve_t(pbng_workspace* ws, void* x, const pbng_solve_opts* o, pbng_stat
             }
         }
     }
-    hipchk(launch_store<R>(ws->W.as<R4>(), ws->orig_of.as<int>(), static_cast<R*>(x), int(ws->nv), s), "store");
+    hipchk(launch_store<PR>(ws->W.as<R4>(), ws->orig_of.as<int>(), static_cast<PR*>(x), int(ws->nv), s), "store");
     std::vector<int> rej(n);
     hipchk(hipMemcpyAsync(rej.data(), ws->rejected.p, n * sizeof(int), hipMemcpyDeviceToHost, s), "d2h");
     hipchk(hipStreamSynchronize(s), "sync");
@@ -977,16 +983,16 @@ int32_t solve_t(pbng_workspace* ws, void* x, const pbng_solve_opts* o, pbng_stat
     return all ? PBNG_OK : PBNG_NOT_CONVERGED;
 }
 
-template <class R>
-AdjArgs<R> adj_args(pbng_workspace* ws, double omega, double gamma)
+template <class R, class PR>
+AdjArgs<R, PR> adj_args(pbng_workspace* ws, double omega, double gamma)
 {
-    using R4 = typename R4t<R>::T;
-    AdjArgs<R> a;
-    a.X = ws->Wres.as<R4>();
-    a.L = ws->L.as<R4>();
-    a.P = ws->LP.as<R4>();
-    a.N = ws->LN.as<R4>();
-    a.B = ws->B.as<R4>();
+    using P4 = typename R4t<PR>::T;
+    AdjArgs<R, PR> a;
+    a.X = ws->Wres.as<P4>();
+    a.L = ws->L.as<P4>();
+    a.P = ws->LP.as<P4>();
+    a.N = ws->LN.as<P4>();
+    a.B = ws->B.as<P4>();
     a.vptr = ws->vptr.as<int>();
     a.j1 = ws->j1.as<int>();
     a.j2 = ws->j2.as<int>();
@@ -1005,8 +1011,8 @@ AdjArgs<R> adj_args(pbng_workspace* ws, double omega, double gamma)
     a.wc_K = ws->wc_K.as<R>();
     a.plane_ptr = ws->plane_ptr.as<int>();
     a.planes = ws->planes.as<R>();
-    a.omega = R(omega);
-    a.gamma = R(gamma);
+    a.omega = PR(omega);
+    a.gamma = PR(gamma);
     return a;
 }
 
@@ -1024,12 +1030,12 @@ void adjoint_check(pbng_workspace* ws, double* dmu, double* dlam, double* dxd, h
     for (int q = 0; q < ws->n_inst; ++q) ws->hbuf[q] = std::sqrt(ws->hbuf[q]);
 }
 
-template <class R>
+template <class R, class PR>
 int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double* dxd, double* dmu,
                   double* dlam, double* lam_out, const pbng_adjoint_opts* o, pbng_stats* st,
                   hipStream_t s)
 {
-    using R4 = typename R4t<R>::T;
+    using R4 = typename R4t<PR>::T;
     const int n = ws->n_inst;
     const bool accel = o->accel == PBNG_ACCEL_CHEBYSHEV;
     pick_lanes(ws, o->lanes, 0);
@@ -1039,10 +1045,10 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
         if (!ws->LP.p) ws->LP.alloc(ws->nv * ws->r4());
         if (!ws->LN.p) ws->LN.alloc(ws->nv * ws->r4());
     }
-    hipchk(launch_load<R>(static_cast<const R*>(x_eq), ws->orig_of.as<int>(), nullptr, ws->Wres.as<R4>(), nullptr,
+    hipchk(launch_load<PR>(static_cast<const PR*>(x_eq), ws->orig_of.as<int>(), nullptr, ws->Wres.as<R4>(), nullptr,
                           nullptr, int(ws->nfree), int(ws->nv), s),
            "load");
-    hipchk(launch_load_vec<R>(static_cast<const R*>(dLdx), ws->orig_of.as<int>(), ws->B.as<R4>(), int(ws->nfree),
+    hipchk(launch_load_vec<PR>(static_cast<const PR*>(dLdx), ws->orig_of.as<int>(), ws->B.as<R4>(), int(ws->nfree),
                               int(ws->nv), s),
            "load");
     hipchk(hipMemsetAsync(ws->L.p, 0, ws->nv * ws->r4(), s), "memset");
@@ -1050,7 +1056,7 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
         hipchk(hipMemsetAsync(ws->LP.p, 0, ws->nv * ws->r4(), s), "memset");
         hipchk(hipMemsetAsync(ws->LN.p, 0, ws->nv * ws->r4(), s), "memset");
     }
-    adjoint_check<R>(ws, nullptr, nullptr, nullptr, s);
+    adjoint_check<PR>(ws, nullptr, nullptr, nullptr, s);
     std::vector<double> b0(ws->hbuf, ws->hbuf + n), rr(b0);
     std::vector<int> act(n, 1), sweeps(n, 0), conv(n, 0);
     int n_active = 0;
@@ -1068,15 +1074,15 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
         double omega = 1.0;
         if (accel) omega = chebyshev_next(sw, o->rho, omega_prev);
         omega_prev = omega;
-        const AdjArgs<R> a = adj_args<R>(ws, omega, accel ? o->gamma : 1.0);
+        const AdjArgs<R, PR> a = adj_args<R, PR>(ws, omega, accel ? o->gamma : 1.0);
         for (int c = 0; c < ws->ncol; ++c)
-            hipchk(launch_adjoint_phase<R>(a, pick_lanes(ws, o->lanes, c), accel, ws->any_wc, ws->col_ptr[c],
+            hipchk(launch_adjoint_phase<R, PR>(a, pick_lanes(ws, o->lanes, c), accel, ws->any_wc, ws->col_ptr[c],
                                            ws->col_ptr[c + 1], s),
                    "adjoint launch");
         if (accel) std::swap(ws->L.p, ws->LN.p);
         for (int q = 0; q < n; ++q) sweeps[q] += act[q];
         if ((sw + 1) % o->check_every == 0 || sw + 1 == o->max_sweeps) {
-            adjoint_check<R>(ws, nullptr, nullptr, nullptr, s);
+            adjoint_check<PR>(ws, nullptr, nullptr, nullptr, s);
             n_active = 0;
             for (int q = 0; q < n; ++q) {
                 if (!act[q]) continue;
@@ -1091,10 +1097,10 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
         }
     }
     // final assembly with the gradients
-    adjoint_check<R>(ws, dmu, dlam, dxd, s);
+    adjoint_check<PR>(ws, dmu, dlam, dxd, s);
     for (int q = 0; q < n; ++q) rr[q] = ws->hbuf[q];
     if (lam_out)
-        hipchk(launch_store64<R>(ws->L.as<R4>(), ws->orig_of.as<int>(), lam_out, int(ws->nv), s), "store");
+        hipchk(launch_store64<PR>(ws->L.as<R4>(), ws->orig_of.as<int>(), lam_out, int(ws->nv), s), "store");
     hipchk(hipStreamSynchronize(s), "sync");
     const double t_all = now_ms() - t0;
     bool all = true;
@@ -1208,7 +1214,8 @@ int32_t pbng_workspace_create(const pbng_problem* p, int32_t n_problems, const i
 {
     return guard([&] {
         if (!p || !ws_out || n_problems <= 0) fail(PBNG_EINVAL, "null argument or n_problems <= 0");
-        if (real != PBNG_F32 && real != PBNG_F64) fail(PBNG_EINVAL, "real must be PBNG_F32 or PBNG_F64");
+        if (real != PBNG_F32 && real != PBNG_F64 && real != PBNG_MIXED)
+            fail(PBNG_EINVAL, "real must be PBNG_F32, PBNG_F64 or PBNG_MIXED");
         *ws_out = nullptr;
         pbng_workspace* ws = new pbng_workspace;
         ws->real = real;
@@ -1253,7 +1260,7 @@ int32_t pbng_workspace_set_materials(pbng_workspace* ws, const double* mu_dev, c
         check_ws(ws);
         if (!mu_dev || !lambda_dev) fail(PBNG_EINVAL, "null material arrays");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        if (ws->real == PBNG_F64)
+        if (ws->math64())
             hipchk(launch_set_materials<double>(mu_dev, lambda_dev, ws->geo.as<TetGeo>(), int(ws->nt), ws->rv.as<int>(),
                                                 int(ws->nvis), ws->vmu.as<double>(), ws->vlam.as<double>(), s),
                    "set materials");
@@ -1271,7 +1278,7 @@ int32_t pbng_workspace_set_dirichlet(pbng_workspace* ws, const double* xd_dev, v
         check_ws(ws);
         if (ws->nd > 0 && !xd_dev) fail(PBNG_EINVAL, "null Dirichlet array");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        if (ws->real == PBNG_F64)
+        if (ws->pos64())
             hipchk(launch_set_dirichlet<double>(xd_dev, ws->dir_internal.as<int>(), ws->nd, int(ws->nfree),
                                                 ws->xd_int.as<double4>(), s),
                    "set dirichlet");
@@ -1291,8 +1298,9 @@ int32_t pbng_solve(pbng_workspace* ws, void* x_inout, const pbng_solve_opts* o, 
         if (!x_inout) fail(PBNG_EINVAL, "x_inout is null");
         check_solve_opts(o);
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        return ws->real == PBNG_F64 ? solve_t<double>(ws, x_inout, o, stats, s)
-                                    : solve_t<float>(ws, x_inout, o, stats, s);
+        if (ws->real == PBNG_F64) return solve_t<double, double>(ws, x_inout, o, stats, s);
+        if (ws->real == PBNG_MIXED) return solve_t<float, double>(ws, x_inout, o, stats, s);
+        return solve_t<float, float>(ws, x_inout, o, stats, s);
     });
 }
 
@@ -1303,7 +1311,7 @@ int32_t pbng_residual(pbng_workspace* ws, const void* x, double* res_norm, doubl
         check_ws(ws);
         if (!x) fail(PBNG_EINVAL, "x is null");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        if (ws->real == PBNG_F64) {
+        if (ws->pos64()) {
             hipchk(launch_load<double>(static_cast<const double*>(x), ws->orig_of.as<int>(), nullptr,
                                        ws->Wres.as<double4>(), nullptr, nullptr, int(ws->nfree), int(ws->nv), s),
                    "load");
@@ -1336,9 +1344,11 @@ int32_t pbng_adjoint(pbng_workspace* ws, const void* x_eq, const void* dL_dx, do
         if (o->accel == PBNG_ACCEL_CHEBYSHEV && !(o->rho > 0 && o->rho < 1 && o->gamma > 0))
             fail(PBNG_EINVAL, "Chebyshev needs 0 < rho < 1 and gamma > 0");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        return ws->real == PBNG_F64
-                   ? adjoint_t<double>(ws, x_eq, dL_dx, dL_dxD, dL_dmu, dL_dlambda, lam_out, o, stats, s)
-                   : adjoint_t<float>(ws, x_eq, dL_dx, dL_dxD, dL_dmu, dL_dlambda, lam_out, o, stats, s);
+        if (ws->real == PBNG_F64)
+            return adjoint_t<double, double>(ws, x_eq, dL_dx, dL_dxD, dL_dmu, dL_dlambda, lam_out, o, stats, s);
+        if (ws->real == PBNG_MIXED)
+            return adjoint_t<float, double>(ws, x_eq, dL_dx, dL_dxD, dL_dmu, dL_dlambda, lam_out, o, stats, s);
+        return adjoint_t<float, float>(ws, x_eq, dL_dx, dL_dxD, dL_dmu, dL_dlambda, lam_out, o, stats, s);
     });
 }
 
@@ -1348,9 +1358,8 @@ int32_t pbng_load(pbng_workspace* ws, const void* x, void* hip_stream)
         check_ws(ws);
         if (!x) fail(PBNG_EINVAL, "x is null");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        if (!ws->P.p) ws->P.alloc(ws->nv * ws->r4());
-        if (!ws->N.p) ws->N.alloc(ws->nv * ws->r4());
-        if (ws->real == PBNG_F64)
+        ensure_ring(ws);
+        if (ws->pos64())
             hipchk(launch_load<double>(static_cast<const double*>(x), ws->orig_of.as<int>(), ws->xd_int.as<double4>(),
                                        ws->W.as<double4>(), ws->P.as<double4>(), ws->N.as<double4>(),
                                        int(ws->nfree), int(ws->nv), s),
@@ -1377,7 +1386,7 @@ int32_t pbng_store(pbng_workspace* ws, void* x, void* hip_stream)
         check_ws(ws);
         if (!x) fail(PBNG_EINVAL, "x is null");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        if (ws->real == PBNG_F64)
+        if (ws->pos64())
             hipchk(launch_store<double>(ws->W.as<double4>(), ws->orig_of.as<int>(), static_cast<double*>(x),
                                         int(ws->nv), s),
                    "store");
@@ -1405,8 +1414,9 @@ int32_t pbng_sweeps(pbng_workspace* ws, int32_t n_sweeps, const pbng_solve_opts*
             } else if (o->accel == PBNG_ACCEL_SOR) {
                 omega = o->omega;
             }
-            if (ws->real == PBNG_F64) launch_sweep<double>(ws, o, omega, gamma, s);
-            else launch_sweep<float>(ws, o, omega, gamma, s);
+            if (ws->real == PBNG_F64) launch_sweep<double, double>(ws, o, omega, gamma, s);
+            else if (ws->real == PBNG_MIXED) launch_sweep<float, double>(ws, o, omega, gamma, s);
+            else launch_sweep<float, float>(ws, o, omega, gamma, s);
             ws->omega_l = omega;
             ws->sweep_l++;
         }
@@ -1427,13 +1437,18 @@ int32_t pbng_phase(pbng_workspace* ws, int32_t color, const pbng_solve_opts* o, 
         const bool accel = o->accel != PBNG_ACCEL_NONE;
         // with acceleration the phase blends with omega = 1 and gamma = 1 and
         // does not advance the ring (measurement of the fused kernel only)
+        const int c0 = ws->col_ptr[color], c1 = ws->col_ptr[color + 1];
         if (ws->real == PBNG_F64)
-            hipchk(launch_phase<double>(sweep_args<double>(ws, 1.0, 1.0, o->max_halvings), ws->model, lanes, accel,
-                                        safe, ws->general(), ws->col_ptr[color], ws->col_ptr[color + 1], s),
+            hipchk(launch_phase<double, double>(sweep_args<double, double>(ws, 1.0, 1.0, o->max_halvings),
+                                                ws->model, lanes, accel, safe, ws->general(), c0, c1, s),
+                   "phase");
+        else if (ws->real == PBNG_MIXED)
+            hipchk(launch_phase<float, double>(sweep_args<float, double>(ws, 1.0, 1.0, o->max_halvings),
+                                               ws->model, lanes, accel, safe, ws->general(), c0, c1, s),
                    "phase");
         else
-            hipchk(launch_phase<float>(sweep_args<float>(ws, 1.0, 1.0, o->max_halvings), ws->model, lanes, accel,
-                                       safe, ws->general(), ws->col_ptr[color], ws->col_ptr[color + 1], s),
+            hipchk(launch_phase<float, float>(sweep_args<float, float>(ws, 1.0, 1.0, o->max_halvings),
+                                              ws->model, lanes, accel, safe, ws->general(), c0, c1, s),
                    "phase");
         return PBNG_OK;
     });

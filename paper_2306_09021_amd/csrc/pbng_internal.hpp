@@ -39,12 +39,15 @@ struct TetGeo {
     double V0, mu, lam;
 };
 
-template <class R>
+// R: arithmetic type of the sweep; PR: type of the stored positions (PR =
+// double with R = float keeps an FP64 master copy of the iterate).
+template <class R, class PR = R>
 struct SweepArgs {
     using R4 = typename R4t<R>::T;
-    R4* W;                 // working iterate (Gauss-Seidel, in place)
-    R4* P;                 // x^{l-1}                (acceleration only)
-    R4* N;                 // x^{l+1} being blended  (acceleration only)
+    using P4 = typename R4t<PR>::T;
+    P4* W;                 // working iterate (Gauss-Seidel, in place)
+    P4* P;                 // x^{l-1}                (acceleration only)
+    P4* N;                 // x^{l+1} being blended  (acceleration only)
     const int* vptr;       // [n_free + 1]
     const int* j1;
     const int* j2;
@@ -66,7 +69,7 @@ struct SweepArgs {
     const int* plane_ptr;  // [n_inst + 1]
     const R* planes;       // [n_planes][5]
     int* rejected;         // [n_inst]
-    R omega, gamma;
+    PR omega, gamma;
     int max_halvings;
 };
 
@@ -118,8 +121,8 @@ struct SegPlan {
 // launch_load: free vertices from the caller array, Dirichlet vertices from
 // xd_int (or, when xd_int is null, also from the caller array).
 // gen: the general variant (batched instances, weak constraints, planes)
-template <class R>
-hipError_t launch_phase(const SweepArgs<R>& a, int model, int lanes, bool accel, bool safe,
+template <class R, class PR>
+hipError_t launch_phase(const SweepArgs<R, PR>& a, int model, int lanes, bool accel, bool safe,
                         bool gen, int vbeg, int vend, hipStream_t s);
 template <class R>
 hipError_t launch_load(const R* x_user, const int* orig_of, const typename R4t<R>::T* xd_int,
@@ -155,14 +158,14 @@ hipError_t launch_load_vec(const R* v_user, const int* orig_of, typename R4t<R>:
 
 // Adjoint block Gauss-Seidel phase: L holds lambda (internal order), B the
 // right-hand side dL/dx (internal order, free vertices), X the equilibrium.
-template <class R>
+template <class R, class PR = R>
 struct AdjArgs {
-    using R4 = typename R4t<R>::T;
-    const R4* X;
-    R4* L;                 // working adjoint iterate
-    R4* P;                 // previous (acceleration)
-    R4* N;                 // next (acceleration)
-    const R4* B;
+    using P4 = typename R4t<PR>::T;
+    const P4* X;
+    P4* L;                 // working adjoint iterate
+    P4* P;                 // previous (acceleration)
+    P4* N;                 // next (acceleration)
+    const P4* B;
     const int* vptr;
     const int* j1;
     const int* j2;
@@ -181,10 +184,10 @@ struct AdjArgs {
     const R* wc_K;
     const int* plane_ptr;
     const R* planes;
-    R omega, gamma;
+    PR omega, gamma;
 };
-template <class R>
-hipError_t launch_adjoint_phase(const AdjArgs<R>& a, int lanes, bool accel, bool wc, int vbeg,
+template <class R, class PR>
+hipError_t launch_adjoint_phase(const AdjArgs<R, PR>& a, int lanes, bool accel, bool wc, int vbeg,
                                 int vend, hipStream_t s);
 
 }  // namespace pbng

@@ -14,6 +14,10 @@
 #include "pbng_internal.hpp"
 #include "pbng_math.hpp"
 
+#ifndef PBNG_KERNEL_SET
+#define PBNG_KERNEL_SET 0
+#endif
+
 namespace pbng {
 
 constexpr int kNeo = 0;
@@ -86,10 +90,32 @@ __device__ __forceinline__ V3<R> symK_mul(const R* K, V3<R> v)
             K[2] * v.x + K[4] * v.y + K[5] * v.z};
 }
 
+template <class T, class S>
+__device__ __forceinline__ V3<T> cvt(V3<S> v)
+{
+    return V3<T>{T(v.x), T(v.y), T(v.z)};
+}
+
+// Edge vector x_j - x_i formed in the position precision PR, then rounded to
+// the arithmetic precision R (with FP64 positions and FP32 arithmetic the
+// edge keeps FP32 accuracy relative to the element size, not to |x|).
+template <class R, class P4, class PR>
+__device__ __forceinline__ V3<R> rel(P4 pj, V3<PR> xi)
+{
+    return cvt<R>(V3<PR>{PR(pj.x) - xi.x, PR(pj.y) - xi.y, PR(pj.z) - xi.z});
+}
+
+// Signed distance n . x - d of a position to a plane (n, d, k).
+template <class R, class PR>
+__device__ __forceinline__ R plane_phi(const R* pl, V3<PR> x)
+{
+    return R(PR(pl[0]) * x.x + PR(pl[1]) * x.y + PR(pl[2]) * x.z - PR(pl[3]));
+}
+
 // Visit k of vertex at xi: deformation gradient, own gradient a = dN_i,
 // V0 mu, V0 lambda.
-template <class R, class A>
-__device__ __forceinline__ void load_visit(const A& a, int k, V3<R> xi, Cols<R>& F, V3<R>& av,
+template <class R, class A, class PR>
+__device__ __forceinline__ void load_visit(const A& a, int k, V3<PR> xi, Cols<R>& F, V3<R>& av,
                                            R& vm, R& vl)
 {
     const int i1 = a.j1[k], i2 = a.j2[k], i3 = a.j3[k];
@@ -98,9 +124,9 @@ __device__ __forceinline__ void load_visit(const A& a, int k, V3<R> xi, Cols<R>&
     for (int q = 0; q < 9; ++q) m[q] = a.m[q * a.nvis + k];
     vm = a.vmu[k];
     vl = a.vlam[k];
-    const V3<R> e1 = xyz(a.W[i1]) - xi;
-    const V3<R> e2 = xyz(a.W[i2]) - xi;
-    const V3<R> e3 = xyz(a.W[i3]) - xi;
+    const V3<R> e1 = rel<R>(a.W[i1], xi);
+    const V3<R> e2 = rel<R>(a.W[i2], xi);
+    const V3<R> e3 = rel<R>(a.W[i3], xi);
     F = edge_F(e1, e2, e3, m);
     av = mk(-(m[0] + m[3] + m[6]), -(m[1] + m[4] + m[7]), -(m[2] + m[5] + m[8]));
 }
@@ -185,17 +211,17 @@ __device__ __forceinline__ void visit_accumulate(Acc<R>& q, const VisitRaw<R>& r
 // GEN = false: one instance without weak constraints or planes (no
 // per-vertex instance lookup); GEN = true: batched instances with per-
 // instance activity flags, weak constraints and contact planes.
-template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool GEN>
-__global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int vend)
+template <class R, class PR, int MODEL, int LANES, bool ACCEL, bool SAFE, bool GEN>
+__global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, int vend)
 {
-    using R4 = typename R4t<R>::T;
+    using P4 = typename R4t<PR>::T;
     constexpr bool WC = GEN;
     const int gid = blockIdx.x * kBlock + threadIdx.x;
     const int v = vbeg + gid / LANES;
     const int lane = gid & (LANES - 1);
     if (v >= vend) return;
     const int kb = a.vptr[v], ke = a.vptr[v + 1];
-    const R4 xw = a.W[v];
+    const P4 xw = a.W[v];
     int inst = 0;
     if (GEN) {
         inst = a.vinst[v];
@@ -204,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int 
             return;
         }
     }
-    const V3<R> xi = xyz(xw);
+    const V3<PR> xi = xyz(xw);
 
     Acc<R> q;
     q.g = mk<R>(0, 0, 0);
@@ -220,15 +246,15 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int 
     for (; k + LANES < ke; k += 2 * LANES) {
         const VisitRaw<R> r0 = load_raw<R>(a, k);
         const VisitRaw<R> r1 = load_raw<R>(a, k + LANES);
-        const V3<R> p01 = xyz(a.W[r0.i1]), p02 = xyz(a.W[r0.i2]), p03 = xyz(a.W[r0.i3]);
-        const V3<R> p11 = xyz(a.W[r1.i1]), p12 = xyz(a.W[r1.i2]), p13 = xyz(a.W[r1.i3]);
-        visit_accumulate<R, MODEL, SAFE>(q, r0, p01 - xi, p02 - xi, p03 - xi);
-        visit_accumulate<R, MODEL, SAFE>(q, r1, p11 - xi, p12 - xi, p13 - xi);
+        const P4 p01 = a.W[r0.i1], p02 = a.W[r0.i2], p03 = a.W[r0.i3];
+        const P4 p11 = a.W[r1.i1], p12 = a.W[r1.i2], p13 = a.W[r1.i3];
+        visit_accumulate<R, MODEL, SAFE>(q, r0, rel<R>(p01, xi), rel<R>(p02, xi), rel<R>(p03, xi));
+        visit_accumulate<R, MODEL, SAFE>(q, r1, rel<R>(p11, xi), rel<R>(p12, xi), rel<R>(p13, xi));
     }
     if (k < ke) {
         const VisitRaw<R> r0 = load_raw<R>(a, k);
-        visit_accumulate<R, MODEL, SAFE>(q, r0, xyz(a.W[r0.i1]) - xi, xyz(a.W[r0.i2]) - xi,
-                                         xyz(a.W[r0.i3]) - xi);
+        visit_accumulate<R, MODEL, SAFE>(q, r0, rel<R>(a.W[r0.i1], xi), rel<R>(a.W[r0.i2], xi),
+                                         rel<R>(a.W[r0.i3], xi));
     }
     V3<R>& g = q.g;
     R& S = q.S;
@@ -242,9 +268,10 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int 
         for (int k = a.wvptr[v] + lane; k < a.wvptr[v + 1]; k += LANES) {
             const int cc = a.wv_c[k];
             const R s = a.wv_s[k];
-            V3<R> Cc = mk<R>(0, 0, 0);
+            V3<PR> Cp = mk<PR>(0, 0, 0);
             for (int j = a.wc_ptr[cc]; j < a.wc_ptr[cc + 1]; ++j)
-                Cc = Cc + a.wc_w[j] * xyz(a.W[a.wc_vert[j]]);
+                Cp = Cp + PR(a.wc_w[j]) * xyz(a.W[a.wc_vert[j]]);
+            const V3<R> Cc = cvt<R>(Cp);
             const R* K = a.wc_K + 6 * cc;
             const V3<R> gk = s * symK_mul(K, Cc);
             g = g + gk;
@@ -283,7 +310,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int 
         for (int q = pb; q < pe; ++q) {
             const R* pl = a.planes + 5 * q;
             const V3<R> n = mk(pl[0], pl[1], pl[2]);
-            const R phi = dot(n, xi) - pl[3];
+            const R phi = plane_phi(pl, xi);
             if (phi < R(0)) {
                 gtot = gtot + (pl[4] * phi) * n;
                 sym_add_outer(A, pl[4], n);
@@ -316,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int 
                 for (int q2 = pb; q2 < pe; ++q2) {
                     const R* pl = a.planes + 5 * q2;
                     const V3<R> n = mk(pl[0], pl[1], pl[2]);
-                    const R phi0 = dot(n, xi) - pl[3];
+                    const R phi0 = plane_phi(pl, xi);
                     const R phi1 = phi0 + dot(n, d);
                     const R e0 = phi0 < R(0) ? R(0.5) * pl[4] * phi0 * phi0 : R(0);
                     const R e1 = phi1 < R(0) ? R(0.5) * pl[4] * phi1 * phi1 : R(0);
@@ -353,7 +380,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int 
                 for (int q = pb; q < pe; ++q) {
                     const R* pl = a.planes + 5 * q;
                     const V3<R> n = mk(pl[0], pl[1], pl[2]);
-                    const R phi0 = dot(n, xi) - pl[3];
+                    const R phi0 = plane_phi(pl, xi);
                     const R phi1 = phi0 + alpha * dot(n, d);
                     const R e0 = phi0 < R(0) ? R(0.5) * pl[4] * phi0 * phi0 : R(0);
                     const R e1 = phi1 < R(0) ? R(0.5) * pl[4] * phi1 * phi1 : R(0);
@@ -395,12 +422,12 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int 
             ++h;
         }
     }
-    const V3<R> xn = reject ? xi : xi + alpha * d;
+    const V3<PR> xn = reject ? xi : xi + cvt<PR>(alpha * d);
     if (lane == 0) {
         if (reject) atomicAdd(a.rejected + inst, 1);
         if (ACCEL) {
-            const V3<R> xp = xyz(a.P[v]);
-            const V3<R> b = a.omega * (a.gamma * (xn - xi) + xi - xp) + xp;
+            const V3<PR> xp = xyz(a.P[v]);
+            const V3<PR> b = a.omega * (a.gamma * (xn - xi) + xi - xp) + xp;
             a.W[v] = pack4(xn);
             a.P[v] = xw;
             a.N[v] = pack4(b);
@@ -410,62 +437,57 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R> a, int vbeg, int 
     }
 }
 
-template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool GEN>
-static hipError_t launch_phase_t(const SweepArgs<R>& a, int vbeg, int vend, hipStream_t s)
+template <class R, class PR, int MODEL, int LANES, bool ACCEL, bool SAFE, bool GEN>
+static hipError_t launch_phase_t(const SweepArgs<R, PR>& a, int vbeg, int vend, hipStream_t s)
 {
     const int64_t threads = int64_t(vend - vbeg) * LANES;
     if (threads <= 0) return hipSuccess;
     const int blocks = int((threads + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_phase<R, MODEL, LANES, ACCEL, SAFE, GEN>), dim3(blocks), dim3(kBlock), 0,
+    hipLaunchKernelGGL((k_phase<R, PR, MODEL, LANES, ACCEL, SAFE, GEN>), dim3(blocks), dim3(kBlock), 0,
                        s, a, vbeg, vend);
     return hipGetLastError();
 }
 
-template <class R, int MODEL, int LANES>
-static hipError_t dispatch_flags(const SweepArgs<R>& a, bool accel, bool safe, bool wc, int vb,
+template <class R, class PR, int MODEL, int LANES>
+static hipError_t dispatch_flags(const SweepArgs<R, PR>& a, bool accel, bool safe, bool wc, int vb,
                                  int ve, hipStream_t s)
 {
     const int code = (accel ? 4 : 0) | (safe ? 2 : 0) | (wc ? 1 : 0);
     switch (code) {
-    case 0: return launch_phase_t<R, MODEL, LANES, false, false, false>(a, vb, ve, s);
-    case 1: return launch_phase_t<R, MODEL, LANES, false, false, true>(a, vb, ve, s);
-    case 2: return launch_phase_t<R, MODEL, LANES, false, true, false>(a, vb, ve, s);
-    case 3: return launch_phase_t<R, MODEL, LANES, false, true, true>(a, vb, ve, s);
-    case 4: return launch_phase_t<R, MODEL, LANES, true, false, false>(a, vb, ve, s);
-    case 5: return launch_phase_t<R, MODEL, LANES, true, false, true>(a, vb, ve, s);
-    case 6: return launch_phase_t<R, MODEL, LANES, true, true, false>(a, vb, ve, s);
-    default: return launch_phase_t<R, MODEL, LANES, true, true, true>(a, vb, ve, s);
+    case 0: return launch_phase_t<R, PR, MODEL, LANES, false, false, false>(a, vb, ve, s);
+    case 1: return launch_phase_t<R, PR, MODEL, LANES, false, false, true>(a, vb, ve, s);
+    case 2: return launch_phase_t<R, PR, MODEL, LANES, false, true, false>(a, vb, ve, s);
+    case 3: return launch_phase_t<R, PR, MODEL, LANES, false, true, true>(a, vb, ve, s);
+    case 4: return launch_phase_t<R, PR, MODEL, LANES, true, false, false>(a, vb, ve, s);
+    case 5: return launch_phase_t<R, PR, MODEL, LANES, true, false, true>(a, vb, ve, s);
+    case 6: return launch_phase_t<R, PR, MODEL, LANES, true, true, false>(a, vb, ve, s);
+    default: return launch_phase_t<R, PR, MODEL, LANES, true, true, true>(a, vb, ve, s);
     }
 }
 
-template <class R, int MODEL>
-static hipError_t dispatch_lanes(const SweepArgs<R>& a, int lanes, bool accel, bool safe,
+template <class R, class PR, int MODEL>
+static hipError_t dispatch_lanes(const SweepArgs<R, PR>& a, int lanes, bool accel, bool safe,
                                  bool wc, int vb, int ve, hipStream_t s)
 {
     switch (lanes) {
-    case 1: return dispatch_flags<R, MODEL, 1>(a, accel, safe, wc, vb, ve, s);
-    case 2: return dispatch_flags<R, MODEL, 2>(a, accel, safe, wc, vb, ve, s);
-    case 4: return dispatch_flags<R, MODEL, 4>(a, accel, safe, wc, vb, ve, s);
-    case 8: return dispatch_flags<R, MODEL, 8>(a, accel, safe, wc, vb, ve, s);
-    case 16: return dispatch_flags<R, MODEL, 16>(a, accel, safe, wc, vb, ve, s);
-    case 32: return dispatch_flags<R, MODEL, 32>(a, accel, safe, wc, vb, ve, s);
-    case 64: return dispatch_flags<R, MODEL, 64>(a, accel, safe, wc, vb, ve, s);
+    case 1: return dispatch_flags<R, PR, MODEL, 1>(a, accel, safe, wc, vb, ve, s);
+    case 2: return dispatch_flags<R, PR, MODEL, 2>(a, accel, safe, wc, vb, ve, s);
+    case 4: return dispatch_flags<R, PR, MODEL, 4>(a, accel, safe, wc, vb, ve, s);
+    case 8: return dispatch_flags<R, PR, MODEL, 8>(a, accel, safe, wc, vb, ve, s);
+    case 16: return dispatch_flags<R, PR, MODEL, 16>(a, accel, safe, wc, vb, ve, s);
+    case 32: return dispatch_flags<R, PR, MODEL, 32>(a, accel, safe, wc, vb, ve, s);
+    case 64: return dispatch_flags<R, PR, MODEL, 64>(a, accel, safe, wc, vb, ve, s);
     default: return hipErrorInvalidValue;
     }
 }
 
-template <class R>
-hipError_t launch_phase(const SweepArgs<R>& a, int model, int lanes, bool accel, bool safe,
+template <class R, class PR>
+hipError_t launch_phase(const SweepArgs<R, PR>& a, int model, int lanes, bool accel, bool safe,
                         bool wc, int vbeg, int vend, hipStream_t s)
 {
-    if (model == kNeo) return dispatch_lanes<R, kNeo>(a, lanes, accel, safe, wc, vbeg, vend, s);
-    return dispatch_lanes<R, kCor>(a, lanes, accel, safe, wc, vbeg, vend, s);
+    if (model == kNeo) return dispatch_lanes<R, PR, kNeo>(a, lanes, accel, safe, wc, vbeg, vend, s);
+    return dispatch_lanes<R, PR, kCor>(a, lanes, accel, safe, wc, vbeg, vend, s);
 }
-
-template hipError_t launch_phase<float>(const SweepArgs<float>&, int, int, bool, bool, bool, int,
-                                        int, hipStream_t);
-template hipError_t launch_phase<double>(const SweepArgs<double>&, int, int, bool, bool, bool,
-                                         int, int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Adjoint: block Gauss-Seidel on the true Hessian H lam = b (Neo-Hookean).
@@ -478,31 +500,28 @@ template hipError_t launch_phase<double>(const SweepArgs<double>&, int, int, boo
 // + planes, c = cof F dN_i (along x_i alone the Neo-Hookean energy is
 // exactly quadratic).  Each update: lam_i += H_ii^{-1} (b_i - (H lam)_i).
 // ---------------------------------------------------------------------------
-template <class R, int LANES, bool ACCEL, bool WC>
-__global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R> a, int vbeg, int vend)
+template <class R, class PR, int LANES, bool ACCEL, bool WC>
+__global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg, int vend)
 {
-    using R4 = typename R4t<R>::T;
+    using P4 = typename R4t<PR>::T;
     const int gid = blockIdx.x * kBlock + threadIdx.x;
     const int v = vbeg + gid / LANES;
     const int lane = gid & (LANES - 1);
     if (v >= vend) return;
-    const int inst = a.vinst[v];
-    const V3<R> xi = xyz(a.X[v]);
-    const R4 lw = a.L[v];
-    const V3<R> li = xyz(lw);
+    const V3<PR> xi = xyz(a.X[v]);
+    const P4 lw = a.L[v];
+    const V3<PR> li = xyz(lw);
     V3<R> r = mk<R>(0, 0, 0);
     R S = R(0);
     Sym<R> Hc = sym_zero<R>();
     const int kb = a.vptr[v], ke = a.vptr[v + 1];
     for (int k = kb + lane; k < ke; k += LANES) {
-        const int i1 = a.j1[k], i2 = a.j2[k], i3 = a.j3[k];
-        R m[9];
-#pragma unroll
-        for (int q = 0; q < 9; ++q) m[q] = a.m[q * a.nvis + k];
-        const R vm = a.vmu[k], vl = a.vlam[k];
-        const Cols<R> F = edge_F(xyz(a.X[i1]) - xi, xyz(a.X[i2]) - xi, xyz(a.X[i3]) - xi, m);
-        const Cols<R> Lm = edge_F(xyz(a.L[i1]) - li, xyz(a.L[i2]) - li, xyz(a.L[i3]) - li, m);
-        const V3<R> av = mk(-(m[0] + m[3] + m[6]), -(m[1] + m[4] + m[7]), -(m[2] + m[5] + m[8]));
+        const VisitRaw<R> q = load_raw<R>(a, k);
+        const Cols<R> F = edge_F(rel<R>(a.X[q.i1], xi), rel<R>(a.X[q.i2], xi), rel<R>(a.X[q.i3], xi), q.m);
+        const Cols<R> Lm = edge_F(rel<R>(a.L[q.i1], li), rel<R>(a.L[q.i2], li), rel<R>(a.L[q.i3], li), q.m);
+        const V3<R> av = mk(-(q.m[0] + q.m[3] + q.m[6]), -(q.m[1] + q.m[4] + q.m[7]),
+                            -(q.m[2] + q.m[5] + q.m[8]));
+        const R vm = q.vm, vl = q.vl;
         const Cols<R> C = cofactor(F);
         const R J = dot(F.c0, C.c0);
         const V3<R> c = apply(C, av);
@@ -517,15 +536,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R> a, int vbeg, in
         S += vm * dot(av, av);
         sym_add_outer(Hc, lh, c);
     }
+    int inst = 0;
     if (WC) {
+        inst = a.vinst[v];
         for (int k = a.wvptr[v] + lane; k < a.wvptr[v + 1]; k += LANES) {
             const int cc = a.wv_c[k];
             const R s = a.wv_s[k];
-            V3<R> Cl = mk<R>(0, 0, 0);
+            V3<PR> Cl = mk<PR>(0, 0, 0);
             for (int j = a.wc_ptr[cc]; j < a.wc_ptr[cc + 1]; ++j)
-                Cl = Cl + a.wc_w[j] * xyz(a.L[a.wc_vert[j]]);
+                Cl = Cl + PR(a.wc_w[j]) * xyz(a.L[a.wc_vert[j]]);
             const R* K = a.wc_K + 6 * cc;
-            r = r + s * symK_mul(K, Cl);
+            r = r + s * symK_mul(K, cvt<R>(Cl));
             sym_add_scaled(Hc, s * s, K);
         }
     }
@@ -541,20 +562,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R> a, int vbeg, in
         for (int q = a.plane_ptr[inst]; q < a.plane_ptr[inst + 1]; ++q) {
             const R* pl = a.planes + 5 * q;
             const V3<R> n = mk(pl[0], pl[1], pl[2]);
-            if (dot(n, xi) - pl[3] < R(0)) {
-                r = r + (pl[4] * dot(n, li)) * n;
+            if (plane_phi(pl, xi) < R(0)) {
+                r = r + (pl[4] * dot(n, cvt<R>(li))) * n;
                 sym_add_outer(Hc, pl[4], n);
             }
         }
     }
-    const V3<R> rho = xyz(a.B[v]) - r;
+    const V3<R> rho = cvt<R>(xyz(a.B[v])) - r;
     V3<R> dl;
     if (!chol_solve(Hc, rho, dl)) dl = mk<R>(0, 0, 0);
-    const V3<R> ln = li + dl;
+    const V3<PR> ln = li + cvt<PR>(dl);
     if (lane == 0) {
         if (ACCEL) {
-            const V3<R> lp = xyz(a.P[v]);
-            const V3<R> b = a.omega * (a.gamma * (ln - li) + li - lp) + lp;
+            const V3<PR> lp = xyz(a.P[v]);
+            const V3<PR> b = a.omega * (a.gamma * (ln - li) + li - lp) + lp;
             a.L[v] = pack4(ln);
             a.P[v] = lw;
             a.N[v] = pack4(b);
@@ -564,48 +585,44 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R> a, int vbeg, in
     }
 }
 
-template <class R, int LANES, bool ACCEL, bool WC>
-static hipError_t launch_adj_t(const AdjArgs<R>& a, int vb, int ve, hipStream_t s)
+template <class R, class PR, int LANES, bool ACCEL, bool WC>
+static hipError_t launch_adj_t(const AdjArgs<R, PR>& a, int vb, int ve, hipStream_t s)
 {
     const int64_t threads = int64_t(ve - vb) * LANES;
     if (threads <= 0) return hipSuccess;
     const int blocks = int((threads + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_adj_phase<R, LANES, ACCEL, WC>), dim3(blocks), dim3(kBlock), 0, s, a,
+    hipLaunchKernelGGL((k_adj_phase<R, PR, LANES, ACCEL, WC>), dim3(blocks), dim3(kBlock), 0, s, a,
                        vb, ve);
     return hipGetLastError();
 }
 
-template <class R, int LANES>
-static hipError_t adj_flags(const AdjArgs<R>& a, bool accel, bool wc, int vb, int ve,
+template <class R, class PR, int LANES>
+static hipError_t adj_flags(const AdjArgs<R, PR>& a, bool accel, bool wc, int vb, int ve,
                             hipStream_t s)
 {
     if (accel) {
-        return wc ? launch_adj_t<R, LANES, true, true>(a, vb, ve, s)
-                  : launch_adj_t<R, LANES, true, false>(a, vb, ve, s);
+        return wc ? launch_adj_t<R, PR, LANES, true, true>(a, vb, ve, s)
+                  : launch_adj_t<R, PR, LANES, true, false>(a, vb, ve, s);
     }
-    return wc ? launch_adj_t<R, LANES, false, true>(a, vb, ve, s)
-              : launch_adj_t<R, LANES, false, false>(a, vb, ve, s);
+    return wc ? launch_adj_t<R, PR, LANES, false, true>(a, vb, ve, s)
+              : launch_adj_t<R, PR, LANES, false, false>(a, vb, ve, s);
 }
 
-template <class R>
-hipError_t launch_adjoint_phase(const AdjArgs<R>& a, int lanes, bool accel, bool wc, int vbeg,
+template <class R, class PR>
+hipError_t launch_adjoint_phase(const AdjArgs<R, PR>& a, int lanes, bool accel, bool wc, int vbeg,
                                 int vend, hipStream_t s)
 {
     switch (lanes) {
-    case 1: return adj_flags<R, 1>(a, accel, wc, vbeg, vend, s);
-    case 2: return adj_flags<R, 2>(a, accel, wc, vbeg, vend, s);
-    case 4: return adj_flags<R, 4>(a, accel, wc, vbeg, vend, s);
-    case 8: return adj_flags<R, 8>(a, accel, wc, vbeg, vend, s);
-    case 16: return adj_flags<R, 16>(a, accel, wc, vbeg, vend, s);
-    case 32: return adj_flags<R, 32>(a, accel, wc, vbeg, vend, s);
-    case 64: return adj_flags<R, 64>(a, accel, wc, vbeg, vend, s);
+    case 1: return adj_flags<R, PR, 1>(a, accel, wc, vbeg, vend, s);
+    case 2: return adj_flags<R, PR, 2>(a, accel, wc, vbeg, vend, s);
+    case 4: return adj_flags<R, PR, 4>(a, accel, wc, vbeg, vend, s);
+    case 8: return adj_flags<R, PR, 8>(a, accel, wc, vbeg, vend, s);
+    case 16: return adj_flags<R, PR, 16>(a, accel, wc, vbeg, vend, s);
+    case 32: return adj_flags<R, PR, 32>(a, accel, wc, vbeg, vend, s);
+    case 64: return adj_flags<R, PR, 64>(a, accel, wc, vbeg, vend, s);
     default: return hipErrorInvalidValue;
     }
 }
-template hipError_t launch_adjoint_phase<float>(const AdjArgs<float>&, int, bool, bool, int, int,
-                                                hipStream_t);
-template hipError_t launch_adjoint_phase<double>(const AdjArgs<double>&, int, bool, bool, int,
-                                                 int, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // FP64 passes: residual r = f + fhat and energy (Eq. fem_qs, pe_hat), and
@@ -772,8 +789,6 @@ hipError_t launch_residual(const ResArgs<R>& a, double* rsq, double* r_out, hipS
                            rsq, r_out);
     return hipGetLastError();
 }
-template hipError_t launch_residual<float>(const ResArgs<float>&, double*, double*, hipStream_t);
-template hipError_t launch_residual<double>(const ResArgs<double>&, double*, double*, hipStream_t);
 
 // Adjoint assembly in FP64: per tet V0 dP[Lam] (into vp) and the parameter
 // gradients; per vertex (H lam)_i, the adjoint residual b - H lam on free
@@ -853,17 +868,12 @@ hipError_t launch_adjoint_assembly(const ResArgs<R>& a, const typename R4t<R>::T
                            lam, b, rsq, dxd, dir_pos);
     return hipGetLastError();
 }
-template hipError_t launch_adjoint_assembly<float>(const ResArgs<float>&, const float4*,
-                                                   const float4*, double*, double*, double*,
-                                                   double*, const int*, hipStream_t);
-template hipError_t launch_adjoint_assembly<double>(const ResArgs<double>&, const double4*,
-                                                    const double4*, double*, double*, double*,
-                                                    double*, const int*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Deterministic segmented sums: fixed per-thread strides and a fixed LDS
 // tree, first per chunk, then per instance over its chunks.
 // ---------------------------------------------------------------------------
+#if PBNG_KERNEL_SET == 0
 __device__ __forceinline__ double block_sum(double v, double* sh)
 {
     sh[threadIdx.x] = v;
@@ -906,6 +916,8 @@ hipError_t launch_segsum(const double* vals, const SegPlan& plan, int n_inst, do
     hipLaunchKernelGGL(k_inst_sum, dim3(n_inst), dim3(kBlock), 0, s, plan.partial, plan.qptr, out);
     return hipGetLastError();
 }
+
+#endif
 
 // ---------------------------------------------------------------------------
 // Layout conversion and parameter updates
@@ -1081,7 +1093,10 @@ hipError_t launch_set_dirichlet(const double* xd, const int* dir_internal, int n
     return hipGetLastError();
 }
 
-#define PBNG_INST(R)                                                                              \
+// Explicit instantiations.  The library compiles this file once per
+// PBNG_KERNEL_SET (0: FP32, 1: FP64, 2: FP32 arithmetic on FP64 positions)
+// so the three sets build in parallel; set 0 also holds the shared helpers.
+#define PBNG_INST_POS(R)                                                                          \
     template hipError_t launch_load<R>(const R*, const int*, const R4t<R>::T*, R4t<R>::T*,       \
                                        R4t<R>::T*, R4t<R>::T*, int, int, hipStream_t);           \
     template hipError_t launch_load_vec<R>(const R*, const int*, R4t<R>::T*, int, int,           \
@@ -1090,11 +1105,29 @@ hipError_t launch_set_dirichlet(const double* xd, const int* dir_internal, int n
     template hipError_t launch_copy4<R>(const R4t<R>::T*, R4t<R>::T*, int, hipStream_t);         \
     template hipError_t launch_store64<R>(const R4t<R>::T*, const int*, double*, int,            \
                                           hipStream_t);                                           \
-    template hipError_t launch_set_materials<R>(const double*, const double*, TetGeo*, int,      \
-                                                const int*, int, R*, R*, hipStream_t);            \
     template hipError_t launch_set_dirichlet<R>(const double*, const int*, int, int, R4t<R>::T*, \
-                                                hipStream_t);
-PBNG_INST(float)
-PBNG_INST(double)
+                                                hipStream_t);                                     \
+    template hipError_t launch_residual<R>(const ResArgs<R>&, double*, double*, hipStream_t);    \
+    template hipError_t launch_adjoint_assembly<R>(const ResArgs<R>&, const R4t<R>::T*,          \
+                                                   const R4t<R>::T*, double*, double*, double*,   \
+                                                   double*, const int*, hipStream_t);
+#define PBNG_INST_SWEEP(R, PR)                                                                    \
+    template hipError_t launch_phase<R, PR>(const SweepArgs<R, PR>&, int, int, bool, bool, bool,  \
+                                            int, int, hipStream_t);                               \
+    template hipError_t launch_adjoint_phase<R, PR>(const AdjArgs<R, PR>&, int, bool, bool, int,  \
+                                                    int, hipStream_t);
+#if PBNG_KERNEL_SET == 0
+PBNG_INST_POS(float)
+PBNG_INST_POS(double)
+template hipError_t launch_set_materials<float>(const double*, const double*, TetGeo*, int,
+                                                const int*, int, float*, float*, hipStream_t);
+template hipError_t launch_set_materials<double>(const double*, const double*, TetGeo*, int,
+                                                 const int*, int, double*, double*, hipStream_t);
+PBNG_INST_SWEEP(float, float)
+#elif PBNG_KERNEL_SET == 1
+PBNG_INST_SWEEP(double, double)
+#else
+PBNG_INST_SWEEP(float, double)
+#endif
 
 }  // namespace pbng

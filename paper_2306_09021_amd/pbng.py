@@ -21,7 +21,7 @@ OK, NOT_CONVERGED = 0, 1
 ERRORS = {-1: "EINVAL", -2: "EMESH", -3: "EMATERIAL", -4: "ECOLOR", -5: "ENAN", -6: "EHIP",
           -7: "ENOMEM", -8: "EUNSUPPORTED"}
 MODEL = {"nh": 0, "corotated": 1}
-REAL = {"f32": 0, "f64": 1}
+REAL = {"f32": 0, "f64": 1, "mixed": 2}
 ACCEL = {"none": 0, "chebyshev": 1, "sor": 2}
 SAFEGUARD = {"none": 0, "backtrack": 1}
 
@@ -303,7 +303,7 @@ class Workspace:
     @property
     def dtype(self):
         import torch
-        return torch.float64 if self.real == "f64" else torch.float32
+        return torch.float32 if self.real == "f32" else torch.float64
 
     def _check_x(self, x):
         import torch

@@ -23,7 +23,7 @@ def require_gpu():
 
 
 def dev_x(x, real):
-    dt = torch.float64 if real == "f64" else torch.float32
+    dt = torch.float32 if real == "f32" else torch.float64
     return torch.tensor(np.asarray(x, np.float64).reshape(-1, 3), dtype=dt, device="cuda").contiguous()
 
 

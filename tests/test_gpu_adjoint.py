@@ -46,7 +46,7 @@ def gpu_adjoint(sc, x, dLdx, real, **kw):
     return {k: host(v) for k, v in out.items()}, st[0], rc
 
 
-@pytest.mark.parametrize("real,tol", [("f64", 1e-8), ("f32", 1e-4)])
+@pytest.mark.parametrize("real,tol", [("f64", 1e-8), ("f32", 1e-4), ("mixed", 1e-4)])
 def test_adjoint_matches_dense_solve(real, tol):
     sc, target = tiny_case()
     op = O.make_problem(sc)

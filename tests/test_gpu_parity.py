@@ -242,3 +242,38 @@ def test_sampled_vertex_updates_full_beam():
     upd = O.update_vertices(op, before, pick, safeguard="backtrack")
     d = np.abs(upd - xg[pick]).max()
     assert d <= 1e-5 * np.abs(upd - before[pick]).max() + 1e-6
+
+
+@pytest.mark.parametrize("model", ["nh", "corotated"])
+def test_mixed_parity(model):
+    """FP32 arithmetic on an FP64 master copy of the positions."""
+    sc = S.twist_box(6, model, 1e4, 0.3, 60.0, 1.2, 0.01, seed=2)
+    announce("mixed twist6 %s" % model)
+    xg, stg, _ = _run_gpu(sc, "mixed", 30, safeguard="backtrack", accel="chebyshev", rho=0.9,
+                          gamma=1.2)
+    xo, sto, _ = oracle_solve(sc, 30, safeguard="backtrack", accel="chebyshev", rho=0.9, gamma=1.2)
+    print("rel err", rel_err(xg, xo), "disp err", disp_err(xg, xo, sc.rest_pos))
+    assert rel_err(xg, xo) <= 1e-5
+
+
+def test_mixed_converges_below_fp32_storage_floor():
+    """A corotated cube (nu = 0.3): FP32 sweeps on FP32 positions stall at
+    the storage floor (~ stiffness x u32 x |x|, here above 1e-5); with an
+    FP64 master copy of the positions the same FP32 arithmetic goes below
+    5e-6 (its own floor, from FP32 stresses, is near 1e-6)."""
+    rng = np.random.default_rng(17)
+    sc = S.random_cube(rng, 10, "corotated", 1e5, 0.3, 40.0, 0.8, 1.2, "cube")
+    announce("mixed cube10 to 5e-6 (and f32 for comparison)")
+    out = {}
+    for real in ("f32", "mixed"):
+        ws = workspace([sc], real)
+        x = dev_x(sc.initial_iterate(), real)
+        rc, st = ws.solve(x, max_sweeps=20000, rel_tol=5e-6, check_every=50, accel="chebyshev",
+                          rho=0.95, gamma=1.7)
+        print(real, st[0])
+        out[real] = (x, st[0], ws)
+    x, st, ws = out["mixed"]
+    assert st["converged"] == 1 and st["rel_residual"] <= 5e-6
+    assert out["f32"][1]["converged"] == 0
+    res, en = ws.residual(x)
+    assert res[0] <= 5e-6 * st["residual0"]
