@@ -142,8 +142,10 @@ typedef struct pbng_problem {
  *  lanes           lanes of a 64-wide wavefront per vertex (1, 2, 4, 8,
  *                  16, 32, 64); 0 = per colour, the power of two covering
  *                  half the colour's mean number of incident tets
- *  sweeps_per_graph  >0: capture that many steady-state sweeps in one HIP
- *                  graph and replay it; 0 = plain launches
+ *  sweeps_per_graph  >0: once the blend weight is at its fixed point,
+ *                  capture that many sweeps (rounded up to even with a
+ *                  blend) in one HIP graph and replay it between residual
+ *                  checks; 0 = plain launches.  Needs a non-null stream.
  *  resume          1: continue the acceleration state (x^{l-1}, l,
  *                  omega_l) left in the workspace by the previous solve
  *                  instead of starting a new iteration at l = 0
@@ -296,6 +298,20 @@ int32_t pbng_residual(pbng_workspace* ws, const void* x, double* res_norm, doubl
 int32_t pbng_adjoint(pbng_workspace* ws, const void* x_eq, const void* dL_dx, double* dL_dxD,
                      double* dL_dmu, double* dL_dlambda, double* lam_out,
                      const pbng_adjoint_opts* o, pbng_stats* stats, void* hip_stream);
+
+/*
+ * Autotuner: on the iterate x (device, position type), times every colour
+ * phase of the workspace for each lanes-per-vertex candidate (1 .. 64 around
+ * the colour's mean visit count, best of 3 x 8 launches) and keeps the
+ * fastest per colour as the workspace's automatic choice (o->lanes = 0),
+ * then times 64 sweeps as plain launches and as replays of graphs of 2, 8
+ * and 32 sweeps.  *tuned receives *o with lanes = 0 and the chosen
+ * sweeps_per_graph; lanes_out [n_colors] (host, nullable) the lanes per
+ * colour.  hip_stream must not be NULL.  The workspace's internal iterate is
+ * left undefined (the next pbng_solve reloads it).
+ */
+int32_t pbng_autotune(pbng_workspace* ws, const void* x, const pbng_solve_opts* o,
+                      pbng_solve_opts* tuned, int32_t* lanes_out, void* hip_stream);
 
 /*
  * Launch-level access for measurement: run n_sweeps sweeps (with the

@@ -362,8 +362,31 @@ struct pbng_workspace {
     double omega_l = 1.0;
     bool ring_valid = false;
 
+    // captured steady-state sweeps (one HIP graph, replayed)
+    hipGraphExec_t gexec = nullptr;
+    struct GraphKey {
+        void *W, *P, *N;
+        double omega, gamma;
+        int sweeps, accel, safe, lanes, max_halvings;
+        hipStream_t stream;
+        bool operator==(const GraphKey& o) const
+        {
+            return W == o.W && P == o.P && N == o.N && omega == o.omega && gamma == o.gamma &&
+                   sweeps == o.sweeps && accel == o.accel && safe == o.safe && lanes == o.lanes &&
+                   max_halvings == o.max_halvings && stream == o.stream;
+        }
+    } gkey{};
+    uint64_t lanes_version = 0;   // bumped when the automatic lane table changes
+    uint64_t gkey_lanes_version = ~uint64_t(0);
+
+    void drop_graph()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        gexec = nullptr;
+    }
     ~pbng_workspace()
     {
+        drop_graph();
         if (hbuf) (void)hipHostFree(hbuf);
         if (hact) (void)hipHostFree(hact);
     }
@@ -872,6 +895,39 @@ void launch_sweep(pbng_workspace* ws, const pbng_solve_opts* o, double omega, do
     if (accel) std::swap(ws->W.p, ws->N.p);
 }
 
+// Replays `reps` times a HIP graph holding `S` sweeps with fixed blend
+// weights (the steady state of the acceleration), capturing it first if the
+// launch arguments changed.  S is even when the blend swaps buffers, so the
+// buffer roles after a replay equal those at capture time.
+template <class R, class PR>
+void graph_sweeps(pbng_workspace* ws, const pbng_solve_opts* o, int S, int reps, double omega, double gamma,
+                  hipStream_t s)
+{
+    const pbng_workspace::GraphKey key{ws->W.p, ws->P.p, ws->N.p, omega, gamma, S, o->accel, o->safeguard,
+                                       o->lanes, o->max_halvings, s};
+    if (!ws->gexec || !(ws->gkey == key) || ws->gkey_lanes_version != ws->lanes_version) {
+        ws->drop_graph();
+        hipchk(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "capture begin");
+        try {
+            for (int k = 0; k < S; ++k) launch_sweep<R, PR>(ws, o, omega, gamma, s);
+        } catch (...) {
+            hipGraph_t g = nullptr;
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        hipGraph_t g = nullptr;
+        hipchk(hipStreamEndCapture(s, &g), "capture end");
+        const hipError_t e = hipGraphInstantiate(&ws->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        hipchk(e, "graph instantiate");
+        ws->gkey = key;
+        ws->gkey_lanes_version = ws->lanes_version;
+        // the capture ran the host-side buffer swaps S times: even S restores them
+    }
+    for (int r = 0; r < reps; ++r) hipchk(hipGraphLaunch(ws->gexec, s), "graph launch");
+}
+
 template <class R, class PR>
 int32_t solve_t(pbng_workspace* ws, void* x, const pbng_solve_opts* o, pbng_stats* st, hipStream_t s)
 {
@@ -917,7 +973,11 @@ int32_t solve_t(pbng_workspace* ws, void* x, const pbng_solve_opts* o, pbng_stat
     int n_active = 0;
     for (int q = 0; q < n; ++q) n_active += act[q];
     bool nan = false;
-    for (int sw = 0; sw < o->max_sweeps && n_active > 0; ++sw) {
+    const bool accel_swaps = o->accel != PBNG_ACCEL_NONE;
+    int S = o->sweeps_per_graph > 0 ? o->sweeps_per_graph : 0;
+    if (accel_swaps && (S & 1)) ++S;
+    if (s == nullptr) S = 0;  // the legacy null stream cannot be captured
+    for (int sw = 0; sw < o->max_sweeps && n_active > 0;) {
         double omega = 1.0, gamma = 1.0;
         if (o->accel == PBNG_ACCEL_CHEBYSHEV) {
             omega = chebyshev_next(ws->sweep_l, o->rho, ws->omega_l);
@@ -925,11 +985,28 @@ int32_t solve_t(pbng_workspace* ws, void* x, const pbng_solve_opts* o, pbng_stat
         } else if (o->accel == PBNG_ACCEL_SOR) {
             omega = o->omega;
         }
-        launch_sweep<R, PR>(ws, o, omega, gamma, s);
+        // sweeps until the next residual check
+        const int next_check = std::min(o->max_sweeps, (sw / o->check_every + 1) * o->check_every);
+        const int todo = next_check - sw;
+        // blend weights at their fixed point in the position precision: a
+        // block of sweeps can be replayed from one captured graph
+        // (for Chebyshev only past the special weights of l < 3, where
+        // omega_{l+1} = omega_l marks the fixed point of the recurrence)
+        const bool steady = o->accel != PBNG_ACCEL_CHEBYSHEV || (ws->sweep_l >= 3 && omega == ws->omega_l);
+        int done = 1;
+        if (S > 0 && steady && ws->sweep_l > 0 && todo >= S) {
+            const int reps = todo / S;
+            graph_sweeps<R, PR>(ws, o, S, reps, omega, gamma, s);
+            done = reps * S;
+            ws->sweep_l += done - 1;
+        } else {
+            launch_sweep<R, PR>(ws, o, omega, gamma, s);
+        }
         ws->omega_l = omega;
         ws->sweep_l++;
-        for (int q = 0; q < n; ++q) sweeps[q] += act[q];
-        if ((sw + 1) % o->check_every == 0 || sw + 1 == o->max_sweeps) {
+        sw += done;
+        for (int q = 0; q < n; ++q) sweeps[q] += act[q] * done;
+        if (sw % o->check_every == 0 || sw == o->max_sweeps) {
             residual_internal<PR>(ws, ws->W.p, nullptr, s);
             const double t = now_ms() - t0;
             bool changed = false;
@@ -1126,6 +1203,109 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
 void check_ws(const pbng_workspace* ws)
 {
     if (!ws) fail(PBNG_EINVAL, "workspace is null");
+}
+
+struct Events {
+    hipEvent_t a = nullptr, b = nullptr;
+    Events()
+    {
+        hipchk(hipEventCreate(&a), "event");
+        hipchk(hipEventCreate(&b), "event");
+    }
+    ~Events()
+    {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+    }
+    float ms()
+    {
+        hipchk(hipEventSynchronize(b), "event sync");
+        float t = 0.f;
+        hipchk(hipEventElapsedTime(&t, a, b), "event time");
+        return t;
+    }
+};
+
+// Measured choice of the lanes per vertex of every colour (the tile of the
+// colour-phase kernel) and of the sweeps per captured graph.
+template <class R, class PR>
+void autotune_t(pbng_workspace* ws, const void* x, const pbng_solve_opts* o, pbng_solve_opts* tuned,
+                hipStream_t s)
+{
+    using P4 = typename R4t<PR>::T;
+    ensure_ring(ws);
+    auto reload = [&]() {
+        hipchk(launch_load<PR>(static_cast<const PR*>(x), ws->orig_of.as<int>(), ws->xd_int.as<P4>(), ws->W.as<P4>(),
+                               ws->P.as<P4>(), ws->N.as<P4>(), int(ws->nfree), int(ws->nv), s),
+               "load");
+        for (int q = 0; q < ws->n_inst; ++q) ws->hact[q] = 1;
+        hipchk(hipMemcpyAsync(ws->active.p, ws->hact, ws->n_inst * sizeof(int), hipMemcpyHostToDevice, s), "h2d");
+        hipchk(hipMemsetAsync(ws->rejected.p, 0, ws->n_inst * sizeof(int), s), "memset");
+    };
+    reload();
+    Events ev;
+    const bool accel = o->accel != PBNG_ACCEL_NONE;
+    const bool safe = o->safeguard == PBNG_SAFEGUARD_BACKTRACK;
+    const SweepArgs<R, PR> a = sweep_args<R, PR>(ws, 1.0, 1.0, o->max_halvings);
+    for (int c = 0; c < ws->ncol; ++c) {
+        const int vb = ws->col_ptr[c], ve = ws->col_ptr[c + 1];
+        if (ve <= vb) continue;
+        const double mv = double(ws->phase_visits[c]) / double(ve - vb);
+        int best = ws->phase_lanes[c];
+        float best_t = 1e30f;
+        for (int L = 1; L <= 64; L *= 2) {
+            if (L > 2 * mv + 1 || 16 * L < mv) continue;
+            float t = 1e30f;
+            for (int trial = 0; trial < 3; ++trial) {
+                hipchk(hipEventRecord(ev.a, s), "record");
+                for (int r = 0; r < 8; ++r)
+                    hipchk(launch_phase<R, PR>(a, ws->model, L, accel, safe, ws->general(), vb, ve, s), "phase");
+                hipchk(hipEventRecord(ev.b, s), "record");
+                t = std::min(t, ev.ms());
+            }
+            if (t < best_t) {
+                best_t = t;
+                best = L;
+            }
+        }
+        ws->phase_lanes[c] = best;
+    }
+    ws->lanes_version++;
+    // sweeps per graph: plain launches against replayed graphs
+    pbng_solve_opts q = *o;
+    q.lanes = 0;
+    const int n_sw = 64;
+    int best_S = 0;
+    float best_t = 1e30f;
+    for (int S : {0, 2, 8, 32}) {
+        q.sweeps_per_graph = S;
+        float t = 1e30f;
+        for (int trial = 0; trial < 2; ++trial) {
+            reload();
+            if (S > 0) graph_sweeps<R, PR>(ws, &q, S, 1, 1.0, 1.0, s);  // capture outside the timing
+            hipchk(hipEventRecord(ev.a, s), "record");
+            if (S == 0) {
+                for (int k = 0; k < n_sw; ++k) launch_sweep<R, PR>(ws, &q, 1.0, 1.0, s);
+            } else {
+                graph_sweeps<R, PR>(ws, &q, S, n_sw / S, 1.0, 1.0, s);
+            }
+            hipchk(hipEventRecord(ev.b, s), "record");
+            t = std::min(t, ev.ms());
+        }
+        // a graph must win by more than timing noise to be chosen
+        if (S == 0 || t < 0.98f * best_t) {
+            if (t < best_t || S == 0) {
+                best_t = t;
+                best_S = S;
+            }
+        }
+    }
+    ws->drop_graph();
+    ws->ring_valid = false;
+    hipchk(hipStreamSynchronize(s), "sync");
+    *tuned = *o;
+    tuned->lanes = 0;
+    tuned->sweeps_per_graph = best_S;
 }
 
 }  // namespace
@@ -1450,6 +1630,24 @@ int32_t pbng_phase(pbng_workspace* ws, int32_t color, const pbng_solve_opts* o, 
             hipchk(launch_phase<float, float>(sweep_args<float, float>(ws, 1.0, 1.0, o->max_halvings),
                                               ws->model, lanes, accel, safe, ws->general(), c0, c1, s),
                    "phase");
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_autotune(pbng_workspace* ws, const void* x, const pbng_solve_opts* o, pbng_solve_opts* tuned,
+                      int32_t* lanes_out, void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        check_solve_opts(o);
+        if (!x || !tuned) fail(PBNG_EINVAL, "null argument");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        if (s == nullptr) fail(PBNG_EINVAL, "pbng_autotune needs a non-null stream (graphs are captured)");
+        if (ws->real == PBNG_F64) autotune_t<double, double>(ws, x, o, tuned, s);
+        else if (ws->real == PBNG_MIXED) autotune_t<float, double>(ws, x, o, tuned, s);
+        else autotune_t<float, float>(ws, x, o, tuned, s);
+        if (lanes_out)
+            for (int c = 0; c < ws->ncol; ++c) lanes_out[c] = ws->phase_lanes[c];
         return PBNG_OK;
     });
 }

@@ -105,6 +105,8 @@ def lib():
             "pbng_phase": ([vp, C.c_int32, C.POINTER(SolveOpts), vp], C.c_int32),
             "pbng_phase_bytes": ([vp, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                   C.POINTER(C.c_int64)], C.c_int32),
+            "pbng_autotune": ([vp, vp, C.POINTER(SolveOpts), C.POINTER(SolveOpts), _ip, vp],
+                              C.c_int32),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)
@@ -119,7 +121,8 @@ def exported_symbols() -> List[str]:
             "pbng_default_adjoint_opts", "pbng_color", "pbng_workspace_create",
             "pbng_workspace_destroy", "pbng_workspace_info", "pbng_workspace_set_materials",
             "pbng_workspace_set_dirichlet", "pbng_solve", "pbng_residual", "pbng_adjoint",
-            "pbng_load", "pbng_store", "pbng_sweeps", "pbng_phase", "pbng_phase_bytes"]
+            "pbng_load", "pbng_store", "pbng_sweeps", "pbng_phase", "pbng_phase_bytes",
+            "pbng_autotune"]
 
 
 def _check(rc: int) -> int:
@@ -387,6 +390,16 @@ class Workspace:
     def phase(self, color_idx, opts: Optional[SolveOpts] = None, stream=None, **kw):
         o = opts if opts is not None else solve_opts(**kw)
         _check(lib().pbng_phase(self.handle, color_idx, C.byref(o), _stream(stream)))
+
+    def autotune(self, x, opts: Optional[SolveOpts] = None, stream=None, **kw):
+        """pbng_autotune: returns (tuned SolveOpts, lanes per colour)."""
+        self._check_x(x)
+        o = opts if opts is not None else solve_opts(**kw)
+        tuned = SolveOpts()
+        lanes = np.zeros(self.n_colors, np.int32)
+        _check(lib().pbng_autotune(self.handle, _ptr(x), C.byref(o), C.byref(tuned), _i(lanes),
+                                   _stream(stream)))
+        return tuned, lanes
 
     def phase_bytes(self, color_idx):
         b, v, k = C.c_int64(), C.c_int64(), C.c_int64()

@@ -277,3 +277,43 @@ def test_mixed_converges_below_fp32_storage_floor():
     assert out["f32"][1]["converged"] == 0
     res, en = ws.residual(x)
     assert res[0] <= 5e-6 * st["residual0"]
+
+
+@pytest.mark.parametrize("accel,kw", [("sor", dict(omega=1.6)),
+                                      ("chebyshev", dict(rho=0.95, gamma=1.7)),
+                                      ("none", dict())])
+def test_graph_replay_matches_plain_launches(accel, kw):
+    """Sweeps replayed from a captured HIP graph give the same bits as plain
+    launches (the graph only replays launches with identical arguments)."""
+    sc = S.gravity_beam(24, 6, 6, 1.0 / 5)
+    announce("graph replay vs plain %s" % accel)
+    stream = torch.cuda.Stream()
+    outs = []
+    with torch.cuda.stream(stream):
+        for spg in (0, 8, 6):
+            ws = workspace([sc], "f32")
+            x = dev_x(sc.initial_iterate(), "f32")
+            rc, st = ws.solve(x, max_sweeps=300, rel_tol=0.0, check_every=100, accel=accel,
+                              sweeps_per_graph=spg, stream=stream, **kw)
+            stream.synchronize()
+            outs.append(host(x))
+            assert st[0]["sweeps"] == 300
+    assert np.array_equal(outs[0], outs[1]) and np.array_equal(outs[0], outs[2])
+
+
+def test_autotune_then_solve_matches_oracle():
+    sc = S.twist_box(8, "nh", 1e4, 0.3, 60.0, 1.2, 0.01, seed=4)
+    announce("autotune twist8")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ws = workspace([sc], "f32")
+        x = dev_x(sc.initial_iterate(), "f32")
+        base = pbng.solve_opts(max_sweeps=40, rel_tol=0.0, check_every=40, accel="chebyshev",
+                               rho=0.95, gamma=1.7)
+        tuned, lanes = ws.autotune(x, base, stream=stream)
+        assert all(l in (1, 2, 4, 8, 16, 32, 64) for l in lanes)
+        assert tuned.lanes == 0 and tuned.sweeps_per_graph in (0, 2, 8, 32)
+        rc, st = ws.solve(x, tuned, stream=stream)
+        stream.synchronize()
+    xo, _, _ = oracle_solve(sc, 40, accel="chebyshev", rho=0.95, gamma=1.7)
+    assert rel_err(host(x), xo) <= 1e-5
