@@ -1,18 +1,23 @@
 """Benchmark of the PBNG hot path on one MI355X.
 
-Default workload: the 128x32x32-vertex cantilever beam (131,072 vertices,
+Headline workload: the 128x32x32-vertex cantilever beam (131,072 vertices,
 610,235 tets, Neo-Hookean E = 1e5, nu = 0.45, gravity at density 1000, x = 0
 face pinned), FP32 sweeps with FP64 residuals, SOR omega = 1.6 across
 sweeps, safeguarded local steps, run to 1e-5 relative residual or 2000
-sweeps.  One step = one whole solve from the initial iterate (sweeps,
-fused blend, FP64 residual checks), with the packed problem resident in HBM.
+sweeps.  One step = one whole solve from the initial iterate (sweeps with
+the fused blend, FP64 residual checks), with the packed problem resident in
+HBM.  Lanes per colour and sweeps per graph come from the library's
+autotuner, run before the timed region.
 
 Prints one JSON line: vertex updates per second over the timed steps, the
 roofline of the dominant kernel (the colour-phase vertex update) measured
-live with HIP events on the launch stream, and the FP64 oracle timed on the
-host cores on a bounded sample of the same workload.
+live with HIP events on the launch stream, the FP64 oracle timed on the host
+cores on a bounded sample, and two sub-reports: batched cubes (one batched
+solve against per-instance solves, time to 1e-5) and the differentiable
+cubes (forward and adjoint sweeps).
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -24,6 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "k_phase_beam_128x32x32_f32_counters.json")
+KERNEL_SOURCES = ["pbng_kernels.hip", "pbng_math.hpp", "pbng_internal.hpp"]
 
 
 def parse():
@@ -31,10 +38,11 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="beam", choices=["beam", "batched", "plain_f64"])
     ap.add_argument("--check-every", type=int, default=50)
-    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched and differentiable sub-reports")
     ap.add_argument("--cpu-sweeps", type=int, default=300)
     ap.add_argument("--roofline-sweeps", type=int, default=20)
     ap.add_argument("--max-sweeps", type=int, default=0,
@@ -42,34 +50,31 @@ def parse():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="MiB: run device-to-device copies of this size first, so that a "
                          "counter profile holds a plain copy kernel of known traffic")
+    ap.add_argument("--batched-subset", type=int, default=32,
+                    help="instances solved one by one for the per-instance comparison")
+    ap.add_argument("--diff-instances", type=int, default=64)
     return ap.parse_args()
 
 
-def workload(name):
-    from paper_2306_09021_amd import scenarios as S
-    if name == "beam":
-        sc = S.config_beam_f32()
-        # SOR omega = 1.6: the Chebyshev rho = 0.995 / relaxation 1.6 reading
-        # diverges on this beam in exact arithmetic (oracle and GPU agree)
-        opts = dict(max_sweeps=2000, rel_tol=1e-5, accel="sor", omega=1.6,
-                    safeguard="backtrack")
-        cfg = {"workload": "beam_128x32x32_neohookean_gravity", "vertices": sc.n_verts,
-               "tets": sc.n_tets, "free_vertices": sc.n_free, "model": "neo-hookean",
-               "E": 1e5, "nu": 0.45, "density": 1000.0, "accel": "sor omega=1.6",
-               "safeguard": "backtrack", "rel_tol": 1e-5, "max_sweeps": 2000}
-        return [sc], "f32", opts, cfg
-    if name == "plain_f64":
-        sc = S.config_plain_f64()
-        opts = dict(max_sweeps=200, rel_tol=0.0, accel="none", safeguard="backtrack")
-        cfg = {"workload": "cube_10x10x10_corotated_twist90_stretch1.3_f64", "vertices": sc.n_verts,
-               "tets": sc.n_tets, "sweeps": 200}
-        return [sc], "f64", opts, cfg
-    scs = S.config_batched()
-    opts = dict(max_sweeps=20000, rel_tol=1e-5, accel="chebyshev", rho=0.95, gamma=1.7,
-                safeguard="backtrack")
-    cfg = {"workload": "batched_256_cubes_4to32_corotated", "instances": len(scs),
-           "vertices": int(sum(s.n_verts for s in scs)), "tets": int(sum(s.n_tets for s in scs))}
-    return scs, "f32", opts, cfg
+def kernel_sources_sha256():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2306_09021_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch():
+    """HBM bytes per k_phase launch from the committed counter profile, or
+    None when the kernel sources changed since it was taken."""
+    try:
+        with open(COUNTERS) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return c.get("traffic_bytes_per_launch")
 
 
 def main():
@@ -81,8 +86,11 @@ def main():
         sys.exit(2)
     import torch
     from paper_2306_09021_amd import pbng
+    from paper_2306_09021_amd import scenarios as S
 
     torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()          # default priority; non-null so graphs can be captured
+    torch.cuda.set_stream(stream)
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -91,16 +99,26 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    scs, real, sopts, cfg = workload(args.workload)
+
+    sc = S.config_beam_f32()
+    # SOR omega = 1.6: the Chebyshev rho = 0.995 / relaxation 1.6 reading
+    # diverges on this beam in exact arithmetic (oracle and GPU agree)
+    sopts = dict(max_sweeps=2000, rel_tol=1e-5, accel="sor", omega=1.6, safeguard="backtrack")
     if args.max_sweeps > 0:
-        sopts = dict(sopts, max_sweeps=args.max_sweeps)
-    dt = torch.float32 if real == "f32" else torch.float64
-    ws = pbng.Workspace([pbng.problem_from_scenario(s) for s in scs], real=real)
-    x0 = torch.tensor(pbng.concat_positions([s.initial_iterate() for s in scs]), dtype=dt,
-                      device="cuda")
+        sopts["max_sweeps"] = args.max_sweeps
+    cfg = {"workload": "beam_128x32x32_neohookean_gravity", "vertices": sc.n_verts,
+           "tets": sc.n_tets, "free_vertices": sc.n_free, "model": "neo-hookean",
+           "E": 1e5, "nu": 0.45, "density": 1000.0, "accel": "sor omega=1.6",
+           "safeguard": "backtrack", "rel_tol": 1e-5, "max_sweeps": sopts["max_sweeps"],
+           "positions": "f32", "sweep_arithmetic": "f32", "residual": "f64"}
+    ws = pbng.Workspace([pbng.problem_from_scenario(sc)], real="f32")
+    x0 = torch.tensor(sc.initial_iterate(), dtype=torch.float32, device="cuda")
     x = x0.clone()
-    opts = pbng.solve_opts(check_every=args.check_every, lanes=args.lanes, **sopts)
-    stream = torch.cuda.current_stream()
+    opts = pbng.solve_opts(check_every=args.check_every, **sopts)
+    if not args.no_autotune:
+        opts, lanes = ws.autotune(x0, opts, stream=stream)
+        cfg["lanes_per_colour"] = [int(v) for v in lanes]
+        cfg["sweeps_per_graph"] = int(opts.sweeps_per_graph)
 
     def step():
         x.copy_(x0)
@@ -115,8 +133,7 @@ def main():
         rc, st = step()
         stats.append(st)
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    elapsed = t1 - t0
+    elapsed = time.perf_counter() - t0
     updates = sum(sum(s["vertex_updates"] for s in st) for st in stats)
     last = stats[-1]
     value = updates / elapsed
@@ -125,7 +142,7 @@ def main():
     # variant as the solve): HIP events on the launch stream bracket
     # back-to-back sweeps of launches, so the average launch duration is the
     # kernel time plus the (sub-microsecond) gaps between dependent launches
-    ws.load(x0)
+    ws.load(x0, stream=stream)
     n_col = ws.n_colors
     ws.sweeps(3, opts, stream=stream)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -138,22 +155,26 @@ def main():
     torch.cuda.synchronize()
     n_launch = args.roofline_sweeps * n_col
     avg_dur = ev0.elapsed_time(ev1) * 1e-3 / n_launch
-    accel = sopts.get("accel", "none") != "none"
     total_bytes = 0
     for c in range(n_col):
         b, v, k = ws.phase_bytes(c)
-        total_bytes += args.roofline_sweeps * (b + (48 * v if accel else 0))
+        total_bytes += args.roofline_sweeps * (b + 48 * v)
     avg_bytes = total_bytes / n_launch
     achieved = avg_bytes / avg_dur / 1e9
+    tr = traffic_per_launch()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": (int(tr) if tr is not None else None),
+                "traffic_note": "bytes per launch from rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0",
                 "kernel": "k_phase (colour-phase vertex update)",
-                "avg_launch_us": round(avg_dur * 1e6, 2), "avg_algorithmic_bytes": int(avg_bytes),
-                "launches_timed": n_launch}
+                "avg_launch_us": round(avg_dur * 1e6, 2),
+                "avg_algorithmic_bytes": int(avg_bytes), "launches_timed": n_launch}
 
-    cpu = None
-    if not args.no_cpu_baseline and args.workload == "beam":
-        cpu = cpu_baseline(scs[0], args.cpu_sweeps)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(sc, args.cpu_sweeps)
+    extras = {} if args.no_extras else {
+        "batched": batched_report(pbng, S, torch, stream, args.batched_subset),
+        "differentiable": differentiable_report(pbng, S, torch, stream, args.diff_instances),
+    }
 
     sweeps = max(s["sweeps"] for s in last)
     line = {
@@ -167,7 +188,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32" if real == "f32" else "f64",
+        "dtype": "f32",
         "data": "synthetic (seeded generator; no dataset)",
         "config": cfg,
         "sweeps_per_step": sweeps,
@@ -179,7 +200,124 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
+    line.update(extras)
     print(json.dumps(line))
+
+
+def batched_report(pbng, S, torch, stream, subset):
+    """Batched cubes (256, n ~ U{4..32}, corotated, MIXED: FP32 sweeps on
+    FP64 positions): one batched solve to 1e-5; then a seeded subset solved
+    once batched and once instance by instance."""
+    scs = S.config_batched()
+    so = dict(max_sweeps=20000, rel_tol=1e-5, check_every=100, accel="chebyshev", rho=0.95,
+              gamma=1.7, safeguard="backtrack")
+    out = {"instances": len(scs), "vertices": int(sum(s.n_verts for s in scs)),
+           "tets": int(sum(s.n_tets for s in scs)), "real": "mixed",
+           "accel": "chebyshev rho=0.95 gamma=1.7", "rel_tol": 1e-5, "max_sweeps": 20000}
+    ws = pbng.Workspace([pbng.problem_from_scenario(s) for s in scs], real="mixed")
+    x0 = torch.tensor(pbng.concat_positions([s.initial_iterate() for s in scs]),
+                      dtype=torch.float64, device="cuda")
+    opts = pbng.solve_opts(**so)
+    opts, _ = ws.autotune(x0, opts, stream=stream)
+    x = x0.clone()
+    ws.solve(x, opts, stream=stream)   # warm
+    x.copy_(x0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = ws.solve(x, opts, stream=stream)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    conv = [s for s in st if s["converged"]]
+    out.update({"wall_s": round(t, 3), "converged": len(conv),
+                "time_to_tol_all_converged_ms": round(max(s["time_to_tol_ms"] for s in conv), 1)
+                if conv else None,
+                "vertex_updates_per_s": round(sum(s["vertex_updates"] for s in st) / t, 1),
+                "not_converged_rel_residual": [round(s["rel_residual"], 8) for s in st
+                                               if not s["converged"]]})
+    # subset: batched vs one instance at a time
+    rng = np.random.default_rng(44)
+    idx = sorted(rng.choice(len(scs), size=min(subset, len(scs)), replace=False).tolist())
+    sub = [scs[i] for i in idx]
+    wsb = pbng.Workspace([pbng.problem_from_scenario(s) for s in sub], real="mixed")
+    xb0 = torch.tensor(pbng.concat_positions([s.initial_iterate() for s in sub]),
+                       dtype=torch.float64, device="cuda")
+    xb = xb0.clone()
+    wsb.solve(xb, opts, stream=stream)
+    xb.copy_(xb0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rcb, stb = wsb.solve(xb, opts, stream=stream)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    singles = [pbng.Workspace([pbng.problem_from_scenario(s)], real="mixed") for s in sub]
+    xs0 = [torch.tensor(s.initial_iterate(), dtype=torch.float64, device="cuda") for s in sub]
+    plain = pbng.solve_opts(**so)
+    xs = [v.clone() for v in xs0]
+    for w, v in zip(singles, xs):
+        w.solve(v, plain, stream=stream)
+    for v, v0 in zip(xs, xs0):
+        v.copy_(v0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = []
+    for w, v in zip(singles, xs):
+        rcs, s1 = w.solve(v, plain, stream=stream)
+        sts.append(s1[0])
+    torch.cuda.synchronize()
+    ts = time.perf_counter() - t0
+    out["subset"] = {"instances": len(sub), "seed": 44,
+                     "batched_wall_s": round(tb, 4),
+                     "per_instance_wall_s": round(ts, 4),
+                     "speedup": round(ts / tb, 2),
+                     "batched_converged": int(sum(s["converged"] for s in stb)),
+                     "per_instance_converged": int(sum(s["converged"] for s in sts))}
+    return out
+
+
+def differentiable_report(pbng, S, torch, stream, n_inst):
+    """Differentiable cubes (32^3, Neo-Hookean, per-tet Lame, MIXED): forward
+    solve to 5e-6 and the adjoint solve to 1e-6 for all instances at once."""
+    scs = S.config_differentiable(n_inst)
+    ws = pbng.Workspace([pbng.problem_from_scenario(s) for s in scs], real="mixed")
+    x0 = torch.tensor(pbng.concat_positions([s.initial_iterate() for s in scs]),
+                      dtype=torch.float64, device="cuda")
+    T = torch.tensor(pbng.concat_positions([s.loss_target for s in scs]), dtype=torch.float64,
+                     device="cuda")
+    free = np.ones((x0.shape[0], 1))
+    off = 0
+    for s in scs:
+        free[off + s.dirichlet_idx] = 0.0
+        off += s.n_verts
+    freet = torch.tensor(free, dtype=torch.float64, device="cuda")
+    so = pbng.solve_opts(max_sweeps=20000, rel_tol=5e-6, check_every=100, accel="chebyshev",
+                         rho=0.98, gamma=1.0, safeguard="backtrack")
+    so, _ = ws.autotune(x0, so, stream=stream)
+    ao = pbng.adjoint_opts(max_sweeps=20000, rel_tol=1e-6, check_every=100, accel="chebyshev",
+                           rho=0.98, gamma=1.0)
+    x = x0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rc, st = ws.solve(x, so, stream=stream)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    g = (2.0 * (x - T) * freet).contiguous()
+    t0 = time.perf_counter()
+    rca, out, sta = ws.adjoint(x, g, ao, stream=stream, want=("xd", "mu", "lam"))
+    torch.cuda.synchronize()
+    ta = time.perf_counter() - t0
+    fw_upd = sum(s["vertex_updates"] for s in st)
+    ad_upd = sum(s["vertex_updates"] for s in sta)
+    return {"instances": len(scs), "vertices": int(x0.shape[0]), "real": "mixed",
+            "forward": {"rel_tol": 5e-6, "wall_s": round(tf, 3),
+                        "converged": int(sum(s["converged"] for s in st)),
+                        "max_sweeps_used": int(max(s["sweeps"] for s in st)),
+                        "max_rel_residual": max(s["rel_residual"] for s in st),
+                        "vertex_updates_per_s": round(fw_upd / tf, 1)},
+            "adjoint": {"rel_tol": 1e-6, "wall_s": round(ta, 3),
+                        "converged": int(sum(s["converged"] for s in sta)),
+                        "max_sweeps_used": int(max(s["sweeps"] for s in sta)),
+                        "max_rel_residual": max(s["rel_residual"] for s in sta),
+                        "vertex_updates_per_s": round(ad_upd / ta, 1)}}
 
 
 def cpu_baseline(sc, sweeps):

@@ -330,6 +330,14 @@ struct pbng_workspace {
     int ncol = 0;
     int n_wc = 0, n_planes = 0, nd = 0;
     bool any_wc = false;
+    // The safeguard cannot reject a step here (so the plain kernel gives the
+    // same result): no contact planes, and either the corotated model (its
+    // modified Hessian is the Hessian of a majoriser of the local energy) or
+    // the Neo-Hookean model with lambda >= mu in every tet (then 2 A - H is
+    // positive semidefinite and the full step always lowers the exactly
+    // quadratic local energy).  Weak constraints are exact quadratics inside
+    // A and do not change either argument.
+    bool safeguard_inactive = false;
     // general sweep kernel: batched instances, weak constraints or planes
     bool general() const { return any_wc || n_inst > 1; }
     int device = 0;
@@ -498,6 +506,11 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
         }
     }
     if (ws->ncol > 64) fail(PBNG_ECOLOR, "more than 64 colours");
+    {
+        bool lam_ge_mu = true;
+        for (int64_t e = 0; e < nt; ++e) lam_ge_mu = lam_ge_mu && lam[e] >= mu[e];
+        ws->safeguard_inactive = ws->n_planes == 0 && (ws->model == PBNG_COROTATED || lam_ge_mu);
+    }
 
     // internal order
     std::vector<int> inst_of(nv);
@@ -842,6 +855,11 @@ void residual_internal(pbng_workspace* ws, const void* X, double* r_out, hipStre
     for (int q = 0; q < ws->n_inst; ++q) ws->hbuf[q] = std::sqrt(ws->hbuf[q]);
 }
 
+bool safe_effective(const pbng_workspace* ws, const pbng_solve_opts* o)
+{
+    return o->safeguard == PBNG_SAFEGUARD_BACKTRACK && !ws->safeguard_inactive;
+}
+
 // Lanes per vertex for colour c: the requested power of two, or (0) the
 // workspace's automatic choice for that colour.
 int pick_lanes(const pbng_workspace* ws, int requested, int c)
@@ -889,7 +907,7 @@ void launch_sweep(pbng_workspace* ws, const pbng_solve_opts* o, double omega, do
     const SweepArgs<R, PR> a = sweep_args<R, PR>(ws, omega, gamma, o->max_halvings);
     for (int c = 0; c < ws->ncol; ++c)
         hipchk(launch_phase<R, PR>(a, ws->model, pick_lanes(ws, o->lanes, c), accel,
-                               o->safeguard == PBNG_SAFEGUARD_BACKTRACK, ws->general(), ws->col_ptr[c],
+                               safe_effective(ws, o), ws->general(), ws->col_ptr[c],
                                ws->col_ptr[c + 1], s),
                "sweep launch");
     if (accel) std::swap(ws->W.p, ws->N.p);
@@ -1245,7 +1263,7 @@ void autotune_t(pbng_workspace* ws, const void* x, const pbng_solve_opts* o, pbn
     reload();
     Events ev;
     const bool accel = o->accel != PBNG_ACCEL_NONE;
-    const bool safe = o->safeguard == PBNG_SAFEGUARD_BACKTRACK;
+    const bool safe = safe_effective(ws, o);
     const SweepArgs<R, PR> a = sweep_args<R, PR>(ws, 1.0, 1.0, o->max_halvings);
     for (int c = 0; c < ws->ncol; ++c) {
         const int vb = ws->col_ptr[c], ve = ws->col_ptr[c + 1];
@@ -1613,7 +1631,7 @@ int32_t pbng_phase(pbng_workspace* ws, int32_t color, const pbng_solve_opts* o, 
         if (color < 0 || color >= ws->ncol) fail(PBNG_EINVAL, "colour out of range");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
         const int lanes = pick_lanes(ws, o->lanes, color);
-        const bool safe = o->safeguard == PBNG_SAFEGUARD_BACKTRACK;
+        const bool safe = safe_effective(ws, o);
         const bool accel = o->accel != PBNG_ACCEL_NONE;
         // with acceleration the phase blends with omega = 1 and gamma = 1 and
         // does not advance the ring (measurement of the fused kernel only)

@@ -317,3 +317,16 @@ def test_autotune_then_solve_matches_oracle():
         stream.synchronize()
     xo, _, _ = oracle_solve(sc, 40, accel="chebyshev", rho=0.95, gamma=1.7)
     assert rel_err(host(x), xo) <= 1e-5
+
+
+def test_neohookean_safeguard_active_parity():
+    """nu = 0.05 gives lambda < mu, where the Neo-Hookean step can overshoot
+    and the backtracking safeguard runs (and may halve steps)."""
+    sc = S.twist_box(6, "nh", 1e4, 0.05, 90.0, 2.0, 0.01, seed=6)
+    for real, tol in (("f64", 1e-10), ("f32", 1e-5)):
+        announce("nh nu=0.05 stretch 2 safeguard %s" % real)
+        xg, stg, _ = _run_gpu(sc, real, 40, safeguard="backtrack")
+        xo, sto, _ = oracle_solve(sc, 40, safeguard="backtrack")
+        print(real, "rejected", stg["rejected"], "oracle rejected", sto["rejected"], "halvings",
+              sto["halvings"])
+        assert rel_err(xg, xo) <= tol

@@ -394,3 +394,21 @@ def test_adjoint_parameter_gradients_by_linearity():
             op2 = O.OracleProblem(**{**op.__dict__, which: arr})
             dg = O.energy_gradient(op2, x) - g0
             assert abs(-(lam_vec * dg).sum() - ref[e]) <= 1e-9 * max(1.0, abs(ref[e]))
+
+
+def test_safeguard_is_inactive_where_the_step_is_a_descent_step():
+    """The corotated modified Hessian is the Hessian of a majoriser of the
+    local energy, and for Neo-Hookean with lambda >= mu the full step is a
+    descent step of the exactly quadratic local energy: the backtracking
+    safeguard never halves.  With lambda < mu (nu = 0.1) it does."""
+    for model, nu in (("corotated", 0.3), ("corotated", 0.45), ("nh", 0.3), ("nh", 0.45)):
+        sc = S.twist_box(6, model, 1e4, nu, 90.0, 1.3, 0.01, seed=6)
+        op = O.make_problem(sc)
+        col, _ = O.color(op)
+        _, st = O.solve(op, col, sc.initial_iterate(), max_sweeps=30, safeguard="backtrack")
+        assert st["halvings"] == 0 and st["rejected"] == 0, (model, nu, st)
+    sc = S.twist_box(6, "nh", 1e4, 0.05, 90.0, 2.0, 0.01, seed=6)
+    op = O.make_problem(sc)
+    col, _ = O.color(op)
+    _, st = O.solve(op, col, sc.initial_iterate(), max_sweeps=30, safeguard="backtrack")
+    assert st["halvings"] > 0
