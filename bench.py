@@ -259,24 +259,34 @@ def batched_report(pbng, S, torch, stream, subset):
         v.copy_(v0)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    sts = []
+    sts, walls = [], []
     for w, v in zip(singles, xs):
+        t1 = time.perf_counter()
         rcs, s1 = w.solve(v, plain, stream=stream)
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t1)
         sts.append(s1[0])
-    torch.cuda.synchronize()
     ts = time.perf_counter() - t0
+    # instances that reach the tolerance in both runs (an instance stuck at
+    # its FP32-arithmetic floor runs to the sweep cap in both and would
+    # dominate both times)
+    both = [i for i in range(len(sub)) if stb[i]["converged"] and sts[i]["converged"]]
+    t_batched = max(stb[i]["time_to_tol_ms"] for i in both) / 1e3 if both else None
+    t_single = sum(walls[i] for i in both) if both else None
     out["subset"] = {"instances": len(sub), "seed": 44,
-                     "batched_wall_s": round(tb, 4),
-                     "per_instance_wall_s": round(ts, 4),
-                     "speedup": round(ts / tb, 2),
-                     "batched_converged": int(sum(s["converged"] for s in stb)),
-                     "per_instance_converged": int(sum(s["converged"] for s in sts))}
+                     "converged_in_both": len(both),
+                     "batched_time_to_tol_s": round(t_batched, 4) if both else None,
+                     "per_instance_time_to_tol_s": round(t_single, 4) if both else None,
+                     "speedup_time_to_tol": round(t_single / t_batched, 2) if both else None,
+                     "batched_wall_s_incl_capped": round(tb, 4),
+                     "per_instance_wall_s_incl_capped": round(ts, 4)}
     return out
 
 
 def differentiable_report(pbng, S, torch, stream, n_inst):
     """Differentiable cubes (32^3, Neo-Hookean, per-tet Lame, MIXED): forward
-    solve to 5e-6 and the adjoint solve to 1e-6 for all instances at once."""
+    solve and adjoint solve to 1e-5 (above their FP32-arithmetic floors) for
+    all instances at once."""
     scs = S.config_differentiable(n_inst)
     ws = pbng.Workspace([pbng.problem_from_scenario(s) for s in scs], real="mixed")
     x0 = torch.tensor(pbng.concat_positions([s.initial_iterate() for s in scs]),
@@ -289,10 +299,10 @@ def differentiable_report(pbng, S, torch, stream, n_inst):
         free[off + s.dirichlet_idx] = 0.0
         off += s.n_verts
     freet = torch.tensor(free, dtype=torch.float64, device="cuda")
-    so = pbng.solve_opts(max_sweeps=20000, rel_tol=5e-6, check_every=100, accel="chebyshev",
+    so = pbng.solve_opts(max_sweeps=20000, rel_tol=1e-5, check_every=100, accel="chebyshev",
                          rho=0.98, gamma=1.0, safeguard="backtrack")
     so, _ = ws.autotune(x0, so, stream=stream)
-    ao = pbng.adjoint_opts(max_sweeps=20000, rel_tol=1e-6, check_every=100, accel="chebyshev",
+    ao = pbng.adjoint_opts(max_sweeps=20000, rel_tol=1e-5, check_every=100, accel="chebyshev",
                            rho=0.98, gamma=1.0)
     x = x0.clone()
     torch.cuda.synchronize()
@@ -308,12 +318,12 @@ def differentiable_report(pbng, S, torch, stream, n_inst):
     fw_upd = sum(s["vertex_updates"] for s in st)
     ad_upd = sum(s["vertex_updates"] for s in sta)
     return {"instances": len(scs), "vertices": int(x0.shape[0]), "real": "mixed",
-            "forward": {"rel_tol": 5e-6, "wall_s": round(tf, 3),
+            "forward": {"rel_tol": 1e-5, "wall_s": round(tf, 3),
                         "converged": int(sum(s["converged"] for s in st)),
                         "max_sweeps_used": int(max(s["sweeps"] for s in st)),
                         "max_rel_residual": max(s["rel_residual"] for s in st),
                         "vertex_updates_per_s": round(fw_upd / tf, 1)},
-            "adjoint": {"rel_tol": 1e-6, "wall_s": round(ta, 3),
+            "adjoint": {"rel_tol": 1e-5, "wall_s": round(ta, 3),
                         "converged": int(sum(s["converged"] for s in sta)),
                         "max_sweeps_used": int(max(s["sweeps"] for s in sta)),
                         "max_rel_residual": max(s["rel_residual"] for s in sta),
