@@ -174,6 +174,7 @@ def main():
     extras = {} if args.no_extras else {
         "batched": batched_report(pbng, S, torch, stream, args.batched_subset),
         "differentiable": differentiable_report(pbng, S, torch, stream, args.diff_instances),
+        "muscles": muscles_report(pbng, S, torch, stream),
     }
 
     sweeps = max(s["sweeps"] for s in last)
@@ -328,6 +329,34 @@ def differentiable_report(pbng, S, torch, stream, n_inst):
                         "max_sweeps_used": int(max(s["sweeps"] for s in sta)),
                         "max_rel_residual": max(s["rel_residual"] for s in sta),
                         "vertex_updates_per_s": round(ad_upd / ta, 1)}}
+
+
+def muscles_report(pbng, S, torch, stream):
+    """Muscle stand-in (8 ellipsoids, 320k vertices, per-tet E, binding
+    springs, ground contact): 1000 Chebyshev sweeps in FP32 and MIXED."""
+    sc = S.config_muscles()
+    out = {"vertices": sc.n_verts, "tets": sc.n_tets, "springs": int(sc.wc_ptr.size - 1),
+           "accel": "chebyshev rho=0.95 gamma=1.7", "sweeps": 1000}
+    for real in ("f32", "mixed"):
+        ws = pbng.Workspace([pbng.problem_from_scenario(sc)], real=real)
+        dt = torch.float32 if real == "f32" else torch.float64
+        x0 = torch.tensor(sc.initial_iterate(), dtype=dt, device="cuda")
+        so = pbng.solve_opts(max_sweeps=1000, rel_tol=0.0, check_every=100, accel="chebyshev",
+                             rho=0.95, gamma=1.7, safeguard="backtrack")
+        so, _ = ws.autotune(x0, so, stream=stream)
+        x = x0.clone()
+        ws.solve(x, so, stream=stream)
+        x.copy_(x0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc, st = ws.solve(x, so, stream=stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        out[real] = {"colors": st[0]["n_colors"], "wall_s": round(t, 4),
+                     "vertex_updates_per_s": round(st[0]["vertex_updates"] / t, 1),
+                     "rel_residual_fp64": st[0]["rel_residual"],
+                     "safeguard_rejections": st[0]["rejected"]}
+    return out
 
 
 def cpu_baseline(sc, sweeps):

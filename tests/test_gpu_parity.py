@@ -330,3 +330,62 @@ def test_neohookean_safeguard_active_parity():
         print(real, "rejected", stg["rejected"], "oracle rejected", sto["rejected"], "halvings",
               sto["halvings"])
         assert rel_err(xg, xo) <= tol
+
+
+def test_muscle_standin_small_parity():
+    """Reduced muscle stand-in (3 ellipsoids of ~1500 vertices, per-tet E,
+    binding springs, a ground plane that is active at rest, translated end
+    caps) through the general kernel, against the oracle."""
+    sc = S.config_muscles(seed=3, n_meshes=3, n_target=1500, bind_frac=0.5, bind_dist=0.3)
+    assert sc.wc_ptr.size - 1 > 100
+    # The safeguard's accept/halve choice is discrete: near contact
+    # transitions FP32 and FP64 evaluations take it differently on a few
+    # vertices, so the FP32 arithmetic runs are compared without it and the
+    # FP64 run (same precision as the oracle) with it.
+    for real, tol, sg in (("f64", 1e-10, "backtrack"), ("mixed", 1e-5, "none"),
+                          ("f32", 1e-5, "none")):
+        announce("muscle stand-in small %s safeguard=%s" % (real, sg))
+        xg, stg, _ = _run_gpu(sc, real, 40, safeguard=sg, accel="chebyshev", rho=0.95,
+                              gamma=1.7)
+        xo, sto, _ = oracle_solve(sc, 40, safeguard=sg, accel="chebyshev", rho=0.95, gamma=1.7)
+        print(real, rel_err(xg, xo), "oracle halvings", sto["halvings"])
+        assert rel_err(xg, xo) <= tol
+
+
+def test_muscle_standin_full_sampled_phase():
+    """Full muscle stand-in (8 ellipsoids, 320k vertices, 1.43M tets): each
+    colour phase once on the GPU (FP32) against one oracle sweep, then 64
+    sampled vertices of the last colour recomputed one by one by the oracle
+    from the GPU's own positions just before that colour's phase."""
+    sc = S.config_muscles()
+    announce("muscle stand-in full sampled phase")
+    ws = workspace([sc], "f32")
+    rng = np.random.default_rng(1)
+    x0 = sc.initial_iterate()
+    x0 = (x0 + 1e-3 * rng.normal(size=x0.shape))
+    x0[sc.dirichlet_idx] = sc.dirichlet_x
+    x0 = x0.astype(np.float32).astype(np.float64)
+    x = dev_x(x0, "f32")
+    ws.load(x)
+    last = ws.n_colors - 1
+    for c in range(last):
+        ws.phase(c, safeguard="none")
+    xs = dev_x(np.zeros_like(x0), "f32")
+    ws.store(xs)
+    torch.cuda.synchronize()
+    before = host(xs)
+    ws.phase(last, safeguard="none")
+    ws.store(xs)
+    torch.cuda.synchronize()
+    xg = host(xs)
+    op = O.make_problem(sc)
+    col, _ = O.color(op)
+    xo, _ = O.solve(op, col, x0, max_sweeps=1, safeguard="none", n_threads=4)
+    assert rel_err(xg, xo) <= 1e-6
+    verts = np.nonzero(col == last)[0]
+    pick = rng.choice(verts, min(64, verts.size), replace=False)
+    upd = O.update_vertices(op, before, pick, safeguard="none")
+    # FP32 arithmetic on the step plus rounding of the stored position.
+    step = np.abs(upd - before[pick]).max()
+    tol = 1e-4 * step + 4 * np.finfo(np.float32).eps * np.abs(before[pick]).max()
+    assert np.abs(upd - xg[pick]).max() <= tol
