@@ -351,7 +351,7 @@ struct pbng_workspace {
 
     // sweep data
     Dev W, P, N, Wres;
-    Dev j1, j2, j3, m, vmu, vlam, vptr, fext, vinst, active, rejected;
+    Dev jv, ma, mb, mc, vmu, Sv, flag, vptr, fext, vinst, active, rejected;
     Dev wvptr, wv_c, wv_s, wc_ptr, wc_vert, wc_w, wc_K, plane_ptr, planes;
     // FP64 data
     Dev tet, geo, vp, ebuf, tet_eidx, vorder, vert_eidx, rvptr, rv, fext64, vinst_all;
@@ -438,6 +438,38 @@ SegPlan make_plan(const std::vector<int64_t>& seg, Dev& cb, Dev& ce, Dev& qp, De
     P.partial = part.as<double>();
     P.n_chunks = int(b.size());
     return P;
+}
+
+template <class R>
+VisitBuild<R> visit_build(pbng_workspace* ws)
+{
+    VisitBuild<R> b;
+    b.geo = ws->geo.as<TetGeo>();
+    b.rv = ws->rv.as<int>();
+    b.vptr = ws->vptr.as<int>();
+    b.n_free = int(ws->nfree);
+    b.model = ws->model == PBNG_NEOHOOKEAN ? 0 : 1;
+    b.jv = ws->jv.as<int4>();
+    b.ma = ws->ma.as<typename R4t<R>::T>();
+    b.mb = ws->mb.as<typename R4t<R>::T>();
+    b.mc = ws->mc.as<typename R2t<R>::T>();
+    b.vmu = ws->vmu.as<R>();
+    b.Sv = ws->Sv.as<R>();
+    return b;
+}
+
+// Visit records from the tet geometry; with material arrays, first the
+// new mu and lambda into the geometry.
+hipError_t build_visits(pbng_workspace* ws, const double* mu, const double* lam, hipStream_t s)
+{
+    if (ws->math64()) {
+        if (mu) return launch_set_materials<double>(mu, lam, ws->geo.as<TetGeo>(), int(ws->nt),
+                                                    visit_build<double>(ws), s);
+        return launch_build_visits<double>(visit_build<double>(ws), s);
+    }
+    if (mu) return launch_set_materials<float>(mu, lam, ws->geo.as<TetGeo>(), int(ws->nt),
+                                               visit_build<float>(ws), s);
+    return launch_build_visits<float>(visit_build<float>(ws), s);
 }
 
 void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const int32_t* colors_in)
@@ -540,7 +572,6 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     // Dirichlet vertices (FP64 gathers only)
     std::vector<int> rvptr(nv + 1, 0), rv;
     std::vector<int> J1, J2, J3;
-    std::vector<double> M9, VMU, VLAM;
     rv.reserve(4 * nt);
     for (int64_t k = 0; k < nv; ++k) {
         const int gv = order[k];
@@ -553,23 +584,14 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
             const int slot = I.tlist[s] & 3;
             rv.push_back(int(e * 4 + slot));
             if (k < nfree) {
+                // the other three vertices in increasing slot order (the
+                // device record build takes their gradients in this order)
                 int others[3], no = 0;
-                double mrow[9];
-                for (int j = 0; j < 4; ++j) {
-                    if (j == slot) continue;
-                    others[no] = int_of[vo + ps[q].tets[4 * (e - to) + j]];
-                    // dN_j: row j-1 of Dm^{-1}, or minus the sum of the rows for j = 0
-                    for (int c = 0; c < 3; ++c)
-                        mrow[3 * no + c] = (j == 0) ? -(dminv[9 * e + c] + dminv[9 * e + 3 + c] + dminv[9 * e + 6 + c])
-                                                    : dminv[9 * e + 3 * (j - 1) + c];
-                    ++no;
-                }
+                for (int j = 0; j < 4; ++j)
+                    if (j != slot) others[no++] = int_of[vo + ps[q].tets[4 * (e - to) + j]];
                 J1.push_back(others[0]);
                 J2.push_back(others[1]);
                 J3.push_back(others[2]);
-                for (int c = 0; c < 9; ++c) M9.push_back(mrow[c]);
-                VMU.push_back(V0[e] * mu[e]);
-                VLAM.push_back(V0[e] * lam[e]);
             }
         }
         rvptr[k + 1] = int(rv.size());
@@ -578,10 +600,19 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     ws->nvis_all = int64_t(rv.size());
     ws->mean_valence = nfree > 0 ? double(ws->nvis) / double(nfree) : 0.0;
 
-    // SoA [9][nvis]
-    std::vector<double> Msoa(9 * ws->nvis);
-    for (int64_t k = 0; k < ws->nvis; ++k)
-        for (int c = 0; c < 9; ++c) Msoa[c * ws->nvis + k] = M9[9 * k + c];
+    // packed visit streams (jv.xyz here; the rest is built on the device
+    // from the FP64 tet geometry)
+    const size_t rec_max = ws->math64() ? sizeof(double4) : sizeof(float4);
+    const size_t pos_max = ws->pos64() ? sizeof(double4) : sizeof(float4);
+    if (double(ws->nvis) * rec_max >= 4294967296.0 || double(nv) * pos_max >= 4294967296.0)
+        fail(PBNG_EUNSUPPORTED, "workspace too large: visit streams and position arrays must stay "
+                                "under 4 GiB each");
+    std::vector<int32_t> JV(4 * ws->nvis, 0);
+    for (int64_t k = 0; k < ws->nvis; ++k) {
+        JV[4 * k] = J1[k];
+        JV[4 * k + 1] = J2[k];
+        JV[4 * k + 2] = J3[k];
+    }
 
     // algorithmic bytes per colour phase
     ws->phase_bytes.assign(ws->ncol, 0);
@@ -716,12 +747,15 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     };
     std::vector<int> vptr_free(rvptr.begin(), rvptr.begin() + nfree + 1);
     ws->vptr.upload(vptr_free);
-    ws->j1.upload(J1);
-    ws->j2.upload(J2);
-    ws->j3.upload(J3);
-    upR(ws->m, Msoa);
-    upR(ws->vmu, VMU);
-    upR(ws->vlam, VLAM);
+    ws->jv.upload(JV);
+    {
+        const size_t r = ws->math64() ? sizeof(double) : sizeof(float);
+        ws->ma.alloc(size_t(ws->nvis) * 4 * r);
+        ws->mb.alloc(size_t(ws->nvis) * 4 * r);
+        ws->mc.alloc(ws->model == PBNG_COROTATED ? size_t(ws->nvis) * 2 * r : 0);
+        ws->vmu.alloc(ws->math64() ? size_t(ws->nvis) * r : 0);
+        ws->Sv.alloc(size_t(nfree) * r);
+    }
     upR(ws->fext, fext_free);
     std::vector<int> vinst_free(vinst_all.begin(), vinst_all.begin() + nfree);
     ws->vinst.upload(vinst_free);
@@ -766,6 +800,8 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     hipchk(hipHostMalloc((void**)&ws->hbuf, 2 * n * sizeof(double)), "hipHostMalloc");
     hipchk(hipHostMalloc((void**)&ws->hact, n * sizeof(int)), "hipHostMalloc");
     hipchk(hipDeviceSynchronize(), "upload");
+    hipchk(build_visits(ws, nullptr, nullptr, nullptr), "visit records");
+    hipchk(hipDeviceSynchronize(), "visit records");
 }
 
 template <class R, class PR>
@@ -778,13 +814,12 @@ SweepArgs<R, PR> sweep_args(pbng_workspace* ws, double omega, double gamma, int 
     a.P = ws->P.as<P4>();
     a.N = ws->N.as<P4>();
     a.vptr = ws->vptr.as<int>();
-    a.j1 = ws->j1.as<int>();
-    a.j2 = ws->j2.as<int>();
-    a.j3 = ws->j3.as<int>();
-    a.m = ws->m.as<R>();
+    a.jv = ws->jv.as<int4>();
+    a.ma = ws->ma.as<typename R4t<R>::T>();
+    a.mb = ws->mb.as<typename R4t<R>::T>();
+    a.mc = ws->mc.as<typename R2t<R>::T>();
     a.vmu = ws->vmu.as<R>();
-    a.vlam = ws->vlam.as<R>();
-    a.nvis = ws->nvis;
+    a.Sv = ws->Sv.as<R>();
     a.fext = ws->fext.as<R4>();
     a.vinst = ws->vinst.as<int>();
     a.active = ws->active.as<int>();
@@ -1089,13 +1124,12 @@ AdjArgs<R, PR> adj_args(pbng_workspace* ws, double omega, double gamma)
     a.N = ws->LN.as<P4>();
     a.B = ws->B.as<P4>();
     a.vptr = ws->vptr.as<int>();
-    a.j1 = ws->j1.as<int>();
-    a.j2 = ws->j2.as<int>();
-    a.j3 = ws->j3.as<int>();
-    a.m = ws->m.as<R>();
+    a.jv = ws->jv.as<int4>();
+    a.ma = ws->ma.as<typename R4t<R>::T>();
+    a.mb = ws->mb.as<typename R4t<R>::T>();
+    a.mc = ws->mc.as<typename R2t<R>::T>();
     a.vmu = ws->vmu.as<R>();
-    a.vlam = ws->vlam.as<R>();
-    a.nvis = ws->nvis;
+    a.Sv = ws->Sv.as<R>();
     a.vinst = ws->vinst.as<int>();
     a.wvptr = ws->wvptr.as<int>();
     a.wv_c = ws->wv_c.as<int>();
@@ -1458,14 +1492,17 @@ int32_t pbng_workspace_set_materials(pbng_workspace* ws, const double* mu_dev, c
         check_ws(ws);
         if (!mu_dev || !lambda_dev) fail(PBNG_EINVAL, "null material arrays");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        if (ws->math64())
-            hipchk(launch_set_materials<double>(mu_dev, lambda_dev, ws->geo.as<TetGeo>(), int(ws->nt), ws->rv.as<int>(),
-                                                int(ws->nvis), ws->vmu.as<double>(), ws->vlam.as<double>(), s),
-                   "set materials");
-        else
-            hipchk(launch_set_materials<float>(mu_dev, lambda_dev, ws->geo.as<TetGeo>(), int(ws->nt), ws->rv.as<int>(),
-                                               int(ws->nvis), ws->vmu.as<float>(), ws->vlam.as<float>(), s),
-                   "set materials");
+        hipchk(build_visits(ws, mu_dev, lambda_dev, s), "set materials");
+        // the Neo-Hookean step is a descent step without the safeguard only
+        // while lambda >= mu in every tet: re-check on the device
+        if (ws->model == PBNG_NEOHOOKEAN) {
+            if (!ws->flag.p) ws->flag.alloc(sizeof(int));
+            hipchk(launch_lam_ge_mu(mu_dev, lambda_dev, int(ws->nt), ws->flag.as<int>(), s), "material check");
+            int h = 0;
+            hipchk(hipMemcpyAsync(&h, ws->flag.p, sizeof(int), hipMemcpyDeviceToHost, s), "material check");
+            hipchk(hipStreamSynchronize(s), "material check");
+            ws->safeguard_inactive = ws->n_planes == 0 && h != 0;
+        }
         return PBNG_OK;
     });
 }

@@ -7,13 +7,17 @@
 // so the order inside a colour does not change any computed value.
 //
 // Per-visit records (one per (free vertex i, incident tet e) pair, CSR by
-// internal vertex through vptr) are structure-of-arrays so that a wave's
-// lanes read consecutive addresses:
-//   j1, j2, j3      internal indices of the other three vertices of e
-//   m[9]            rows dN_j1, dN_j2, dN_j3 of the rest-state shape-function
-//                   gradients (so F = sum (x_j - x_i) dN_j^T)
-//   vmu, vlam       V0_e mu_e and V0_e lambda_e
-// In float: 3*4 + 11*4 = 56 bytes per visit.
+// internal vertex through vptr) are four packed streams indexed by visit k,
+// so that a wave reads each stream with one wide, coalesced load per lane:
+//   jv[k] = {j1, j2, j3, w}   internal indices of the other three vertices of
+//                              e; in FP32 workspaces w holds the bits of V0 mu
+//   ma[k] = {m0, m1, m2, m3}  m[9]: rows dN_j1, dN_j2, dN_j3 of the rest-state
+//   mb[k] = {m4, m5, m6, m7}  shape-function gradients (so that
+//   mc[k] = {m8, V0 lambda}   F = sum (x_j - x_i) dN_j^T)
+//   vmu[k] = V0 mu             FP64 workspaces only
+// In float: 16 + 16 + 16 + 8 = 56 bytes per visit.  Kernels address every
+// stream with 32-bit byte offsets; the host rejects workspaces whose streams
+// exceed 4 GiB.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -32,6 +36,16 @@ template <>
 struct R4t<double> {
     using T = double4;
 };
+template <class R>
+struct R2t;
+template <>
+struct R2t<float> {
+    using T = float2;
+};
+template <>
+struct R2t<double> {
+    using T = double2;
+};
 
 // Geometry of a tet for the FP64 passes: Dm^{-1} (row-major), V0, mu, lambda.
 struct TetGeo {
@@ -48,14 +62,14 @@ struct SweepArgs {
     P4* W;                 // working iterate (Gauss-Seidel, in place)
     P4* P;                 // x^{l-1}                (acceleration only)
     P4* N;                 // x^{l+1} being blended  (acceleration only)
+    using R2 = typename R2t<R>::T;
     const int* vptr;       // [n_free + 1]
-    const int* j1;
-    const int* j2;
-    const int* j3;
-    const R* m;            // [9][n_visits]
-    const R* vmu;
-    const R* vlam;
-    int64_t nvis;
+    const int4* jv;        // [n_visits] packed visit records (see above)
+    const R4* ma;
+    const R4* mb;
+    const R2* mc;
+    const R* vmu;          // FP64 only
+    const R* Sv;           // [n_free] sum V0 mu |dN_i|^2 per vertex
     const R4* fext;        // [n_free] lumped external force
     const int* vinst;      // [n_free] instance of each free vertex
     const int* active;     // [n_inst] 1 while the instance iterates
@@ -140,9 +154,31 @@ hipError_t launch_adjoint_assembly(const ResArgs<R>& a, const typename R4t<R>::T
                                    hipStream_t s);
 hipError_t launch_segsum(const double* vals, const SegPlan& plan, int n_inst, double* out,
                          hipStream_t s);
+// Visit-record build from the FP64 tet geometry (at workspace creation and
+// after every material update): jv[k].w or vmu[k], ma, mb, mc and the
+// per-vertex sums Sv.
+template <class R>
+struct VisitBuild {
+    const TetGeo* geo;
+    const int* rv;         // tet * 4 + slot, CSR by internal vertex
+    const int* vptr;       // [n_free + 1]
+    int n_free;
+    int model;
+    int4* jv;
+    typename R4t<R>::T* ma;
+    typename R4t<R>::T* mb;
+    typename R2t<R>::T* mc;  // corotated only
+    R* vmu;                  // FP64 only
+    R* Sv;                   // [n_free]
+};
+template <class R>
+hipError_t launch_build_visits(const VisitBuild<R>& b, hipStream_t s);
+// flag (device int) = 1 if lambda >= mu in every tet, else 0.
+hipError_t launch_lam_ge_mu(const double* mu, const double* lam, int n, int* flag, hipStream_t s);
+// Material update: TetGeo mu/lambda, then the visit records.
 template <class R>
 hipError_t launch_set_materials(const double* mu, const double* lam, TetGeo* geo, int n_tets,
-                                const int* rv, int n_vis_free, R* vmu, R* vlam, hipStream_t s);
+                                const VisitBuild<R>& b, hipStream_t s);
 template <class R>
 hipError_t launch_set_dirichlet(const double* xd, const int* dir_internal, int nd, int n_free,
                                 typename R4t<R>::T* xd_int, hipStream_t s);
@@ -166,14 +202,15 @@ struct AdjArgs {
     P4* P;                 // previous (acceleration)
     P4* N;                 // next (acceleration)
     const P4* B;
+    using R4 = typename R4t<R>::T;
+    using R2 = typename R2t<R>::T;
     const int* vptr;
-    const int* j1;
-    const int* j2;
-    const int* j3;
-    const R* m;
-    const R* vmu;
-    const R* vlam;
-    int64_t nvis;
+    const int4* jv;
+    const R4* ma;
+    const R4* mb;
+    const R2* mc;
+    const R* vmu;          // FP64 only
+    const R* Sv;
     const int* vinst;
     const int* wvptr;
     const int* wv_c;

@@ -24,11 +24,66 @@ constexpr int kNeo = 0;
 constexpr int kCor = 1;
 constexpr int kBlock = 256;
 
+// Element i of an array through a 32-bit byte offset, so that the load takes
+// the array base from scalar registers and only the offset from a vector
+// register (the host keeps every array under 4 GiB).
+template <class T>
+__device__ __forceinline__ T at(const T* base, int i)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                       uint32_t(i) * uint32_t(sizeof(T)));
+}
+
+template <class T>
+__device__ __forceinline__ T* ptr_at(T* base, int i)
+{
+    return reinterpret_cast<T*>(reinterpret_cast<char*>(base) + uint32_t(i) * uint32_t(sizeof(T)));
+}
+
+// Block index remapped so that the blocks the dispatcher places on one XCD
+// (block b goes to XCD b % 8) cover one contiguous range of vertices: a
+// colour's vertices are ordered by instance and position, so each XCD's L2
+// then gathers the neighbour positions of a compact region instead of every
+// eighth block of the whole mesh.  A bijection on [0, gridDim.x).
+__device__ __forceinline__ int xcd_block()
+{
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+// Value of v in another lane of the same 16-lane row (data-parallel
+// primitive; CTRL is the row permutation code).
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ double dpp(double v)
+{
+    const unsigned long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, int(b & 0xffffffffull), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, int(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)((unsigned long long)(unsigned)hi << 32 | (unsigned)lo));
+}
+
+// Sum over the LANES lanes of a group (groups are aligned, LANES | 64).  The
+// first four stages pair lanes inside a row: quad permutations [1,0,3,2] and
+// [2,3,0,1], then the half-row mirror (i <-> 7 - i) and the row mirror
+// (i <-> 15 - i); wider groups continue with cross-row shuffles.  Each stage
+// adds two equal partial sums in commuted order, so every lane of the group
+// ends with the same bits.
 template <int LANES, class T>
 __device__ __forceinline__ T lsum(T v)
 {
-#pragma unroll
-    for (int o = LANES / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, LANES);
+    if (LANES >= 2) v += dpp<0xB1>(v);
+    if (LANES >= 4) v += dpp<0x4E>(v);
+    if (LANES >= 8) v += dpp<0x141>(v);
+    if (LANES >= 16) v += dpp<0x140>(v);
+    if (LANES >= 32) v += __shfl_xor(v, 16, LANES);
+    if (LANES >= 64) v += __shfl_xor(v, 32, LANES);
     return v;
 }
 
@@ -112,25 +167,6 @@ __device__ __forceinline__ R plane_phi(const R* pl, V3<PR> x)
     return R(PR(pl[0]) * x.x + PR(pl[1]) * x.y + PR(pl[2]) * x.z - PR(pl[3]));
 }
 
-// Visit k of vertex at xi: deformation gradient, own gradient a = dN_i,
-// V0 mu, V0 lambda.
-template <class R, class A, class PR>
-__device__ __forceinline__ void load_visit(const A& a, int k, V3<PR> xi, Cols<R>& F, V3<R>& av,
-                                           R& vm, R& vl)
-{
-    const int i1 = a.j1[k], i2 = a.j2[k], i3 = a.j3[k];
-    R m[9];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) m[q] = a.m[q * a.nvis + k];
-    vm = a.vmu[k];
-    vl = a.vlam[k];
-    const V3<R> e1 = rel<R>(a.W[i1], xi);
-    const V3<R> e2 = rel<R>(a.W[i2], xi);
-    const V3<R> e3 = rel<R>(a.W[i3], xi);
-    F = edge_F(e1, e2, e3, m);
-    av = mk(-(m[0] + m[3] + m[6]), -(m[1] + m[4] + m[7]), -(m[2] + m[5] + m[8]));
-}
-
 // Corotated energy density times V0 from the signed singular values:
 // mu |F - R|^2 = mu sum (sigma_i - 1)^2.
 template <class R>
@@ -143,6 +179,16 @@ __device__ __forceinline__ R corot_energy(const Polar<R>& P, R J, R vm, R vl)
 
 // Raw record of one visit (loaded before any arithmetic so that the loads of
 // several visits are in flight together).
+//
+// Corotated workspaces keep the three shape-function gradient rows m[9]: the
+// polar decomposition needs F itself.  Neo-Hookean workspaces keep only what
+// the step needs.  With D = [e1 e2 e3] the edge vectors x_j - x_i and M the
+// matrix of rows m_1, m_2, m_3, F = D M, so
+//   F dN_i     = sum_a alpha_a e_a,            alpha_a = m_a . dN_i
+//   cof F dN_i = cof D (cof M dN_i) = sum_k beta_k X_k,
+//                X_1 = e2 x e3, X_2 = e3 x e1, X_3 = e1 x e2,  beta = cof M dN_i
+//   J = det F  = delta (e1 . X_1),              delta = det M
+// and the record holds a = V0 mu alpha, V0 lambda, beta and delta.
 template <class R>
 struct VisitRaw {
     int i1, i2, i3;
@@ -150,25 +196,77 @@ struct VisitRaw {
     R vm, vl;
 };
 
+template <class R>
+struct VisitNH {
+    int i1, i2, i3;
+    R vm, vl, delta;
+    V3<R> a, beta;
+};
+
+template <class R>
+__device__ __forceinline__ R vm_of(int4 j, const R* vmu, int k)
+{
+    if constexpr (sizeof(R) == 4) return __int_as_float(j.w);
+    else return at(vmu, k);
+}
+
 template <class R, class A>
 __device__ __forceinline__ VisitRaw<R> load_raw(const A& a, int k)
 {
     VisitRaw<R> r;
-    r.i1 = a.j1[k];
-    r.i2 = a.j2[k];
-    r.i3 = a.j3[k];
-#pragma unroll
-    for (int q = 0; q < 9; ++q) r.m[q] = a.m[q * a.nvis + k];
-    r.vm = a.vmu[k];
-    r.vl = a.vlam[k];
+    const int4 j = at(a.jv, k);
+    const auto p = at(a.ma, k);
+    const auto q = at(a.mb, k);
+    const auto t = at(a.mc, k);
+    r.i1 = j.x;
+    r.i2 = j.y;
+    r.i3 = j.z;
+    r.m[0] = p.x; r.m[1] = p.y; r.m[2] = p.z; r.m[3] = p.w;
+    r.m[4] = q.x; r.m[5] = q.y; r.m[6] = q.z; r.m[7] = q.w;
+    r.m[8] = t.x;
+    r.vl = t.y;
+    r.vm = vm_of<R>(j, a.vmu, k);
     return r;
+}
+
+template <class R, class A>
+__device__ __forceinline__ VisitNH<R> load_nh(const A& a, int k)
+{
+    VisitNH<R> r;
+    const int4 j = at(a.jv, k);
+    const auto p = at(a.ma, k);
+    const auto q = at(a.mb, k);
+    r.i1 = j.x;
+    r.i2 = j.y;
+    r.i3 = j.z;
+    r.a = mk(p.x, p.y, p.z);
+    r.vl = p.w;
+    r.beta = mk(q.x, q.y, q.z);
+    r.delta = q.w;
+    r.vm = vm_of<R>(j, a.vmu, k);
+    return r;
+}
+
+// Visit k of vertex at xi (corotated records): deformation gradient, own
+// gradient a = dN_i, V0 mu, V0 lambda.
+template <class R, class A, class PR>
+__device__ __forceinline__ void load_visit(const A& a, int k, V3<PR> xi, Cols<R>& F, V3<R>& av,
+                                           R& vm, R& vl)
+{
+    const VisitRaw<R> r = load_raw<R>(a, k);
+    vm = r.vm;
+    vl = r.vl;
+    const V3<R> e1 = rel<R>(at(a.W, r.i1), xi);
+    const V3<R> e2 = rel<R>(at(a.W, r.i2), xi);
+    const V3<R> e3 = rel<R>(at(a.W, r.i3), xi);
+    F = edge_F(e1, e2, e3, r.m);
+    av = mk(-(r.m[0] + r.m[3] + r.m[6]), -(r.m[1] + r.m[4] + r.m[7]), -(r.m[2] + r.m[5] + r.m[8]));
 }
 
 // Per-vertex accumulators of the local gradient and Hessian pieces.
 template <class R>
 struct Acc {
     V3<R> g;     // elastic + weak-constraint gradient
-    R S;         // sum V0 mu |dN_i|^2
     Sym<R> Aw;   // sum V0 lambda c c^T + sum s^2 K
     Sym<R> Cm;   // Neo-Hookean safeguard: sum V0 mu c c^T
     V3<R> gw;    // corotated safeguard: weak-constraint part of g
@@ -176,9 +274,23 @@ struct Acc {
     R E0, E0a;   // corotated safeguard: elastic energy and sum of |terms|
 };
 
-template <class R, int MODEL, bool SAFE>
-__device__ __forceinline__ void visit_accumulate(Acc<R>& q, const VisitRaw<R>& r, V3<R> e1, V3<R> e2,
-                                                 V3<R> e3)
+// Neo-Hookean visit: V0 P dN_i with P = mu F + (lhat (J - 1) - mu) cof F,
+// lhat = mu + lambda, and the V0 lambda c c^T part of the modified Hessian.
+template <class R, bool SAFE>
+__device__ __forceinline__ void visit_nh(Acc<R>& q, const VisitNH<R>& r, V3<R> e1, V3<R> e2, V3<R> e3)
+{
+    const V3<R> X1 = cross(e2, e3), X2 = cross(e3, e1), X3 = cross(e1, e2);
+    const R J = r.delta * dot(e1, X1);
+    const V3<R> c = comb(X1, r.beta.x, X2, r.beta.y, X3, r.beta.z);  // cof F dN_i
+    const V3<R> p = comb(e1, r.a.x, e2, r.a.y, e3, r.a.z);           // V0 mu F dN_i
+    sym_add_outer(q.Aw, r.vl, c);
+    q.g = q.g + p + ((r.vm + r.vl) * (J - R(1)) - r.vm) * c;
+    if (SAFE) sym_add_outer(q.Cm, r.vm, c);
+}
+
+// Corotated visit: V0 P dN_i with P = 2 mu (F - R) + lambda (J - 1) cof F.
+template <class R, bool SAFE>
+__device__ __forceinline__ void visit_cor(Acc<R>& q, const VisitRaw<R>& r, V3<R> e1, V3<R> e2, V3<R> e3)
 {
     const Cols<R> F = edge_F(e1, e2, e3, r.m);
     const V3<R> av = mk(-(r.m[0] + r.m[3] + r.m[6]), -(r.m[1] + r.m[4] + r.m[7]),
@@ -188,22 +300,59 @@ __device__ __forceinline__ void visit_accumulate(Acc<R>& q, const VisitRaw<R>& r
     const V3<R> c = apply(C, av);   // cof(F) dN_i
     const V3<R> p = apply(F, av);   // F dN_i
     const R vm = r.vm, vl = r.vl;
-    q.S += vm * dot(av, av);
     sym_add_outer(q.Aw, vl, c);
-    if (MODEL == kNeo) {
-        // V0 P dN_i, P = mu F + (lhat (J - 1) - mu) cof F, lhat = mu + lambda
-        q.g = q.g + vm * p + ((vm + vl) * (J - R(1)) - vm) * c;
-        if (SAFE) sym_add_outer(q.Cm, vm, c);
-    } else {
-        // V0 P dN_i, P = 2 mu (F - R) + lambda (J - 1) cof F
-        Polar<R> pol;
-        polar(F, pol);
-        const V3<R> ra = polar_apply(pol, av);
-        q.g = q.g + (R(2) * vm) * (p - ra) + (vl * (J - R(1))) * c;
-        if (SAFE) {
-            const R e = corot_energy(pol, J, vm, vl);
-            q.E0 += e;
-            q.E0a += abs_(e);
+    Polar<R> pol;
+    polar(F, pol);
+    const V3<R> ra = polar_apply(pol, av);
+    q.g = q.g + (R(2) * vm) * (p - ra) + (vl * (J - R(1))) * c;
+    if (SAFE) {
+        const R e = corot_energy(pol, J, vm, vl);
+        q.E0 += e;
+        q.E0a += abs_(e);
+    }
+}
+
+// Visits of one lane: two per pass while any lane of the wave still has two,
+// else one; the branch conditions are uniform over the wave, and lanes with
+// fewer visits sit a visit out under the execution mask.  A lane without a
+// second visit loads its first one twice and skips the second accumulation.
+template <class R, int MODEL, bool SAFE, int LANES, class A, class PR>
+__device__ __forceinline__ void lane_visits(const A& a, Acc<R>& q, int kb, int ke, int lane, V3<PR> xi)
+{
+    for (int k = kb + lane; __any(k < ke); k += 2 * LANES) {
+        const bool h0 = k < ke;
+        const bool h1 = k + LANES < ke;
+        const int k1 = h1 ? k + LANES : k;
+        if constexpr (MODEL == kNeo) {
+            if (__any(h1)) {
+                if (h0) {
+                    const VisitNH<R> r0 = load_nh<R>(a, k);
+                    const VisitNH<R> r1 = load_nh<R>(a, k1);
+                    const auto p01 = at(a.W, r0.i1), p02 = at(a.W, r0.i2), p03 = at(a.W, r0.i3);
+                    const auto p11 = at(a.W, r1.i1), p12 = at(a.W, r1.i2), p13 = at(a.W, r1.i3);
+                    visit_nh<R, SAFE>(q, r0, rel<R>(p01, xi), rel<R>(p02, xi), rel<R>(p03, xi));
+                    if (h1) visit_nh<R, SAFE>(q, r1, rel<R>(p11, xi), rel<R>(p12, xi), rel<R>(p13, xi));
+                }
+            } else if (h0) {
+                const VisitNH<R> r0 = load_nh<R>(a, k);
+                visit_nh<R, SAFE>(q, r0, rel<R>(at(a.W, r0.i1), xi), rel<R>(at(a.W, r0.i2), xi),
+                                  rel<R>(at(a.W, r0.i3), xi));
+            }
+        } else {
+            if (__any(h1)) {
+                if (h0) {
+                    const VisitRaw<R> r0 = load_raw<R>(a, k);
+                    const VisitRaw<R> r1 = load_raw<R>(a, k1);
+                    const auto p01 = at(a.W, r0.i1), p02 = at(a.W, r0.i2), p03 = at(a.W, r0.i3);
+                    const auto p11 = at(a.W, r1.i1), p12 = at(a.W, r1.i2), p13 = at(a.W, r1.i3);
+                    visit_cor<R, SAFE>(q, r0, rel<R>(p01, xi), rel<R>(p02, xi), rel<R>(p03, xi));
+                    if (h1) visit_cor<R, SAFE>(q, r1, rel<R>(p11, xi), rel<R>(p12, xi), rel<R>(p13, xi));
+                }
+            } else if (h0) {
+                const VisitRaw<R> r0 = load_raw<R>(a, k);
+                visit_cor<R, SAFE>(q, r0, rel<R>(at(a.W, r0.i1), xi), rel<R>(at(a.W, r0.i2), xi),
+                                   rel<R>(at(a.W, r0.i3), xi));
+            }
         }
     }
 }
@@ -216,17 +365,17 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
 {
     using P4 = typename R4t<PR>::T;
     constexpr bool WC = GEN;
-    const int gid = blockIdx.x * kBlock + threadIdx.x;
+    const int gid = xcd_block() * kBlock + threadIdx.x;
     const int v = vbeg + gid / LANES;
     const int lane = gid & (LANES - 1);
     if (v >= vend) return;
-    const int kb = a.vptr[v], ke = a.vptr[v + 1];
-    const P4 xw = a.W[v];
+    const int kb = at(a.vptr, v), ke = at(a.vptr, v + 1);
+    const P4 xw = at(a.W, v);
     int inst = 0;
     if (GEN) {
-        inst = a.vinst[v];
-        if (!a.active[inst]) {
-            if (ACCEL && lane == 0) a.N[v] = xw;
+        inst = at(a.vinst, v);
+        if (!at(a.active, inst)) {
+            if (ACCEL && lane == 0) *ptr_at(a.N, v) = xw;
             return;
         }
     }
@@ -234,7 +383,6 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
 
     Acc<R> q;
     q.g = mk<R>(0, 0, 0);
-    q.S = R(0);
     q.Aw = sym_zero<R>();
     q.Cm = sym_zero<R>();
     q.gw = mk<R>(0, 0, 0);
@@ -242,22 +390,10 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
     q.E0 = R(0);
     q.E0a = R(0);
 
-    int k = kb + lane;
-    for (; k + LANES < ke; k += 2 * LANES) {
-        const VisitRaw<R> r0 = load_raw<R>(a, k);
-        const VisitRaw<R> r1 = load_raw<R>(a, k + LANES);
-        const P4 p01 = a.W[r0.i1], p02 = a.W[r0.i2], p03 = a.W[r0.i3];
-        const P4 p11 = a.W[r1.i1], p12 = a.W[r1.i2], p13 = a.W[r1.i3];
-        visit_accumulate<R, MODEL, SAFE>(q, r0, rel<R>(p01, xi), rel<R>(p02, xi), rel<R>(p03, xi));
-        visit_accumulate<R, MODEL, SAFE>(q, r1, rel<R>(p11, xi), rel<R>(p12, xi), rel<R>(p13, xi));
-    }
-    if (k < ke) {
-        const VisitRaw<R> r0 = load_raw<R>(a, k);
-        visit_accumulate<R, MODEL, SAFE>(q, r0, rel<R>(a.W[r0.i1], xi), rel<R>(a.W[r0.i2], xi),
-                                         rel<R>(a.W[r0.i3], xi));
-    }
+    // lane l takes visits kb + l, kb + l + LANES, ...
+    lane_visits<R, MODEL, SAFE, LANES>(a, q, kb, ke, lane, xi);
     V3<R>& g = q.g;
-    R& S = q.S;
+    const R S = at(a.Sv, v);  // sum V0 mu |dN_i|^2 of the vertex
     Sym<R>& Aw = q.Aw;
     Sym<R>& Cm = q.Cm;
     V3<R>& gw = q.gw;
@@ -284,7 +420,6 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
     }
     if (LANES > 1) {
         lsum3<LANES>(g);
-        S = lsum<LANES>(S);
         lsum6<LANES>(Aw);
         if (SAFE && MODEL == kNeo) lsum6<LANES>(Cm);
         if (SAFE && MODEL == kCor) {
@@ -296,7 +431,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
             }
         }
     }
-    const V3<R> f = xyz(a.fext[v]);
+    const V3<R> f = xyz(at(a.fext, v));
     const V3<R> gt = g - f;
     Sym<R> A = Aw;
     A.xx += R(2) * S;
@@ -331,7 +466,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
         // evaluation below runs only when this bound does not already show
         // that the step decreases the energy.
         bool bound_ok = false;
-        if (MODEL == kCor) {
+        if constexpr (MODEL == kCor) {
             Sym<R> Ab = Aw;
             Ab.xx += R(2) * S;
             Ab.yy += R(2) * S;
@@ -356,7 +491,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
             }
             bound_ok = dE <= R(8) * u * ab;
         }
-        if (MODEL == kNeo) {
+        if constexpr (MODEL == kNeo) {
             // Along x_i + alpha d the Neo-Hookean energy of the incident tets
             // is exactly quadratic: |F|^2 is quadratic and det F affine in x_i
             // (a rank-one update), with Hessian sum V0 (mu |dN_i|^2 I + lhat
@@ -388,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
                     ab += e0 + e1;
                 }
             }
-            if (MODEL == kCor) {
+            if constexpr (MODEL == kCor) {
                 R E1 = R(0), E1a = R(0);
                 for (int k = kb + lane; k < ke; k += LANES) {
                     Cols<R> F;
@@ -424,15 +559,15 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
     }
     const V3<PR> xn = reject ? xi : xi + cvt<PR>(alpha * d);
     if (lane == 0) {
-        if (reject) atomicAdd(a.rejected + inst, 1);
+        if (reject) atomicAdd(ptr_at(a.rejected, inst), 1);
         if (ACCEL) {
-            const V3<PR> xp = xyz(a.P[v]);
+            const V3<PR> xp = xyz(at(a.P, v));
             const V3<PR> b = a.omega * (a.gamma * (xn - xi) + xi - xp) + xp;
-            a.W[v] = pack4(xn);
-            a.P[v] = xw;
-            a.N[v] = pack4(b);
+            *ptr_at(a.W, v) = pack4(xn);
+            *ptr_at(a.P, v) = xw;
+            *ptr_at(a.N, v) = pack4(b);
         } else {
-            a.W[v] = pack4(xn);
+            *ptr_at(a.W, v) = pack4(xn);
         }
     }
 }
@@ -504,38 +639,41 @@ template <class R, class PR, int LANES, bool ACCEL, bool WC>
 __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg, int vend)
 {
     using P4 = typename R4t<PR>::T;
-    const int gid = blockIdx.x * kBlock + threadIdx.x;
+    const int gid = xcd_block() * kBlock + threadIdx.x;
     const int v = vbeg + gid / LANES;
     const int lane = gid & (LANES - 1);
     if (v >= vend) return;
-    const V3<PR> xi = xyz(a.X[v]);
-    const P4 lw = a.L[v];
+    const V3<PR> xi = xyz(at(a.X, v));
+    const P4 lw = at(a.L, v);
     const V3<PR> li = xyz(lw);
     V3<R> r = mk<R>(0, 0, 0);
-    R S = R(0);
     Sym<R> Hc = sym_zero<R>();
-    const int kb = a.vptr[v], ke = a.vptr[v + 1];
+    const int kb = at(a.vptr, v), ke = at(a.vptr, v + 1);
+    // Per visit with the Neo-Hookean record (e_a, l_a edge vectors of x and
+    // lambda, X_k = cof D columns): Lam dN_i = sum alpha_a l_a,
+    // cof F : Lam = delta sum_k X_k . l_k and dcof[Lam] dN_i =
+    // sum_k beta_k (derivative of X_k along l).
     for (int k = kb + lane; k < ke; k += LANES) {
-        const VisitRaw<R> q = load_raw<R>(a, k);
-        const Cols<R> F = edge_F(rel<R>(a.X[q.i1], xi), rel<R>(a.X[q.i2], xi), rel<R>(a.X[q.i3], xi), q.m);
-        const Cols<R> Lm = edge_F(rel<R>(a.L[q.i1], li), rel<R>(a.L[q.i2], li), rel<R>(a.L[q.i3], li), q.m);
-        const V3<R> av = mk(-(q.m[0] + q.m[3] + q.m[6]), -(q.m[1] + q.m[4] + q.m[7]),
-                            -(q.m[2] + q.m[5] + q.m[8]));
+        const VisitNH<R> q = load_nh<R>(a, k);
+        const V3<R> e1 = rel<R>(at(a.X, q.i1), xi), e2 = rel<R>(at(a.X, q.i2), xi),
+                    e3 = rel<R>(at(a.X, q.i3), xi);
+        const V3<R> l1 = rel<R>(at(a.L, q.i1), li), l2 = rel<R>(at(a.L, q.i2), li),
+                    l3 = rel<R>(at(a.L, q.i3), li);
+        const V3<R> X1 = cross(e2, e3), X2 = cross(e3, e1), X3 = cross(e1, e2);
+        const R J = q.delta * dot(e1, X1);
+        const V3<R> c = comb(X1, q.beta.x, X2, q.beta.y, X3, q.beta.z);
         const R vm = q.vm, vl = q.vl;
-        const Cols<R> C = cofactor(F);
-        const R J = dot(F.c0, C.c0);
-        const V3<R> c = apply(C, av);
         const R lh = vm + vl;
         const R qq = lh * (J - R(1)) - vm;
-        const R cofL = dot(C.c0, Lm.c0) + dot(C.c1, Lm.c1) + dot(C.c2, Lm.c2);
-        const V3<R> dc0 = cross(Lm.c1, F.c2) + cross(F.c1, Lm.c2);
-        const V3<R> dc1 = cross(Lm.c2, F.c0) + cross(F.c2, Lm.c0);
-        const V3<R> dc2 = cross(Lm.c0, F.c1) + cross(F.c0, Lm.c1);
-        const V3<R> dca = comb(dc0, av.x, dc1, av.y, dc2, av.z);
-        r = r + vm * apply(Lm, av) + (lh * cofL) * c + qq * dca;
-        S += vm * dot(av, av);
+        const R cofL = q.delta * (dot(X1, l1) + dot(X2, l2) + dot(X3, l3));
+        const V3<R> d1 = cross(l2, e3) + cross(e2, l3);
+        const V3<R> d2 = cross(l3, e1) + cross(e3, l1);
+        const V3<R> d3 = cross(l1, e2) + cross(e1, l2);
+        const V3<R> dca = comb(d1, q.beta.x, d2, q.beta.y, d3, q.beta.z);
+        r = r + comb(l1, q.a.x, l2, q.a.y, l3, q.a.z) + (lh * cofL) * c + qq * dca;
         sym_add_outer(Hc, lh, c);
     }
+    const R S = at(a.Sv, v);
     int inst = 0;
     if (WC) {
         inst = a.vinst[v];
@@ -552,7 +690,6 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg
     }
     if (LANES > 1) {
         lsum3<LANES>(r);
-        S = lsum<LANES>(S);
         lsum6<LANES>(Hc);
     }
     Hc.xx += S;
@@ -568,19 +705,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg
             }
         }
     }
-    const V3<R> rho = cvt<R>(xyz(a.B[v])) - r;
+    const V3<R> rho = cvt<R>(xyz(at(a.B, v))) - r;
     V3<R> dl;
     if (!chol_solve(Hc, rho, dl)) dl = mk<R>(0, 0, 0);
     const V3<PR> ln = li + cvt<PR>(dl);
     if (lane == 0) {
         if (ACCEL) {
-            const V3<PR> lp = xyz(a.P[v]);
+            const V3<PR> lp = xyz(at(a.P, v));
             const V3<PR> b = a.omega * (a.gamma * (ln - li) + li - lp) + lp;
-            a.L[v] = pack4(ln);
-            a.P[v] = lw;
-            a.N[v] = pack4(b);
+            *ptr_at(a.L, v) = pack4(ln);
+            *ptr_at(a.P, v) = lw;
+            *ptr_at(a.N, v) = pack4(b);
         } else {
-            a.L[v] = pack4(ln);
+            *ptr_at(a.L, v) = pack4(ln);
         }
     }
 }
@@ -1048,28 +1185,74 @@ __global__ __launch_bounds__(kBlock) void k_set_geo(const double* mu, const doub
     geo[e].lam = lam[e];
 }
 
+// Visit records of free vertex v from the FP64 tet geometry: one thread per
+// vertex, visits in CSR order (rv = tet * 4 + slot of v), the other three
+// vertices in increasing slot order as the host listed them in jv.xyz.
+// Also the per-vertex sum S = sum V0 mu |dN_i|^2, in visit order.
 template <class R>
-__global__ __launch_bounds__(kBlock) void k_set_visits(const TetGeo* geo, const int* rv, int n,
-                                                       R* vmu, R* vlam)
+__global__ __launch_bounds__(kBlock) void k_build_visits(VisitBuild<R> b)
 {
-    const int k = blockIdx.x * kBlock + threadIdx.x;
-    if (k >= n) return;
-    const TetGeo& G = geo[rv[k] >> 2];
-    vmu[k] = R(G.V0 * G.mu);
-    vlam[k] = R(G.V0 * G.lam);
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= b.n_free) return;
+    double S = 0.0;
+    for (int k = b.vptr[v]; k < b.vptr[v + 1]; ++k) {
+        const int e = b.rv[k] >> 2, slot = b.rv[k] & 3;
+        const TetGeo& G = b.geo[e];
+        V3<double> m[3];
+        int no = 0;
+        for (int j = 0; j < 4; ++j) {
+            if (j == slot) continue;
+            m[no++] = grad_of_slot(G, j);
+        }
+        const V3<double> av = grad_of_slot(G, slot);
+        const double vm = G.V0 * G.mu, vl = G.V0 * G.lam;
+        S += vm * dot(av, av);
+        if constexpr (sizeof(R) == 4) b.jv[k].w = __float_as_int(float(vm));
+        else b.vmu[k] = vm;
+        using R4 = typename R4t<R>::T;
+        if (b.model == kNeo) {
+            // rows of cof M are m2 x m3, m3 x m1, m1 x m2
+            const V3<double> c1 = cross(m[1], m[2]), c2 = cross(m[2], m[0]), c3 = cross(m[0], m[1]);
+            const double delta = dot(m[0], c1);
+            b.ma[k] = R4{R(vm * dot(m[0], av)), R(vm * dot(m[1], av)), R(vm * dot(m[2], av)), R(vl)};
+            b.mb[k] = R4{R(dot(c1, av)), R(dot(c2, av)), R(dot(c3, av)), R(delta)};
+        } else {
+            b.ma[k] = R4{R(m[0].x), R(m[0].y), R(m[0].z), R(m[1].x)};
+            b.mb[k] = R4{R(m[1].y), R(m[1].z), R(m[2].x), R(m[2].y)};
+            b.mc[k] = typename R2t<R>::T{R(m[2].z), R(vl)};
+        }
+    }
+    b.Sv[v] = R(S);
+}
+
+#if PBNG_KERNEL_SET == 0
+// flag = 1 while lambda >= mu in every tet (NaN counts as a violation)
+__global__ __launch_bounds__(kBlock) void k_flag_one(int* flag) { *flag = 1; }
+
+__global__ __launch_bounds__(kBlock) void k_lam_ge_mu(const double* mu, const double* lam, int n,
+                                                      int* flag)
+{
+    const int e = blockIdx.x * kBlock + threadIdx.x;
+    if (e < n && !(lam[e] >= mu[e])) *flag = 0;
+}
+#endif
+
+template <class R>
+hipError_t launch_build_visits(const VisitBuild<R>& b, hipStream_t s)
+{
+    if (b.n_free > 0)
+        hipLaunchKernelGGL((k_build_visits<R>), dim3(nblk(b.n_free)), dim3(kBlock), 0, s, b);
+    return hipGetLastError();
 }
 
 template <class R>
 hipError_t launch_set_materials(const double* mu, const double* lam, TetGeo* geo, int n_tets,
-                                const int* rv, int n_vis_free, R* vmu, R* vlam, hipStream_t s)
+                                const VisitBuild<R>& b, hipStream_t s)
 {
     if (n_tets > 0)
         hipLaunchKernelGGL((k_set_geo<R>), dim3(nblk(n_tets)), dim3(kBlock), 0, s, mu, lam, geo,
                            n_tets);
-    if (n_vis_free > 0)
-        hipLaunchKernelGGL((k_set_visits<R>), dim3(nblk(n_vis_free)), dim3(kBlock), 0, s, geo, rv,
-                           n_vis_free, vmu, vlam);
-    return hipGetLastError();
+    return launch_build_visits<R>(b, s);
 }
 
 template <class R>
@@ -1120,9 +1303,17 @@ hipError_t launch_set_dirichlet(const double* xd, const int* dir_internal, int n
 PBNG_INST_POS(float)
 PBNG_INST_POS(double)
 template hipError_t launch_set_materials<float>(const double*, const double*, TetGeo*, int,
-                                                const int*, int, float*, float*, hipStream_t);
+                                                const VisitBuild<float>&, hipStream_t);
 template hipError_t launch_set_materials<double>(const double*, const double*, TetGeo*, int,
-                                                 const int*, int, double*, double*, hipStream_t);
+                                                 const VisitBuild<double>&, hipStream_t);
+hipError_t launch_lam_ge_mu(const double* mu, const double* lam, int n, int* flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flag_one, dim3(1), dim3(1), 0, s, flag);
+    if (n > 0) hipLaunchKernelGGL(k_lam_ge_mu, dim3(nblk(n)), dim3(kBlock), 0, s, mu, lam, n, flag);
+    return hipGetLastError();
+}
+template hipError_t launch_build_visits<float>(const VisitBuild<float>&, hipStream_t);
+template hipError_t launch_build_visits<double>(const VisitBuild<double>&, hipStream_t);
 PBNG_INST_SWEEP(float, float)
 #elif PBNG_KERNEL_SET == 1
 PBNG_INST_SWEEP(double, double)

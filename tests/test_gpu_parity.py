@@ -389,3 +389,25 @@ def test_muscle_standin_full_sampled_phase():
     step = np.abs(upd - before[pick]).max()
     tol = 1e-4 * step + 4 * np.finfo(np.float32).eps * np.abs(before[pick]).max()
     assert np.abs(upd - xg[pick]).max() <= tol
+
+
+def test_material_update_reenables_safeguard():
+    """A Neo-Hookean workspace built with lambda >= mu in every tet skips the
+    safeguard (the step is then a descent step); after a material update to
+    lambda < mu the safeguard must run again, so the solve matches the
+    oracle's safeguarded solve with the new materials."""
+    soft = S.twist_box(6, "nh", 1e4, 0.05, 90.0, 2.0, 0.01, seed=6)
+    stiff = S.twist_box(6, "nh", 1e4, 0.45, 90.0, 2.0, 0.01, seed=6)
+    hp = pbng.problem_from_scenario(soft)
+    nt = soft.tets.shape[0]
+    mu = torch.full((nt,), hp.mu, dtype=torch.float64, device="cuda")
+    lam = torch.full((nt,), hp.lam, dtype=torch.float64, device="cuda")
+    xo, sto, _ = oracle_solve(soft, 40, safeguard="backtrack")
+    assert sto["halvings"] > 0
+    for real, tol in (("f64", 1e-10), ("f32", 1e-5)):
+        announce("material update lambda < mu safeguard %s" % real)
+        ws = workspace([stiff], real)
+        ws.set_materials(mu, lam)
+        x = dev_x(soft.initial_iterate(), real)
+        ws.solve(x, max_sweeps=40, rel_tol=0.0, check_every=40, safeguard="backtrack")
+        assert rel_err(host(x), xo) <= tol
