@@ -167,14 +167,14 @@ __device__ __forceinline__ R plane_phi(const R* pl, V3<PR> x)
     return R(PR(pl[0]) * x.x + PR(pl[1]) * x.y + PR(pl[2]) * x.z - PR(pl[3]));
 }
 
-// Corotated energy density times V0 from the signed singular values:
-// mu |F - R|^2 = mu sum (sigma_i - 1)^2.
+// Corotated energy density times V0 from the rotation: with F = R S (S
+// symmetric, signed singular values sigma), |F - R|^2 = |S - I|^2 =
+// sum (sigma_i - 1)^2.
 template <class R>
-__device__ __forceinline__ R corot_energy(const Polar<R>& P, R J, R vm, R vl)
+__device__ __forceinline__ R corot_energy(const Cols<R>& F, const Cols<R>& Rm, R J, R vm, R vl)
 {
-    const V3<R> s = P.sigma;
-    const R d0 = s.x - R(1), d1 = s.y - R(1), d2 = s.z - R(1);
-    return vm * (d0 * d0 + d1 * d1 + d2 * d2) + R(0.5) * vl * (J - R(1)) * (J - R(1));
+    const V3<R> d0 = F.c0 - Rm.c0, d1 = F.c1 - Rm.c1, d2 = F.c2 - Rm.c2;
+    return vm * (dot(d0, d0) + dot(d1, d1) + dot(d2, d2)) + R(0.5) * vl * (J - R(1)) * (J - R(1));
 }
 
 // Raw record of one visit (loaded before any arithmetic so that the loads of
@@ -301,12 +301,11 @@ __device__ __forceinline__ void visit_cor(Acc<R>& q, const VisitRaw<R>& r, V3<R>
     const V3<R> p = apply(F, av);   // F dN_i
     const R vm = r.vm, vl = r.vl;
     sym_add_outer(q.Aw, vl, c);
-    Polar<R> pol;
-    polar(F, pol);
-    const V3<R> ra = polar_apply(pol, av);
+    const Cols<R> Rm = rotation_of(F);
+    const V3<R> ra = apply(Rm, av);
     q.g = q.g + (R(2) * vm) * (p - ra) + (vl * (J - R(1))) * c;
     if (SAFE) {
-        const R e = corot_energy(pol, J, vm, vl);
+        const R e = corot_energy(F, Rm, J, vm, vl);
         q.E0 += e;
         q.E0a += abs_(e);
     }
@@ -535,9 +534,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
                     F.c1 = F.c1 + av.y * ad;
                     F.c2 = F.c2 + av.z * ad;
                     const R J1 = dot(F.c0, cross(F.c1, F.c2));
-                    Polar<R> pol;
-                    polar(F, pol);
-                    const R e = corot_energy(pol, J1, vm, vl);
+                    const R e = corot_energy(F, rotation_of(F), J1, vm, vl);
                     E1 += e;
                     E1a += abs_(e);
                 }
@@ -836,14 +833,12 @@ __global__ __launch_bounds__(kBlock) void k_tet_stress(ResArgs<R> a)
         P.c2 = G.mu * F.c2 + (lh * q) * C.c2;
         psi = 0.5 * G.mu * frob2(F) + 0.5 * lh * q * q;
     } else {
-        Polar<double> pol;
-        polar(F, pol);
-        const Cols<double> Rm = polar_matrix(pol);
+        const Cols<double> Rm = rotation_of(F);
         const double w = G.lam * (J - 1.0);
         P.c0 = (2.0 * G.mu) * (F.c0 - Rm.c0) + w * C.c0;
         P.c1 = (2.0 * G.mu) * (F.c1 - Rm.c1) + w * C.c1;
         P.c2 = (2.0 * G.mu) * (F.c2 - Rm.c2) + w * C.c2;
-        psi = corot_energy(pol, J, G.mu, G.lam);
+        psi = corot_energy(F, Rm, J, G.mu, G.lam);
     }
     store_slot_forces(a.vp + 12 * int64_t(e), G, P);
     a.ebuf[a.tet_eidx[e]] = G.V0 * psi;

@@ -212,17 +212,25 @@ __device__ __forceinline__ void polar(const Cols<R>& F, Polar<R>& out)
     V3<R> v0 = mk<R>(1, 0, 0), v1 = mk<R>(0, 1, 0), v2 = mk<R>(0, 0, 1);
     constexpr bool dbl = sizeof(R) == 8;
     const int max_sweeps = dbl ? 12 : 5;
+    // Cyclic sweeps until the off-diagonal part is below working precision
+    // relative to the diagonal (|off| <= 3e-7 |diag| in float, 1e-17 in
+    // double), tested per lane before every sweep: a converged lane is
+    // masked off, so its result does not depend on the other lanes of its
+    // wave, and the wave leaves the loop once all of its lanes converged.
+    const R tol = dbl ? R(1e-34) : R(1e-13);
+    bool act = true;
     for (int sw = 0; sw < max_sweeps; ++sw) {
-        // pair (0,1), remaining 2
-        jacobi_rot(s00, s11, s01, s02, s12, v0, v1);
-        // pair (0,2), remaining 1: a_rp = s01 (row 1, col 0), a_rq = s12
-        jacobi_rot(s00, s22, s02, s01, s12, v0, v2);
-        // pair (1,2), remaining 0
-        jacobi_rot(s11, s22, s12, s01, s02, v1, v2);
-        if (dbl) {
-            R off = s01 * s01 + s02 * s02 + s12 * s12;
-            R dia = s00 * s00 + s11 * s11 + s22 * s22;
-            if (off <= R(1e-34) * dia) break;
+        const R off = s01 * s01 + s02 * s02 + s12 * s12;
+        const R dia = s00 * s00 + s11 * s11 + s22 * s22;
+        act = act && !(off <= tol * dia);
+        if (!__any(act)) break;
+        if (act) {
+            // pair (0,1), remaining 2
+            jacobi_rot(s00, s11, s01, s02, s12, v0, v1);
+            // pair (0,2), remaining 1: a_rp = s01 (row 1, col 0), a_rq = s12
+            jacobi_rot(s00, s22, s02, s01, s12, v0, v2);
+            // pair (1,2), remaining 0
+            jacobi_rot(s11, s22, s12, s01, s02, v1, v2);
         }
     }
     // B = F V, sorted by decreasing column norm
@@ -296,6 +304,68 @@ __device__ __forceinline__ Cols<R> polar_matrix(const Polar<R>& P)
 {
     return {polar_apply(P, mk<R>(1, 0, 0)), polar_apply(P, mk<R>(0, 1, 0)),
             polar_apply(P, mk<R>(0, 0, 1))};
+}
+
+// Rotation of the polar decomposition by the scaled Newton iteration
+// X <- (zeta X + (zeta X)^{-T}) / 2 with the Frobenius-norm scaling
+// zeta = (|X^{-1}|_F / |X|_F)^{1/2} (Higham 1986, "Computing the polar
+// decomposition - with applications").  It converges quadratically to the
+// orthogonal polar factor, which for det F > 0 is the rotation of the signed
+// convention above.  Once the iteration is in its quadratic regime the error
+// left after a step is about half the square of that step's change, so a
+// change below 3e-5 (float) or 1e-9 (double) in Frobenius norm ends it.
+// Returns false when det F <= 0 (inverted or degenerate) or the iteration
+// has not converged within its budget; the caller then takes the Jacobi/QR
+// path.  Converged lanes are masked off, so a lane's result does not depend
+// on the other lanes of its wave.
+template <class R>
+__device__ __forceinline__ bool polar_newton(const Cols<R>& F, Cols<R>& X)
+{
+    constexpr bool dbl = sizeof(R) == 8;
+    const int iters = dbl ? 12 : 8;
+    const R tol = dbl ? R(1e-18) : R(1e-9);
+    const R tiny = dbl ? R(1e-200) : R(1e-30);
+    X = F;
+    bool act = true, ok = false;
+    for (int it = 0; it < iters; ++it) {
+        if (!__any(act)) break;
+        if (act) {
+            const Cols<R> C = cofactor(X);
+            const R det = dot(X.c0, C.c0);
+            if (!(det > tiny)) {
+                act = false;
+            } else {
+                const R q = sqrt_(frob2(C) * rcp(frob2(X)));   // |X^{-1}|_F det / |X|_F
+                const R zeta = sqrt_(q * rcp(det));
+                const R a = R(0.5) * zeta, b = R(0.5) * rcp(zeta * det);
+                Cols<R> Y;
+                Y.c0 = a * X.c0 + b * C.c0;
+                Y.c1 = a * X.c1 + b * C.c1;
+                Y.c2 = a * X.c2 + b * C.c2;
+                const V3<R> d0 = Y.c0 - X.c0, d1 = Y.c1 - X.c1, d2 = Y.c2 - X.c2;
+                const R d = dot(d0, d0) + dot(d1, d1) + dot(d2, d2);
+                X = Y;
+                if (d <= tol) {
+                    act = false;
+                    ok = true;
+                }
+            }
+        }
+    }
+    return ok;
+}
+
+// Rotation R(F) with det R = +1: Newton where it applies, else Jacobi/QR.
+template <class R>
+__device__ __forceinline__ Cols<R> rotation_of(const Cols<R>& F)
+{
+    Cols<R> X;
+    if (!polar_newton(F, X)) {
+        Polar<R> pol;
+        polar(F, pol);
+        X = polar_matrix(pol);
+    }
+    return X;
 }
 
 }  // namespace pbng
