@@ -17,7 +17,6 @@ solve against per-instance solves, time to 1e-5) and the differentiable
 cubes (forward and adjoint sweeps).
 """
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -30,7 +29,6 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "k_phase_beam_128x32x32_f32_counters.json")
-KERNEL_SOURCES = ["pbng_kernels.hip", "pbng_math.hpp", "pbng_internal.hpp"]
 
 
 def parse():
@@ -56,12 +54,10 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_sources_sha256():
-    h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2306_09021_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    return h.hexdigest()
+def progress(msg):
+    """One line per finished part of the run, on stderr (the JSON line is the
+    only stdout output)."""
+    print("[bench] %s" % msg, file=sys.stderr, flush=True)
 
 
 def traffic_per_launch():
@@ -72,6 +68,7 @@ def traffic_per_launch():
             c = json.load(f)
     except (OSError, ValueError):
         return None
+    from paper_2306_09021_amd.profsum import kernel_sources_sha256
     if c.get("sources_sha256") != kernel_sources_sha256():
         return None
     return c.get("traffic_bytes_per_launch")
@@ -170,12 +167,18 @@ def main():
                 "avg_launch_us": round(avg_dur * 1e6, 2),
                 "avg_algorithmic_bytes": int(avg_bytes), "launches_timed": n_launch}
 
+    progress("beam: %.3e vertex updates/s, k_phase %.2f us per launch" % (value, avg_dur * 1e6))
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc, args.cpu_sweeps)
-    extras = {} if args.no_extras else {
-        "batched": batched_report(pbng, S, torch, stream, args.batched_subset),
-        "differentiable": differentiable_report(pbng, S, torch, stream, args.diff_instances),
-        "muscles": muscles_report(pbng, S, torch, stream),
-    }
+    if cpu:
+        progress("cpu baseline: %.3e vertex updates/s" % cpu["value"])
+    extras = {}
+    if not args.no_extras:
+        extras["batched"] = batched_report(pbng, S, torch, stream, args.batched_subset)
+        progress("batched report done")
+        extras["differentiable"] = differentiable_report(pbng, S, torch, stream, args.diff_instances)
+        progress("differentiable report done")
+        extras["muscles"] = muscles_report(pbng, S, torch, stream)
+        progress("muscles report done")
 
     sweeps = max(s["sweeps"] for s in last)
     line = {
