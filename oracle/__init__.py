@@ -36,7 +36,8 @@ class _Problem(C.Structure):
     _fields_ = [("nv", C.c_int32), ("nt", C.c_int32), ("model", C.c_int32),
                 ("X", _dp), ("tets", _ip), ("mu", _dp), ("lam", _dp), ("fext", _dp),
                 ("is_dir", _up), ("n_wc", C.c_int32), ("wc_ptr", _ip), ("wc_vert", _ip),
-                ("wc_w", _dp), ("wc_K", _dp), ("n_planes", C.c_int32), ("planes", _dp)]
+                ("wc_w", _dp), ("wc_K", _dp), ("n_planes", C.c_int32), ("planes", _dp),
+                ("minert", _dp), ("xhat", _dp)]
 
 
 class _Opts(C.Structure):
@@ -80,6 +81,7 @@ def lib():
         L.or_prep.argtypes = [C.c_int32, C.c_int32, _dp, _ip, _dp, _dp]
         L.or_prep.restype = C.c_int
         L.or_body_force.argtypes = [C.c_int32, C.c_int32, _ip, _dp, C.c_double, _dp, _dp]
+        L.or_lumped_mass.argtypes = [C.c_int32, C.c_int32, _ip, _dp, C.c_double, _dp]
         L.or_color.argtypes = [C.POINTER(_Problem), _ip]
         L.or_color.restype = C.c_int32
         L.or_residual.argtypes = [C.POINTER(_Problem), _dp, _dp, _dp]
@@ -203,6 +205,20 @@ class OracleProblem:
     dN: np.ndarray
     dirichlet_idx: np.ndarray
     dirichlet_x: np.ndarray
+    mass: np.ndarray = None          # lumped m_ii (Eq. fem_be)
+    minert: np.ndarray = None        # m_ii / dt^2 on free vertices, or None
+    xhat: np.ndarray = None          # 2 x^n - x^{n-1}
+
+    def set_inertia(self, dt, x_n=None, x_prev=None):
+        """Backward-Euler inertia with time step dt and xhat = 2 x^n - x^{n-1};
+        dt <= 0 removes it."""
+        if dt is None or dt <= 0:
+            self.minert = self.xhat = None
+            return
+        m = self.mass / (dt * dt)
+        m[self.is_dir != 0] = 0.0
+        self.minert = np.ascontiguousarray(m)
+        self.xhat = np.ascontiguousarray(2.0 * _f64(x_n, (-1, 3)) - _f64(x_prev, (-1, 3)))
 
     def struct(self) -> _Problem:
         s = _Problem()
@@ -215,6 +231,8 @@ class OracleProblem:
                                                 _d(self.wc_w), _d(self.wc_K))
         s.n_planes = self.planes.shape[0]
         s.planes = _d(self.planes)
+        if self.minert is not None:
+            s.minert, s.xhat = _d(self.minert), _d(self.xhat)
         return s
 
 
@@ -244,6 +262,9 @@ def make_problem(sc, mu=None, lam=None) -> OracleProblem:
         fext += np.asarray(sc.nodal_force, np.float64).reshape(nv, 3)
     is_dir = np.zeros(nv, np.uint8)
     is_dir[np.asarray(sc.dirichlet_idx, np.int64)] = 1
+    mass = np.zeros(nv)
+    if nt > 0:
+        L.or_lumped_mass(nv, nt, _i(T), _d(V0), float(sc.density), _d(mass))
     return OracleProblem(nv=nv, nt=nt, model=COROTATED if sc.model == "corotated" else NEOHOOKEAN,
                          X=X, tets=T, mu=mu, lam=lam, fext=np.ascontiguousarray(fext),
                          is_dir=is_dir,
@@ -254,7 +275,7 @@ def make_problem(sc, mu=None, lam=None) -> OracleProblem:
                          planes=np.ascontiguousarray(np.asarray(sc.planes, np.float64).reshape(-1, 5)),
                          V0=V0[:nt], dN=dN[:nt],
                          dirichlet_idx=np.asarray(sc.dirichlet_idx, np.int32),
-                         dirichlet_x=np.asarray(sc.dirichlet_x, np.float64))
+                         dirichlet_x=np.asarray(sc.dirichlet_x, np.float64), mass=mass)
 
 
 def color(op: OracleProblem):

@@ -21,6 +21,8 @@
  *   Sec. "Modified Hessian"                    Eq. (hess), (mod_hess_dens), (mod_hess)
  *   Sec. "Acceleration Techniques"             Chebyshev and SOR updates
  *   Sec. "Coloring and Parallelism"            node colouring with sets S_c
+ *   Sec. "Position-Based Dynamics: Constraint-Based Nonlinear Gauss-Seidel"
+ *                                              Eq. (fem_be), lumped mass m_ii
  */
 #include <math.h>
 #include <stdint.h>
@@ -58,6 +60,12 @@ typedef struct {
     const double* wc_K;     /* [n_wc][6]                        */
     int32_t n_planes;
     const double* planes;   /* [n_planes][5]                    */
+    /* Backward-Euler inertia (Eq. fem_be written as the minimisation of the
+     * incremental potential): when minert is not NULL the energy gains
+     * sum_i 1/2 minert_i |y_i - xhat_i|^2, minert_i = m_ii / dt^2 (zero on
+     * Dirichlet vertices), xhat = 2 x^n - x^{n-1}. */
+    const double* minert;   /* [nv] or NULL                     */
+    const double* xhat;     /* [nv][3]                          */
 } or_problem;
 
 typedef struct {
@@ -354,6 +362,28 @@ void or_body_force(int32_t nv, int32_t nt, const int32_t* tets, const double* V0
             for (int c = 0; c < 3; ++c) fext[3 * tets[4 * e + j] + c] += density * grav[c] * V0[e] / 4.0;
 }
 
+/* Lumped mass of Eq. (fem_be): m_ii = int R0 N_i dX, which for linear tets
+ * is R0 V0_e / 4 from every incident tet.  Accumulates into m[nv]. */
+void or_lumped_mass(int32_t nv, int32_t nt, const int32_t* tets, const double* V0,
+                    double density, double* m)
+{
+    (void)nv;
+    for (int e = 0; e < nt; ++e)
+        for (int j = 0; j < 4; ++j) m[tets[4 * e + j]] += density * V0[e] / 4.0;
+}
+
+/* Inertia term 1/2 minert_i |yi - xhat_i|^2 of vertex i (0 without inertia). */
+static double inertia_energy(const or_problem* p, int i, const double* yi)
+{
+    if (!p->minert) return 0.0;
+    double s = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double d = yi[a] - p->xhat[3 * i + a];
+        s += d * d;
+    }
+    return 0.5 * p->minert[i] * s;
+}
+
 /* F_e(y) = sum_j y_j dN_j^T. */
 static void deformation_gradient(const double* y, const int32_t* t, const double* g, double* F)
 {
@@ -536,6 +566,9 @@ static double local_energy(const or_problem* p, const or_adj* A, const double* y
     double w = -(yi[0] * p->fext[3 * i] + yi[1] * p->fext[3 * i + 1] + yi[2] * p->fext[3 * i + 2]);
     E += w;
     ab += fabs(w);
+    w = inertia_energy(p, i, yi);
+    E += w;
+    ab += fabs(w);
     if (absum) *absum += ab;
     return E;
 }
@@ -593,6 +626,11 @@ static void local_system(const or_problem* p, const or_adj* A, const double* y, 
                 for (int b = 0; b < 3; ++b) Ai[3 * a + b] += pl[4] * pl[a] * pl[b];
             }
     }
+    if (p->minert)
+        for (int a = 0; a < 3; ++a) {
+            gi[a] += p->minert[i] * (y[3 * i + a] - p->xhat[3 * i + a]);
+            Ai[3 * a + a] += p->minert[i];
+        }
 }
 
 static double to_f32(double v) { return (double)(float)v; }
@@ -686,6 +724,10 @@ double or_residual(const or_problem* p, const double* y, double* r_out /* nullab
             }
         }
         for (int a = 0; a < 3; ++a) E -= y[3 * i + a] * p->fext[3 * i + a];
+        if (p->minert) {
+            E += inertia_energy(p, i, y + 3 * i);
+            for (int a = 0; a < 3; ++a) f[3 * i + a] -= p->minert[i] * (y[3 * i + a] - p->xhat[3 * i + a]);
+        }
     }
     double n2 = 0.0;
     for (int i = 0; i < p->nv; ++i)
@@ -880,7 +922,7 @@ int32_t or_update_vertices(const or_problem* p, const double* y, int32_t n, cons
 /* out = H v, with H = d^2 E / dy^2 at y, for every vertex (Dirichlet rows
  * included; callers restrict).  Element part: sum_e V0 dP_e[sum_j v_j dN_j^T]
  * dN_i (Eq. hess with the exact density); weak constraints: s_ci K_c
- * sum_j s_cj v_j; active planes: k n n^T v_i. */
+ * sum_j s_cj v_j; active planes: k n n^T v_i; inertia: minert_i v_i. */
 int32_t or_hvp(const or_problem* p, const double* y, const double* v, double* out)
 {
     if (p->model != OR_NEOHOOKEAN) return -3;
@@ -920,6 +962,9 @@ int32_t or_hvp(const or_problem* p, const double* y, const double* v, double* ou
                 for (int a = 0; a < 3; ++a) out[3 * i + a] += pl[4] * pl[a] * nv_;
             }
         }
+    if (p->minert)
+        for (int i = 0; i < p->nv; ++i)
+            for (int a = 0; a < 3; ++a) out[3 * i + a] += p->minert[i] * v[3 * i + a];
     adj_free(&A);
     return 0;
 }
