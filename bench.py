@@ -179,6 +179,10 @@ def main():
         progress("differentiable report done")
         extras["muscles"] = muscles_report(pbng, S, torch, stream)
         progress("muscles report done")
+        extras["paper_blocks"] = paper_boxes_report(pbng, S, torch, stream)
+        progress("paper stretching blocks done")
+        extras["backward_euler"] = dynamics_report(pbng, S, torch, stream)
+        progress("backward Euler report done")
 
     sweeps = max(s["sweeps"] for s in last)
     line = {
@@ -360,6 +364,76 @@ def muscles_report(pbng, S, torch, stream):
                      "rel_residual_fp64": st[0]["rel_residual"],
                      "safeguard_rejections": st[0]["rejected"]}
     return out
+
+
+def paper_boxes_report(pbng, S, torch, stream):
+    """The paper's quasistatic stretching blocks (Table 3 rows with 1
+    substep): 32^3 corotated and Neo-Hookean at 40 iterations per frame, 64^3
+    at 20, 128^3 at 40.  A frame sets that frame's Dirichlet targets and runs
+    the iterations from the previous frame's positions (Chebyshev rho = 0.95,
+    relaxation 1.7, FP32), with one FP64 residual at the end.  The paper's
+    per-frame times were measured on a 64-core CPU; they are context."""
+    rows = [(32, "corotated", 40, 1300.0), (32, "nh", 40, 825.0), (64, "corotated", 20, 1300.0),
+            (128, "corotated", 40, 61000.0)]
+    out = []
+    for n, model, iters, paper_ms in rows:
+        sc, frames = S.paper_box_frames(n, model, n_frames=4)
+        ws = pbng.Workspace([pbng.problem_from_scenario(sc)], real="f32")
+        so = pbng.solve_opts(max_sweeps=iters, rel_tol=0.0, check_every=iters, accel="chebyshev",
+                             rho=0.95, gamma=1.7, safeguard="backtrack")
+        x = torch.tensor(sc.initial_iterate(), dtype=torch.float32, device="cuda")
+        xds = [torch.tensor(f, dtype=torch.float64, device="cuda") for f in frames]
+        ws.set_dirichlet(xds[0], stream=stream)
+        ws.solve(x, so, stream=stream)          # frame 1 (warm-up)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = []
+        for xd in xds[1:]:
+            ws.set_dirichlet(xd, stream=stream)
+            rc, st = ws.solve(x, so, stream=stream)
+            sts.append(st[0])
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / len(xds[1:])
+        out.append({"block": "%d^3" % n, "vertices": sc.n_verts, "tets": sc.n_tets,
+                    "model": model, "iterations_per_frame": iters,
+                    "ms_per_frame": round(t * 1e3, 3),
+                    "vertex_updates_per_s": round(sc.n_free * iters / t, 1),
+                    "frame_rel_residual_fp64": [round(s["rel_residual"], 6) for s in sts],
+                    "paper_ms_per_frame_cpu": paper_ms})
+        del ws, x, xds
+        torch.cuda.empty_cache()
+    return out
+
+
+def dynamics_report(pbng, S, torch, stream, frames=8):
+    """Backward Euler (inertia term of Eq. fem_be): the 128x32x32 Neo-Hookean
+    beam released from rest under gravity, one step of dt = 1/30 s per
+    frame, 40 Chebyshev iterations per frame, FP32."""
+    sc = S.config_beam_f32()
+    dt, iters = 1.0 / 30.0, 40
+    ws = pbng.Workspace([pbng.problem_from_scenario(sc)], real="f32")
+    so = pbng.solve_opts(max_sweeps=iters, rel_tol=0.0, check_every=iters, accel="chebyshev",
+                         rho=0.95, gamma=1.7, safeguard="backtrack")
+    x_prev = torch.tensor(sc.initial_iterate(), dtype=torch.float64, device="cuda")
+    x_n = x_prev.clone()
+    x = x_n.float()
+    times, rels = [], []
+    for f in range(frames):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ws.set_inertia(dt, x_n, x_prev, stream=stream)
+        rc, st = ws.solve(x, so, stream=stream)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        rels.append(st[0]["rel_residual"])
+        x_prev, x_n = x_n, x.double()
+    tip = float(x_n[:, 1].min() - x_prev.new_tensor(sc.initial_iterate())[:, 1].min())
+    t = sum(times[1:]) / (frames - 1)
+    return {"workload": "beam 128x32x32 Neo-Hookean, gravity, dt = 1/30 s", "frames": frames,
+            "iterations_per_frame": iters, "ms_per_frame": round(t * 1e3, 3),
+            "vertex_updates_per_s": round(sc.n_free * iters / t, 1),
+            "frame_rel_residual_fp64": [round(r, 6) for r in rels],
+            "lowest_point_drop_m": round(-tip, 6)}
 
 
 def cpu_baseline(sc, sweeps):

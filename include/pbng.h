@@ -256,6 +256,20 @@ int32_t pbng_workspace_set_materials(pbng_workspace* ws, const double* mu_dev,
                                      const double* lambda_dev, void* hip_stream);
 int32_t pbng_workspace_set_dirichlet(pbng_workspace* ws, const double* xd_dev, void* hip_stream);
 
+/* Backward-Euler inertia (Eq. fem_be, minimised as the incremental
+ * potential): with dt > 0 every later solve, residual and adjoint of the
+ * workspace adds sum over free vertices i of 1/2 m_ii / dt^2 |y_i - xhat_i|^2
+ * to the energy, with xhat = 2 x^n - x^{n-1} and the lumped mass
+ * m_ii = R0 sum_{e incident to i} V0_e / 4 (R0 = each problem's `density`).
+ * Then A_i gains m_ii / dt^2 I and g_i gains m_ii / dt^2 (y_i - xhat_i).
+ * x_n_dev, x_prev_dev: device double arrays [n_verts][3] over all instances
+ * in the caller's order (Dirichlet rows are ignored), read on hip_stream
+ * before the call returns to the stream; the workspace keeps its own copy of
+ * xhat.  dt <= 0 switches inertia off (the pointers may then be NULL).
+ * Errors: PBNG_EINVAL (null arrays with dt > 0, non-finite dt), PBNG_EHIP. */
+int32_t pbng_workspace_set_inertia(pbng_workspace* ws, double dt, const double* x_n_dev,
+                                   const double* x_prev_dev, void* hip_stream);
+
 /*
  * Solve (Eq. pbgn_update / pbgn_dx over the colours, with the optional
  * Chebyshev / SOR blend of Sec. "Acceleration Techniques").  x_inout

@@ -339,7 +339,7 @@ struct pbng_workspace {
     // A and do not change either argument.
     bool safeguard_inactive = false;
     // general sweep kernel: batched instances, weak constraints or planes
-    bool general() const { return any_wc || n_inst > 1; }
+    bool general() const { return any_wc || n_inst > 1 || inertia; }
     int device = 0;
     std::vector<int> col_ptr;              // internal free-vertex range of each colour
     std::vector<int64_t> v_off, t_off;     // per instance
@@ -352,6 +352,9 @@ struct pbng_workspace {
     // sweep data
     Dev W, P, N, Wres;
     Dev jv, ma, mb, mc, vmu, Sv, flag, vptr, fext, vinst, active, rejected;
+    // backward-Euler inertia (off until pbng_workspace_set_inertia)
+    bool inertia = false;
+    Dev mass64, inert, xhat, inert64, xhat64;
     Dev wvptr, wv_c, wv_s, wc_ptr, wc_vert, wc_w, wc_K, plane_ptr, planes;
     // FP64 data
     Dev tet, geo, vp, ebuf, tet_eidx, vorder, vert_eidx, rvptr, rv, fext64, vinst_all;
@@ -502,6 +505,7 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     std::vector<int32_t> colors(nv);
     std::vector<double> dminv(9 * nt), V0(nt), mu(nt), lam(nt);
     std::vector<double> fext(3 * nv, 0.0);
+    std::vector<double> mass(nv, 0.0);
     std::vector<char> isdir(nv, 0);
     std::vector<int> valence(nv, 0);
     std::vector<Incidence> inc(n);
@@ -527,6 +531,8 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
             for (int j = 0; j < 4; ++j)
                 for (int a = 0; a < 3; ++a)
                     fext[3 * (vo + p->tets[4 * e + j]) + a] += p->density * p->gravity[a] * V0[to + e] / 4.0;
+            // lumped mass m_ii = R0 sum V0_e / 4 (Eq. fem_be), for inertia
+            for (int j = 0; j < 4; ++j) mass[vo + p->tets[4 * e + j]] += p->density * V0[to + e] / 4.0;
         }
         if (p->nodal_force)
             for (int64_t i = 0; i < 3ll * p->n_verts; ++i) fext[3 * vo + i] += p->nodal_force[i];
@@ -646,11 +652,12 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     }
 
     // per-vertex arrays in internal order
-    std::vector<double> fext_int(3 * nv), fext_free(4 * nfree, 0.0);
+    std::vector<double> fext_int(3 * nv), fext_free(4 * nfree, 0.0), mass_free(nfree);
     std::vector<int> vinst_all(nv), orig_of(nv);
     for (int64_t k = 0; k < nv; ++k) {
         const int gv = order[k];
         orig_of[k] = gv;
+        if (k < nfree) mass_free[k] = mass[gv];
         vinst_all[k] = inst_of[gv];
         for (int a = 0; a < 3; ++a) fext_int[3 * k + a] = fext[3 * gv + a];
         if (k < nfree)
@@ -757,6 +764,7 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
         ws->Sv.alloc(size_t(nfree) * r);
     }
     upR(ws->fext, fext_free);
+    ws->mass64.upload(mass_free);
     std::vector<int> vinst_free(vinst_all.begin(), vinst_all.begin() + nfree);
     ws->vinst.upload(vinst_free);
     ws->active.alloc(n * sizeof(int));
@@ -833,6 +841,8 @@ SweepArgs<R, PR> sweep_args(pbng_workspace* ws, double omega, double gamma, int 
     a.plane_ptr = ws->plane_ptr.as<int>();
     a.planes = ws->planes.as<R>();
     a.rejected = ws->rejected.as<int>();
+    a.inert = ws->inertia ? ws->inert.as<R>() : nullptr;
+    a.xhat = ws->inertia ? ws->xhat.as<P4>() : nullptr;
     a.omega = PR(omega);
     a.gamma = PR(gamma);
     a.max_halvings = max_halvings;
@@ -867,6 +877,8 @@ ResArgs<R> res_args(pbng_workspace* ws, const void* X)
     a.plane_ptr = ws->plane_ptr.as<int>();
     a.planes64 = ws->planes64.as<double>();
     a.orig_of = ws->orig_of.as<int>();
+    a.inert64 = ws->inertia ? ws->inert64.as<double>() : nullptr;
+    a.xhat64 = ws->inertia ? ws->xhat64.as<double>() : nullptr;
     a.n_free = int(ws->nfree);
     a.n_verts = int(ws->nv);
     a.n_tets = int(ws->nt);
@@ -1140,6 +1152,7 @@ AdjArgs<R, PR> adj_args(pbng_workspace* ws, double omega, double gamma)
     a.wc_K = ws->wc_K.as<R>();
     a.plane_ptr = ws->plane_ptr.as<int>();
     a.planes = ws->planes.as<R>();
+    a.inert = ws->inertia ? ws->inert.as<R>() : nullptr;
     a.omega = PR(omega);
     a.gamma = PR(gamma);
     return a;
@@ -1205,7 +1218,7 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
         omega_prev = omega;
         const AdjArgs<R, PR> a = adj_args<R, PR>(ws, omega, accel ? o->gamma : 1.0);
         for (int c = 0; c < ws->ncol; ++c)
-            hipchk(launch_adjoint_phase<R, PR>(a, pick_lanes(ws, o->lanes, c), accel, ws->any_wc, ws->col_ptr[c],
+            hipchk(launch_adjoint_phase<R, PR>(a, pick_lanes(ws, o->lanes, c), accel, ws->any_wc || ws->inertia, ws->col_ptr[c],
                                            ws->col_ptr[c + 1], s),
                    "adjoint launch");
         if (accel) std::swap(ws->L.p, ws->LN.p);
@@ -1521,6 +1534,51 @@ int32_t pbng_workspace_set_dirichlet(pbng_workspace* ws, const double* xd_dev, v
             hipchk(launch_set_dirichlet<float>(xd_dev, ws->dir_internal.as<int>(), ws->nd, int(ws->nfree),
                                                ws->xd_int.as<float4>(), s),
                    "set dirichlet");
+        ws->ring_valid = false;
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_workspace_set_inertia(pbng_workspace* ws, double dt, const double* x_n_dev,
+                                   const double* x_prev_dev, void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (std::isnan(dt) || std::isinf(dt)) fail(PBNG_EINVAL, "time step must be finite");
+        const bool was = ws->inertia;
+        if (dt <= 0.0) {
+            ws->inertia = false;
+        } else {
+            if (!x_n_dev || !x_prev_dev) fail(PBNG_EINVAL, "null x^n or x^{n-1} array");
+            hipStream_t s = static_cast<hipStream_t>(hip_stream);
+            const int nf = int(ws->nfree);
+            if (!ws->inert.p) {
+                ws->inert.alloc(size_t(nf) * (ws->math64() ? sizeof(double) : sizeof(float)));
+                ws->xhat.alloc(size_t(nf) * ws->r4());
+                ws->inert64.alloc(size_t(nf) * sizeof(double));
+                ws->xhat64.alloc(size_t(nf) * 3 * sizeof(double));
+            }
+            hipError_t e;
+            if (ws->real == PBNG_F64)
+                e = launch_set_inertia<double, double>(x_n_dev, x_prev_dev, ws->orig_of.as<int>(),
+                                                       ws->mass64.as<double>(), nf, dt, ws->inert.as<double>(),
+                                                       ws->xhat.as<double4>(), ws->inert64.as<double>(),
+                                                       ws->xhat64.as<double>(), s);
+            else if (ws->real == PBNG_MIXED)
+                e = launch_set_inertia<float, double>(x_n_dev, x_prev_dev, ws->orig_of.as<int>(),
+                                                      ws->mass64.as<double>(), nf, dt, ws->inert.as<float>(),
+                                                      ws->xhat.as<double4>(), ws->inert64.as<double>(),
+                                                      ws->xhat64.as<double>(), s);
+            else
+                e = launch_set_inertia<float, float>(x_n_dev, x_prev_dev, ws->orig_of.as<int>(),
+                                                     ws->mass64.as<double>(), nf, dt, ws->inert.as<float>(),
+                                                     ws->xhat.as<float4>(), ws->inert64.as<double>(),
+                                                     ws->xhat64.as<double>(), s);
+            hipchk(e, "set inertia");
+            ws->inertia = true;
+        }
+        // the kernel variant (and its arguments) changes with inertia on or off
+        if (was != ws->inertia) ws->drop_graph();
         ws->ring_valid = false;
         return PBNG_OK;
     });

@@ -83,6 +83,8 @@ struct SweepArgs {
     const int* plane_ptr;  // [n_inst + 1]
     const R* planes;       // [n_planes][5]
     int* rejected;         // [n_inst]
+    const R* inert;        // [n_free] m_ii / dt^2 (backward Euler), or null
+    const P4* xhat;        // [n_free] 2 x^n - x^{n-1}
     PR omega, gamma;
     int max_halvings;
 };
@@ -114,6 +116,8 @@ struct ResArgs {
     const int* plane_ptr;
     const double* planes64;
     const int* orig_of;     // [n_verts] caller index of each internal vertex
+    const double* inert64;  // [n_free] m_ii / dt^2, or null
+    const double* xhat64;   // [n_free][3]
     int n_free;
     int n_verts;
     int n_tets;
@@ -192,6 +196,15 @@ template <class R>
 hipError_t launch_load_vec(const R* v_user, const int* orig_of, typename R4t<R>::T* dst,
                            int n_free, int n_verts, hipStream_t s);
 
+// Backward-Euler inertia: from caller-order x^n, x^{n-1} ([n_verts][3]
+// double) and the lumped masses of the free vertices (internal order), the
+// sweep's m/dt^2 and xhat = 2 x^n - x^{n-1} (R, PR) and their FP64 copies.
+template <class R, class PR>
+hipError_t launch_set_inertia(const double* x_n, const double* x_prev, const int* orig_of,
+                              const double* mass, int n_free, double dt, R* inert,
+                              typename R4t<PR>::T* xhat, double* inert64, double* xhat64,
+                              hipStream_t s);
+
 // Adjoint block Gauss-Seidel phase: L holds lambda (internal order), B the
 // right-hand side dL/dx (internal order, free vertices), X the equilibrium.
 template <class R, class PR = R>
@@ -221,6 +234,7 @@ struct AdjArgs {
     const R* wc_K;
     const int* plane_ptr;
     const R* planes;
+    const R* inert;        // [n_free] m_ii / dt^2, or null
     PR omega, gamma;
 };
 template <class R, class PR>

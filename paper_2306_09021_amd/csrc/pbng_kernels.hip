@@ -430,6 +430,22 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
             }
         }
     }
+    if (GEN && a.inert) {
+        // backward-Euler inertia: 1/2 c |y_i - xhat_i|^2, c = m_ii / dt^2,
+        // exactly quadratic (so it also joins the safeguard's exact part)
+        const R c = at(a.inert, v);
+        const V3<R> dx = cvt<R>(xi - xyz(at(a.xhat, v)));
+        g = g + c * dx;
+        Aw.xx += c;
+        Aw.yy += c;
+        Aw.zz += c;
+        if (SAFE && MODEL == kCor) {
+            gw = gw + c * dx;
+            Kw.xx += c;
+            Kw.yy += c;
+            Kw.zz += c;
+        }
+    }
     const V3<R> f = xyz(at(a.fext, v));
     const V3<R> gt = g - f;
     Sym<R> A = Aw;
@@ -689,6 +705,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg
         lsum3<LANES>(r);
         lsum6<LANES>(Hc);
     }
+    if (WC && a.inert) {
+        const R c = at(a.inert, v);
+        r = r + c * cvt<R>(li);
+        Hc.xx += c;
+        Hc.yy += c;
+        Hc.zz += c;
+    }
     Hc.xx += S;
     Hc.yy += S;
     Hc.zz += S;
@@ -880,12 +903,20 @@ __global__ __launch_bounds__(kBlock) void k_vertex_residual(ResArgs<R> a, double
             gp = gp + (pl[4] * phi) * n;
         }
     }
-    a.ebuf[a.vert_eidx[k]] = ev;
     V3<double> r = mk(0.0, 0.0, 0.0);
     if (v < a.n_free) {
         r = f - gp - gather_vp(a, v);
         if (a.n_wc > 0) r = r - weak_force(a, v, a.X);
+        if (a.inert64) {
+            // backward-Euler inertia 1/2 c |x - xhat|^2, c = m_ii / dt^2
+            const double c = a.inert64[v];
+            const double* xh = a.xhat64 + 3 * int64_t(v);
+            const V3<double> d = xi - mk(xh[0], xh[1], xh[2]);
+            r = r - c * d;
+            ev += 0.5 * c * dot(d, d);
+        }
     }
+    a.ebuf[a.vert_eidx[k]] = ev;
     rsq[k] = dot(r, r);
     if (r_out) {
         double* o = r_out + 3 * int64_t(a.orig_of[v]);
@@ -974,6 +1005,7 @@ __global__ __launch_bounds__(kBlock) void k_vertex_adjoint(ResArgs<R> a,
         if (dot(n, xi) - pl[3] < 0.0) hl = hl + (pl[4] * dot(n, li)) * n;
     }
     if (v < a.n_free) {
+        if (a.inert64) hl = hl + a.inert64[v] * li;
         const V3<double> r = x64(B[v]) - hl;
         rsq[k] = dot(r, r);
     } else {
@@ -1274,6 +1306,38 @@ hipError_t launch_set_dirichlet(const double* xd, const int* dir_internal, int n
 // Explicit instantiations.  The library compiles this file once per
 // PBNG_KERNEL_SET (0: FP32, 1: FP64, 2: FP32 arithmetic on FP64 positions)
 // so the three sets build in parallel; set 0 also holds the shared helpers.
+template <class R, class PR>
+__global__ __launch_bounds__(kBlock) void k_set_inertia(const double* x_n, const double* x_prev,
+                                                        const int* orig_of, const double* mass,
+                                                        int n_free, double inv_dt2, R* inert,
+                                                        typename R4t<PR>::T* xhat, double* inert64,
+                                                        double* xhat64)
+{
+    const int v = blockIdx.x * kBlock + threadIdx.x;
+    if (v >= n_free) return;
+    const int64_t o = 3 * int64_t(orig_of[v]);
+    double h[3];
+    for (int c = 0; c < 3; ++c) h[c] = 2.0 * x_n[o + c] - x_prev[o + c];
+    const double w = mass[v] * inv_dt2;
+    inert[v] = R(w);
+    xhat[v] = typename R4t<PR>::T{PR(h[0]), PR(h[1]), PR(h[2]), PR(0)};
+    inert64[v] = w;
+    for (int c = 0; c < 3; ++c) xhat64[3 * int64_t(v) + c] = h[c];
+}
+
+template <class R, class PR>
+hipError_t launch_set_inertia(const double* x_n, const double* x_prev, const int* orig_of,
+                              const double* mass, int n_free, double dt, R* inert,
+                              typename R4t<PR>::T* xhat, double* inert64, double* xhat64,
+                              hipStream_t s)
+{
+    if (n_free > 0)
+        hipLaunchKernelGGL((k_set_inertia<R, PR>), dim3(nblk(n_free)), dim3(kBlock), 0, s, x_n,
+                           x_prev, orig_of, mass, n_free, 1.0 / (dt * dt), inert, xhat, inert64,
+                           xhat64);
+    return hipGetLastError();
+}
+
 #define PBNG_INST_POS(R)                                                                          \
     template hipError_t launch_load<R>(const R*, const int*, const R4t<R>::T*, R4t<R>::T*,       \
                                        R4t<R>::T*, R4t<R>::T*, int, int, hipStream_t);           \
@@ -1293,7 +1357,10 @@ hipError_t launch_set_dirichlet(const double* xd, const int* dir_internal, int n
     template hipError_t launch_phase<R, PR>(const SweepArgs<R, PR>&, int, int, bool, bool, bool,  \
                                             int, int, hipStream_t);                               \
     template hipError_t launch_adjoint_phase<R, PR>(const AdjArgs<R, PR>&, int, bool, bool, int,  \
-                                                    int, hipStream_t);
+                                                    int, hipStream_t);                            \
+    template hipError_t launch_set_inertia<R, PR>(const double*, const double*, const int*,       \
+                                                  const double*, int, double, R*, R4t<PR>::T*,    \
+                                                  double*, double*, hipStream_t);
 #if PBNG_KERNEL_SET == 0
 PBNG_INST_POS(float)
 PBNG_INST_POS(double)

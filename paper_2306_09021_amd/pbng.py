@@ -95,6 +95,7 @@ def lib():
                                      C.POINTER(C.c_int64), C.POINTER(C.c_int32)], C.c_int32),
             "pbng_workspace_set_materials": ([vp, vp, vp, vp], C.c_int32),
             "pbng_workspace_set_dirichlet": ([vp, vp, vp], C.c_int32),
+            "pbng_workspace_set_inertia": ([vp, C.c_double, vp, vp, vp], C.c_int32),
             "pbng_solve": ([vp, vp, C.POINTER(SolveOpts), C.POINTER(Stats), vp], C.c_int32),
             "pbng_residual": ([vp, vp, _dp, _dp, vp, vp], C.c_int32),
             "pbng_adjoint": ([vp, vp, vp, vp, vp, vp, vp, C.POINTER(AdjointOpts),
@@ -120,7 +121,8 @@ def exported_symbols() -> List[str]:
     return ["pbng_version", "pbng_last_error", "pbng_lame", "pbng_default_solve_opts",
             "pbng_default_adjoint_opts", "pbng_color", "pbng_workspace_create",
             "pbng_workspace_destroy", "pbng_workspace_info", "pbng_workspace_set_materials",
-            "pbng_workspace_set_dirichlet", "pbng_solve", "pbng_residual", "pbng_adjoint",
+            "pbng_workspace_set_dirichlet", "pbng_workspace_set_inertia", "pbng_solve",
+            "pbng_residual", "pbng_adjoint",
             "pbng_load", "pbng_store", "pbng_sweeps", "pbng_phase", "pbng_phase_bytes",
             "pbng_autotune"]
 
@@ -373,6 +375,24 @@ class Workspace:
             raise ValueError("Dirichlet targets must be a float64 cuda tensor")
         _check(lib().pbng_workspace_set_dirichlet(self.handle, _ptr(xd.contiguous()),
                                                   _stream(stream)))
+
+    def set_inertia(self, dt, x_n=None, x_prev=None, stream=None):
+        """Backward-Euler inertia with time step dt and xhat = 2 x^n - x^{n-1}
+        (float64 cuda tensors [n_verts, 3], caller order); dt <= 0 turns it
+        off."""
+        import torch
+        if dt > 0:
+            for t in (x_n, x_prev):
+                if t is None or t.dtype != torch.float64 or not t.is_cuda or \
+                        t.numel() != 3 * self.n_verts:
+                    raise ValueError("x^n and x^{n-1} must be float64 cuda tensors [%d, 3]"
+                                     % self.n_verts)
+            x_n, x_prev = x_n.contiguous(), x_prev.contiguous()
+            _check(lib().pbng_workspace_set_inertia(self.handle, float(dt), _ptr(x_n),
+                                                    _ptr(x_prev), _stream(stream)))
+        else:
+            _check(lib().pbng_workspace_set_inertia(self.handle, float(dt), None, None,
+                                                    _stream(stream)))
 
     # measurement access ---------------------------------------------------
     def load(self, x, stream=None):

@@ -177,6 +177,41 @@ def twist_box(n: int = 10, model: str = COROTATED, E: float = 1e4, nu: float = 0
                                real="f64", rel_tol=0.0))
 
 
+def paper_box_frames(n: int, model: str = COROTATED, n_frames: int = 4, E: float = 1e5,
+                     nu: float = 0.3, density: float = 10.0, twist_deg: float = 90.0,
+                     stretch: float = 1.5):
+    """The paper's stretching block (Sec. "Examples", "Stretching Block"):
+    unit cube of n^3 vertices (n = 32, 64, 128 give the 32K/150K, 260K/1250K
+    and 2097K/10242K meshes of Table 3), R0 = 10, E = 1e5, nu = 0.3, no
+    gravity, both end faces (y = 0 and y = 1) clamped and moved in opposite
+    directions: at frame k of n_frames each is twisted by +-k/n_frames of
+    twist_deg / 2 about the vertical line x = z = 0.5 and pulled apart so the
+    height is 1 + k/n_frames (stretch - 1).  Returns the scenario (targets of
+    frame 1, start at rest) and the Dirichlet targets of frames 1..n_frames."""
+    h = 1.0 / (n - 1)
+    X, T = box_mesh(n, n, n, h)
+    bot = _layer(X, n, 1, 0.0)
+    top = _layer(X, n, 1, 1.0)
+    didx = np.concatenate([bot, top]).astype(np.int32)
+    c = np.array([0.5, 0.0, 0.5])
+    frames = []
+    for k in range(1, n_frames + 1):
+        t = k / n_frames
+        out = []
+        for idx, sgn in ((bot, -1.0), (top, 1.0)):
+            R = _rot_about_axis([0, 1, 0], sgn * t * math.radians(twist_deg) / 2.0)
+            xt = X[idx].copy()
+            xt[:, 1] = 0.0
+            xt = c + (xt - c) @ R.T
+            xt[:, 1] = X[idx, 1] + sgn * 0.5 * t * (stretch - 1.0)
+            out.append(xt)
+        frames.append(np.concatenate(out))
+    sc = Scenario(name=f"paper_box_{n}", rest_pos=X, tets=T, model=model,
+                  E=np.asarray(E, np.float64), nu=np.asarray(nu, np.float64),
+                  dirichlet_idx=didx, dirichlet_x=frames[0], x0=X.copy(), density=density)
+    return sc, frames
+
+
 def config_plain_f64() -> Scenario:
     """Plain PBNG in FP64: 10^3-vertex unit cube (3,645 tets), fixed-corotated,
     E = 1e4, nu = 0.3, bottom pinned, top stretched 1.3x and twisted 90 deg,

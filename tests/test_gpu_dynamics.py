@@ -1,0 +1,199 @@
+"""Backward-Euler inertia on the GPU (pbng_workspace_set_inertia) against the
+FP64 oracle with the same incremental potential: one step in FP64, FP32 and
+MIXED, a sequence of time steps, the FP64 residual and energy, batched
+instances with different densities, the adjoint, and switching inertia off.
+
+Tolerances as for the quasistatic parity tests: FP64 1e-10 relative after
+the same sweeps, FP32 / MIXED 1e-5, residual and energy 1e-10, FP64 adjoint
+1e-8."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import dense as D
+from paper_2306_09021_amd import pbng
+from paper_2306_09021_amd import scenarios as S
+
+from .gpu_util import announce, dev_x, host, rel_err, require_gpu, torch, workspace
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5, "mixed": 1e-5}
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def moving_box(model, n=6, seed=5):
+    """A pinned, twisted box under gravity with an initial velocity field."""
+    sc = S.twist_box(n, model, 1e4, 0.3, 40.0, 1.1, 0.01, seed=seed)
+    sc.density, sc.gravity = 200.0, (0.0, -9.8, 0.0)
+    rng = np.random.default_rng(seed)
+    x_n = sc.initial_iterate()
+    x_prev = x_n - 2e-3 * rng.normal(size=x_n.shape)
+    return sc, x_n, x_prev
+
+
+def t64(a):
+    return torch.tensor(np.asarray(a, np.float64).reshape(-1, 3), dtype=torch.float64,
+                        device="cuda")
+
+
+@pytest.mark.parametrize("model", ["nh", "corotated"])
+@pytest.mark.parametrize("real", ["f64", "f32", "mixed"])
+def test_one_step_parity(model, real):
+    sc, x_n, x_prev = moving_box(model)
+    dt = 1e-2
+    op = O.make_problem(sc)
+    op.set_inertia(dt, x_n, x_prev)
+    col, _ = O.color(op)
+    kw = dict(accel="chebyshev", rho=0.9, gamma=1.3, safeguard="backtrack")
+    xo, sto = O.solve(op, col, x_n, max_sweeps=40, **kw)
+    announce("backward Euler one step %s %s" % (model, real))
+    ws = workspace([sc], real)
+    ws.set_inertia(dt, t64(x_n), t64(x_prev))
+    x = dev_x(x_n, real)
+    rc, st = ws.solve(x, max_sweeps=40, rel_tol=0.0, check_every=40, **kw)
+    e = rel_err(host(x), xo)
+    print(model, real, "rel err", e)
+    assert e <= TOL[real]
+
+
+@pytest.mark.parametrize("model", ["nh", "corotated"])
+def test_time_steps_parity(model):
+    """Six backward-Euler steps of 30 sweeps each, x^{n-1} <- x^n <- x^{n+1}
+    between steps, against the oracle step by step (FP64)."""
+    sc, x_n, x_prev = moving_box(model, n=5, seed=8)
+    dt = 5e-3
+    op = O.make_problem(sc)
+    col, _ = O.color(op)
+    ws = workspace([sc], "f64")
+    g_n, g_prev = t64(x_n), t64(x_prev)
+    o_n, o_prev = x_n.copy(), x_prev.copy()
+    announce("backward Euler 6 steps %s" % model)
+    for step in range(6):
+        op.set_inertia(dt, o_n, o_prev)
+        xo, _ = O.solve(op, col, o_n, max_sweeps=30, accel="none", safeguard="backtrack")
+        ws.set_inertia(dt, g_n, g_prev)
+        x = g_n.clone()
+        ws.solve(x, max_sweeps=30, rel_tol=0.0, check_every=30, accel="none",
+                 safeguard="backtrack")
+        assert rel_err(host(x), xo) <= 1e-10, step
+        o_prev, o_n = o_n, xo
+        g_prev, g_n = g_n, x
+    # the body has moved under gravity
+    assert np.abs(o_n - x_n).max() > 1e-4
+
+
+def test_residual_and_energy_with_inertia():
+    sc, x_n, x_prev = moving_box("nh")
+    op = O.make_problem(sc)
+    op.set_inertia(1e-2, x_n, x_prev)
+    x = x_n + 1e-3 * np.random.default_rng(1).normal(size=x_n.shape)
+    x[sc.dirichlet_idx] = sc.dirichlet_x
+    n_o, E_o, r_o = O.residual(op, x)
+    announce("residual with inertia f64")
+    ws = workspace([sc], "f64")
+    ws.set_inertia(1e-2, t64(x_n), t64(x_prev))
+    rn, E, r = ws.residual(dev_x(x, "f64"), want_r=True)
+    assert abs(rn[0] - n_o) <= 1e-10 * n_o
+    assert abs(E[0] - E_o) <= 1e-10 * abs(E_o)
+    assert np.abs(host(r) - r_o).max() <= 1e-10 * np.abs(r_o).max()
+
+
+def test_batched_instances_with_inertia():
+    """Two instances of different densities in one workspace against each
+    instance's own oracle solve."""
+    scs = []
+    for k, dens in enumerate((50.0, 800.0)):
+        sc, _, _ = moving_box("corotated", n=5, seed=20 + k)
+        sc.density = dens
+        scs.append(sc)
+    x_n = [s.initial_iterate() for s in scs]
+    x_prev = [x - 1e-3 for x in x_n]
+    announce("batched backward Euler 2 instances f64")
+    ws = workspace(scs, "f64")
+    ws.set_inertia(1e-2, t64(np.concatenate(x_n)), t64(np.concatenate(x_prev)))
+    x = dev_x(np.concatenate(x_n), "f64")
+    ws.solve(x, max_sweeps=25, rel_tol=0.0, check_every=25, accel="chebyshev", rho=0.9, gamma=1.2)
+    xg = host(x)
+    off = 0
+    for sc, a, b in zip(scs, x_n, x_prev):
+        op = O.make_problem(sc)
+        op.set_inertia(1e-2, a, b)
+        col, _ = O.color(op)
+        xo, _ = O.solve(op, col, a, max_sweeps=25, accel="chebyshev", rho=0.9, gamma=1.2)
+        assert rel_err(xg[off:off + sc.n_verts], xo) <= 1e-10
+        off += sc.n_verts
+
+
+def test_adjoint_with_inertia():
+    """Adjoint of one backward-Euler step (Neo-Hookean): H gains m/dt^2 I on
+    the free block; against the oracle's dense adjoint and gradient
+    assembly."""
+    rng = np.random.default_rng(11)
+    sc = S.random_cube(rng, 4, "nh", 1e4, 0.3, 15.0, 0.9, 1.1, "adj")
+    sc.density = 300.0
+    op = O.make_problem(sc)
+    x_n = sc.initial_iterate()
+    x_prev = x_n - 1e-3
+    op.set_inertia(1e-2, x_n, x_prev)
+    x, it, rel = D.newton(op, x_n, tol=1e-14)
+    target = sc.rest_pos + 0.05 * rng.normal(size=sc.rest_pos.shape)
+    free = (op.is_dir == 0)[:, None]
+    g = 2.0 * (x - target) * free
+    lam_d = D.adjoint_dense(op, x, g)
+    dmu, dla, dxd = O.adjoint_gradients(op, x, lam_d)
+    dxd = dxd[op.dirichlet_idx] + g[op.dirichlet_idx]
+    announce("adjoint with inertia f64")
+    ws = workspace([sc], "f64")
+    ws.set_inertia(1e-2, t64(x_n), t64(x_prev))
+    o = pbng.adjoint_opts(rel_tol=1e-12, max_sweeps=20000, check_every=20, accel="chebyshev",
+                          rho=0.9, gamma=1.0)
+    rc, out, st = ws.adjoint(dev_x(x, "f64"), dev_x(g, "f64"), o)
+    out = {k: host(v) for k, v in out.items()}
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert st[0]["rel_residual"] <= 1e-11
+    assert rel(out["lam_vec"], lam_d) <= 1e-8
+    assert rel(out["mu"], dmu) <= 1e-8
+    assert rel(out["lam"], dla) <= 1e-8
+    assert rel(out["xd"], dxd) <= 1e-8
+
+
+def test_inertia_off_restores_quasistatic_solve():
+    sc, x_n, x_prev = moving_box("nh", n=5)
+    announce("inertia on then off f64")
+    ws = workspace([sc], "f64")
+    x0 = dev_x(sc.initial_iterate(), "f64")
+    xa = x0.clone()
+    ws.solve(xa, max_sweeps=20, rel_tol=0.0, check_every=20)
+    ws.set_inertia(1e-2, t64(x_n), t64(x_prev))
+    xb = x0.clone()
+    ws.solve(xb, max_sweeps=20, rel_tol=0.0, check_every=20)
+    ws.set_inertia(0.0)
+    xc = x0.clone()
+    ws.solve(xc, max_sweeps=20, rel_tol=0.0, check_every=20)
+    assert torch.equal(xa, xc)
+    assert not torch.equal(xa, xb)
+
+
+def test_graph_replay_with_inertia():
+    """Sweeps replayed from a HIP graph equal plain launches bit for bit with
+    inertia on, and after xhat changes between steps."""
+    sc, x_n, x_prev = moving_box("corotated", n=5, seed=3)
+    announce("graph replay with inertia f32")
+    outs = []
+    for spg in (0, 4):
+        ws = workspace([sc], "f32")
+        res = []
+        for k in range(2):
+            ws.set_inertia(1e-2, t64(x_n + 1e-3 * k), t64(x_prev))
+            x = dev_x(x_n, "f32")
+            ws.solve(x, max_sweeps=24, rel_tol=0.0, check_every=24, accel="chebyshev", rho=0.9,
+                     gamma=1.3, sweeps_per_graph=spg)
+            res.append(x)
+        outs.append(res)
+    for a, b in zip(*outs):
+        assert torch.equal(a, b)
