@@ -23,7 +23,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pbng_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
-NEOHOOKEAN, COROTATED = 0, 1
+NEOHOOKEAN, COROTATED, STABLE_NEOHOOKEAN = 0, 1, 2
+MODEL = {"nh": NEOHOOKEAN, "corotated": COROTATED, "snh": STABLE_NEOHOOKEAN}
 ACCEL = {"none": 0, "chebyshev": 1, "sor": 2}
 SAFEGUARD = {"none": 0, "backtrack": 1}
 
@@ -76,6 +77,7 @@ def lib():
         L.or_psi.restype = C.c_double
         L.or_pk1.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp]
         L.or_nh_dpk1.argtypes = [C.c_double, C.c_double, _dp, _dp, _dp]
+        L.or_dpk1.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp, _dp]
         L.or_mod_hess_density.argtypes = [C.c_double, C.c_double, _dp, _dp]
         L.or_svd3.argtypes = [_dp, _dp, _dp, _dp]
         L.or_prep.argtypes = [C.c_int32, C.c_int32, _dp, _ip, _dp, _dp]
@@ -155,6 +157,15 @@ def nh_dpk1(mu, lam, F, dF):
     dF = _f64(dF, (3, 3))
     out = np.zeros((3, 3))
     lib().or_nh_dpk1(mu, lam, _d(F), _d(dF), _d(out))
+    return out
+
+
+def dpk1(model, mu, lam, F, dF):
+    """dP[dF] for any model (the true Hessian density applied to dF)."""
+    F = _f64(F, (3, 3))
+    dF = _f64(dF, (3, 3))
+    out = np.zeros((3, 3))
+    lib().or_dpk1(model, mu, lam, _d(F), _d(dF), _d(out))
     return out
 
 
@@ -265,7 +276,7 @@ def make_problem(sc, mu=None, lam=None) -> OracleProblem:
     mass = np.zeros(nv)
     if nt > 0:
         L.or_lumped_mass(nv, nt, _i(T), _d(V0), float(sc.density), _d(mass))
-    return OracleProblem(nv=nv, nt=nt, model=COROTATED if sc.model == "corotated" else NEOHOOKEAN,
+    return OracleProblem(nv=nv, nt=nt, model=MODEL[sc.model],
                          X=X, tets=T, mu=mu, lam=lam, fext=np.ascontiguousarray(fext),
                          is_dir=is_dir,
                          wc_ptr=np.ascontiguousarray(sc.wc_ptr, np.int32),

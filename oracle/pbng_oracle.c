@@ -14,7 +14,7 @@
  * element or constraint).
  *
  * Section references are to the paper:
- *   Sec. "Equations" / "Constitutive Models"   Eq. (cor), (nh), (lame)
+ *   Sec. "Equations" / "Constitutive Models"   Eq. (cor), (nh), (snh), (lame)
  *   Sec. "Discretization"                      Eq. (fem_qs), (pe_hat), (disc_pe)
  *   Sec. "Weak Constraints"                    PE^wc, C_c, K_c
  *   Sec. "Position-Based Nonlinear Gauss-Seidel"  Eq. (pbgn_update), (pbgn_dx)
@@ -34,6 +34,7 @@
 
 #define OR_NEOHOOKEAN 0
 #define OR_COROTATED 1
+#define OR_STABLE_NEOHOOKEAN 2
 
 #define OR_ACCEL_NONE 0
 #define OR_ACCEL_CHEBYSHEV 1
@@ -252,10 +253,19 @@ void or_lame(double E, double nu, double* mu, double* lam)
 
 /* Psi(F).  Corotated, Eq. (cor): mu |F - R(F)|_F^2 + lambda/2 (det F - 1)^2.
  * Neo-Hookean, Eq. (nh): 1/2 mu |F|_F^2 + lhat/2 (det F - 1 - mu/lhat)^2,
- * lhat = mu + lambda. */
+ * lhat = mu + lambda.  Stable Neo-Hookean, Eq. (snh) with the Lame lambda on
+ * its volume term (the printed equation lacks a factor there; with it the
+ * rest state is stress free): 1/2 mu (|F|^2 - 3) + 1/2 lambda (det F - alpha)^2
+ * - 1/2 mu log(1 + |F|^2), alpha = 1 + 3 mu / (4 lambda). */
 double or_psi(int model, double mu, double lam, const double* F)
 {
     double J = det3(F);
+    if (model == OR_STABLE_NEOHOOKEAN) {
+        double f2 = 0.0;
+        for (int k = 0; k < 9; ++k) f2 += F[k] * F[k];
+        double q = J - 1.0 - 0.75 * mu / lam;
+        return 0.5 * mu * (f2 - 3.0) + 0.5 * lam * q * q - 0.5 * mu * log(1.0 + f2);
+    }
     if (model == OR_NEOHOOKEAN) {
         double lh = mu + lam, f2 = 0.0;
         for (int k = 0; k < 9; ++k) f2 += F[k] * F[k];
@@ -277,7 +287,13 @@ void or_pk1(int model, double mu, double lam, const double* F, double* P)
     double C[9];
     double J = det3(F);
     cofactor3(F, C);
-    if (model == OR_NEOHOOKEAN) {
+    if (model == OR_STABLE_NEOHOOKEAN) {
+        /* d/dF [-1/2 mu log(1 + |F|^2)] = -mu F / (1 + |F|^2) */
+        double f2 = 0.0;
+        for (int k = 0; k < 9; ++k) f2 += F[k] * F[k];
+        double q = J - 1.0 - 0.75 * mu / lam;
+        for (int k = 0; k < 9; ++k) P[k] = mu * (1.0 - 1.0 / (1.0 + f2)) * F[k] + lam * q * C[k];
+    } else if (model == OR_NEOHOOKEAN) {
         double lh = mu + lam;
         double q = J - 1.0 - mu / lh;
         for (int k = 0; k < 9; ++k) P[k] = mu * F[k] + lh * q * C[k];
@@ -305,6 +321,70 @@ void or_nh_dpk1(double mu, double lam, const double* F, const double* dF, double
     for (int k = 0; k < 9; ++k) dJ += C[k] * dF[k];
     for (int k = 0; k < 9; ++k)
         dP[k] = mu * dF[k] + lh * dJ * C[k] + lh * q * 0.5 * (Cp[k] - Cm[k]);
+}
+
+/* Stress differential dP[dF] for any model (the true Hessian density of
+ * Eq. (hess) applied to dF).  The cofactor is quadratic in F, so its
+ * derivative along dF is exactly (cof(F + dF) - cof(F - dF)) / 2, and
+ * d det = cof(F) : dF.
+ *   Neo-Hookean:        mu dF + lhat (cof:dF) cof + lhat (J - 1 - mu/lhat) dcof
+ *   stable Neo-Hookean: mu (1 - 1/(1+|F|^2)) dF + 2 mu (F:dF)/(1+|F|^2)^2 F
+ *                       + lambda (cof:dF) cof + lambda (J - alpha) dcof
+ *   corotated:          2 mu (dF - dR) + lambda (cof:dF) cof + lambda (J - 1) dcof,
+ * where, with F = R S (S symmetric), dR = R [w]_x and w solves
+ * ((tr S) I - S) w = axial(R^T dF - dF^T R): the skew part of R^T dF equals
+ * (W S + S W) / 2 for W = [w]_x, and W S + S W = [((tr S) I - S) w]_x. */
+void or_dpk1(int model, double mu, double lam, const double* F, const double* dF, double* dP)
+{
+    double C[9], Cp[9], Cm[9], Fp[9], Fm[9];
+    double J = det3(F);
+    cofactor3(F, C);
+    for (int k = 0; k < 9; ++k) { Fp[k] = F[k] + dF[k]; Fm[k] = F[k] - dF[k]; }
+    cofactor3(Fp, Cp);
+    cofactor3(Fm, Cm);
+    double dJ = 0.0;
+    for (int k = 0; k < 9; ++k) dJ += C[k] * dF[k];
+    if (model == OR_NEOHOOKEAN) {
+        or_nh_dpk1(mu, lam, F, dF, dP);
+    } else if (model == OR_STABLE_NEOHOOKEAN) {
+        double f2 = 0.0, fd = 0.0;
+        for (int k = 0; k < 9; ++k) { f2 += F[k] * F[k]; fd += F[k] * dF[k]; }
+        double q = J - 1.0 - 0.75 * mu / lam;
+        double a = mu * (1.0 - 1.0 / (1.0 + f2)), b = 2.0 * mu * fd / ((1.0 + f2) * (1.0 + f2));
+        for (int k = 0; k < 9; ++k)
+            dP[k] = a * dF[k] + b * F[k] + lam * dJ * C[k] + lam * q * 0.5 * (Cp[k] - Cm[k]);
+    } else {
+        double R[9], S[9], M[9], Mi[9], W[9], w[3], om[3], Om[9], dR[9];
+        rotation_part(F, R);
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) {
+                double s = 0.0, t = 0.0;
+                for (int k = 0; k < 3; ++k) {
+                    s += R[3 * k + i] * F[3 * k + j];    /* S = R^T F */
+                    t += R[3 * k + i] * dF[3 * k + j];   /* R^T dF    */
+                }
+                S[3 * i + j] = s;
+                W[3 * i + j] = t;
+            }
+        /* axial vector of R^T dF - (R^T dF)^T */
+        w[0] = W[3 * 2 + 1] - W[3 * 1 + 2];
+        w[1] = W[3 * 0 + 2] - W[3 * 2 + 0];
+        w[2] = W[3 * 1 + 0] - W[3 * 0 + 1];
+        double tr = S[0] + S[4] + S[8];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) M[3 * i + j] = (i == j ? tr : 0.0) - 0.5 * (S[3 * i + j] + S[3 * j + i]);
+        if (inv3(M, Mi)) {
+            for (int k = 0; k < 9; ++k) dP[k] = NAN;
+            return;
+        }
+        for (int i = 0; i < 3; ++i) om[i] = Mi[3 * i] * w[0] + Mi[3 * i + 1] * w[1] + Mi[3 * i + 2] * w[2];
+        Om[0] = 0.0;    Om[1] = -om[2]; Om[2] = om[1];
+        Om[3] = om[2];  Om[4] = 0.0;    Om[5] = -om[0];
+        Om[6] = -om[1]; Om[7] = om[0];  Om[8] = 0.0;
+        matmul3(R, Om, dR);
+        for (int k = 0; k < 9; ++k)
+            dP[k] = 2.0 * mu * (dF[k] - dR[k]) + lam * dJ * C[k] + lam * (J - 1.0) * 0.5 * (Cp[k] - Cm[k]);
+    }
 }
 
 /* Modified Hessian density, Eq. (mod_hess_dens), as the full fourth-order
@@ -917,7 +997,7 @@ int32_t or_update_vertices(const or_problem* p, const double* y, int32_t n, cons
 }
 
 /* ------------------------------------------------------------------ */
-/* True Hessian (Neo-Hookean only) and adjoint gradient assembly         */
+/* True Hessian and adjoint gradient assembly                           */
 /* ------------------------------------------------------------------ */
 /* out = H v, with H = d^2 E / dy^2 at y, for every vertex (Dirichlet rows
  * included; callers restrict).  Element part: sum_e V0 dP_e[sum_j v_j dN_j^T]
@@ -925,7 +1005,6 @@ int32_t or_update_vertices(const or_problem* p, const double* y, int32_t n, cons
  * sum_j s_cj v_j; active planes: k n n^T v_i; inertia: minert_i v_i. */
 int32_t or_hvp(const or_problem* p, const double* y, const double* v, double* out)
 {
-    if (p->model != OR_NEOHOOKEAN) return -3;
     or_adj A;
     int rc = adj_build(p, &A);
     if (rc) return rc;
@@ -936,7 +1015,7 @@ int32_t or_hvp(const or_problem* p, const double* y, const double* v, double* ou
         double F[9], dF[9], dP[9];
         deformation_gradient(y, t, g, F);
         deformation_gradient(v, t, g, dF);
-        or_nh_dpk1(p->mu[e], p->lam[e], F, dF, dP);
+        or_dpk1(p->model, p->mu[e], p->lam[e], F, dF, dP);
         for (int j = 0; j < 4; ++j)
             for (int r = 0; r < 3; ++r) {
                 double s = 0.0;
@@ -972,14 +1051,15 @@ int32_t or_hvp(const or_problem* p, const double* y, const double* v, double* ou
 /* Given the adjoint vector lam (zero on Dirichlet rows) solving H_FF lam =
  * dL/dx_F, the gradients of L(x*(theta)) follow from dL/dtheta =
  * -lam^T dg/dtheta with g = dE/dy_F:
- *   dL/dmu_e     = -V0 < dP/dmu,  Lam_e >,   dP/dmu  = F + (J - 2) cof F
- *   dL/dlambda_e = -V0 < dP/dlam, Lam_e >,   dP/dlam = (J - 1) cof F
+ *   dL/dmu_e     = -V0 < dP/dmu,  Lam_e >
+ *   dL/dlambda_e = -V0 < dP/dlam, Lam_e >,   dP/dlam = (J - 1) cof F (all models)
  *   dL/dx_k      = -(H lam)_k for Dirichlet vertices k
- * where Lam_e = sum_j lam_j dN_j^T.  Any output may be NULL. */
+ * with dP/dmu = F + (J - 2) cof F (Neo-Hookean), 2 (F - R) (corotated) and
+ * (1 - 1/(1+|F|^2)) F - 3/4 cof F (stable Neo-Hookean), and
+ * Lam_e = sum_j lam_j dN_j^T.  Any output may be NULL. */
 int32_t or_adjoint_gradients(const or_problem* p, const double* y, const double* lam,
                              double* dmu, double* dlam, double* dxd /* [nv][3] */)
 {
-    if (p->model != OR_NEOHOOKEAN) return -3;
     or_adj A;
     int rc = adj_build(p, &A);
     if (rc) return rc;
@@ -991,9 +1071,17 @@ int32_t or_adjoint_gradients(const or_problem* p, const double* y, const double*
         deformation_gradient(lam, t, g, L);
         cofactor3(F, C);
         double J = det3(F);
+        double Pm[9], R[9], f2 = 0.0;
+        for (int k = 0; k < 9; ++k) f2 += F[k] * F[k];
+        if (p->model == OR_COROTATED) rotation_part(F, R);
+        for (int k = 0; k < 9; ++k) {
+            if (p->model == OR_NEOHOOKEAN) Pm[k] = F[k] + (J - 2.0) * C[k];
+            else if (p->model == OR_COROTATED) Pm[k] = 2.0 * (F[k] - R[k]);
+            else Pm[k] = (1.0 - 1.0 / (1.0 + f2)) * F[k] - 0.75 * C[k];
+        }
         double smu = 0.0, slam = 0.0;
         for (int k = 0; k < 9; ++k) {
-            smu += (F[k] + (J - 2.0) * C[k]) * L[k];
+            smu += Pm[k] * L[k];
             slam += (J - 1.0) * C[k] * L[k];
         }
         if (dmu) dmu[e] = -A.V0[e] * smu;

@@ -7,7 +7,7 @@ import pytest
 import oracle as O
 
 RNG = np.random.default_rng(1234)
-MODELS = [O.NEOHOOKEAN, O.COROTATED]
+MODELS = [O.NEOHOOKEAN, O.COROTATED, O.STABLE_NEOHOOKEAN]
 
 
 def rand_rot(rng):
@@ -127,7 +127,7 @@ def test_modified_hessian_density_is_spd():
         assert w.min() >= 2 * mu * (1 - 1e-12)
 
 
-@pytest.mark.parametrize("model", MODELS)
+@pytest.mark.parametrize("model", [O.NEOHOOKEAN, O.COROTATED])
 def test_lame_consistency_at_rest(model):
     """Sec. "Lame Coefficients": at F = I the Hessian of Psi matches linear
     elasticity, Eq. (le), whose second variation for a symmetric dF is
@@ -147,6 +147,58 @@ def test_lame_consistency_at_rest(model):
         Ct = O.mod_hess_density(mu, lam, np.eye(3))
         qt = float(np.einsum("agbd,ag,bd->", Ct, dF, dF))
         assert abs(qt - le) <= 1e-10 * le
+
+
+def test_stable_neohookean_at_rest():
+    """Eq. (snh) with lambda on the volume term: Psi(I) = 9 mu^2 / (32 lambda)
+    - mu log 2 (|I|^2 = 3, det I - alpha = -3 mu / (4 lambda)), and its
+    second variation on a symmetric dF, worked out by hand from the Taylor
+    series of |F|^2, det F and log(1 + |F|^2) about I, is
+    (3/2) mu |dF|^2 + (lambda - 5 mu / 8) tr(dF)^2 (the printed model is not
+    Lame-consistent without a rescaling of mu and lambda, which the paper
+    does not give)."""
+    mu, lam = O.lame(1e5, 0.45)
+    assert abs(O.psi(O.STABLE_NEOHOOKEAN, mu, lam, np.eye(3))
+               - (9 * mu * mu / (32 * lam) - mu * np.log(2.0))) <= 1e-9 * mu
+    h = 1e-5
+    for _ in range(10):
+        A = RNG.normal(size=(3, 3))
+        dF = 0.5 * (A + A.T)
+        dP = (O.pk1(O.STABLE_NEOHOOKEAN, mu, lam, np.eye(3) + h * dF)
+              - O.pk1(O.STABLE_NEOHOOKEAN, mu, lam, np.eye(3) - h * dF)) / (2 * h)
+        q = float((dP * dF).sum())
+        ref = 1.5 * mu * float((dF * dF).sum()) + (lam - 0.625 * mu) * np.trace(dF) ** 2
+        assert abs(q - ref) <= 1e-6 * abs(ref)
+
+
+@pytest.mark.parametrize("model", MODELS)
+def test_stress_differential_all_models(model):
+    """dP[dF] (the true Hessian density) against central differences of P,
+    including inverted F for the Neo-Hookean models; for the corotated model
+    F is kept away from the inversion where dR is singular."""
+    mu, lam = O.lame(1e5, 0.45)
+    h = 1e-6
+    for inverted in (False, True):
+        if inverted and model == O.COROTATED:
+            continue
+        for _ in range(10):
+            F = rand_F(RNG, inverted)
+            dF = RNG.normal(size=(3, 3))
+            dP = O.dpk1(model, mu, lam, F, dF)
+            fd = (O.pk1(model, mu, lam, F + h * dF) - O.pk1(model, mu, lam, F - h * dF)) / (2 * h)
+            assert np.abs(fd - dP).max() <= 1e-7 * max(1.0, np.abs(dP).max())
+
+
+def test_corotated_stress_differential_is_symmetric():
+    """The Hessian density of a hyperelastic energy is symmetric:
+    dF2 : dP[dF1] = dF1 : dP[dF2]."""
+    mu, lam = O.lame(1e4, 0.3)
+    for _ in range(10):
+        F = rand_F(RNG)
+        A, B = RNG.normal(size=(3, 3)), RNG.normal(size=(3, 3))
+        a = float((B * O.dpk1(O.COROTATED, mu, lam, F, A)).sum())
+        b = float((A * O.dpk1(O.COROTATED, mu, lam, F, B)).sum())
+        assert abs(a - b) <= 1e-10 * max(abs(a), 1.0)
 
 
 def test_signed_svd_against_library():

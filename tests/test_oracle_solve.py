@@ -151,8 +151,9 @@ def test_body_force_lumping():
     assert abs(op.V0.sum() - vol) < 1e-12
 
 
-def test_hessian_vector_product_matches_gradient_differences():
-    sc = with_extras(small_twist(4, "nh"))
+@pytest.mark.parametrize("model", ["nh", "corotated", "snh"])
+def test_hessian_vector_product_matches_gradient_differences(model):
+    sc = with_extras(small_twist(4, model))
     op = O.make_problem(sc)
     x = sc.initial_iterate()
     v = RNG.normal(size=x.shape)
@@ -244,7 +245,7 @@ def test_single_free_vertex_matches_minimizer(model):
     assert np.abs(x[centre] - res.x).max() < 1e-8
 
 
-@pytest.mark.parametrize("model", ["nh", "corotated"])
+@pytest.mark.parametrize("model", ["nh", "corotated", "snh"])
 def test_equilibrium_matches_dense_newton(model):
     sc = small_twist(4, model, twist=25.0, stretch=1.1, noise=0.0)
     sc.density, sc.gravity = 100.0, (0.0, -9.8, 0.0)
@@ -331,9 +332,9 @@ def test_openmp_within_colour_is_bit_identical():
 # ---------------------------------------------------------------------------
 # adjoint
 # ---------------------------------------------------------------------------
-def _adjoint_case(seed=11):
+def _adjoint_case(seed=11, model="nh"):
     rng = np.random.default_rng(seed)
-    sc = S.random_cube(rng, 4, "nh", 1e4, 0.3, 15.0, 0.9, 1.1, "adj")
+    sc = S.random_cube(rng, 4, model, 1e4, 0.3, 15.0, 0.9, 1.1, "adj")
     op = O.make_problem(sc)
     op.mu = op.mu * np.exp(0.2 * rng.normal(size=op.nt))
     op.lam = op.lam * np.exp(0.2 * rng.normal(size=op.nt))
@@ -350,11 +351,12 @@ def _loss_at(op, sc, target, mu, lam, xd):
     return float(((x - target)[free] ** 2).sum()), x
 
 
-def test_adjoint_gradients_match_central_differences():
+@pytest.mark.parametrize("model", ["nh", "corotated", "snh"])
+def test_adjoint_gradients_match_central_differences(model):
     """dL/dtheta from H lam = dL/dx (dense solve) and the gradient-assembly
     formulas, against FP64 central differences of L(x*(theta)) with Newton
     re-solves, on random directions in (x_D, log mu, log lambda)."""
-    sc, op, target = _adjoint_case()
+    sc, op, target = _adjoint_case(model=model)
     free = op.is_dir == 0
     L0, x = _loss_at(op, sc, target, op.mu, op.lam, op.dirichlet_x)
     dLdx = np.where(free[:, None], 2.0 * (x - target), 0.0)
@@ -378,11 +380,12 @@ def test_adjoint_gradients_match_central_differences():
         assert abs(fd - an) <= 1e-6 * max(abs(fd), 1e-3 * abs(L0)), (fd, an)
 
 
-def test_adjoint_parameter_gradients_by_linearity():
+@pytest.mark.parametrize("model", ["nh", "corotated", "snh"])
+def test_adjoint_parameter_gradients_by_linearity(model):
     """The energy gradient g is linear in (mu, lambda); so dg/dmu_e is exact
     by a difference quotient and dL/dmu_e = -lam^T dg/dmu_e (brute force over
     every tet of a tiny mesh)."""
-    sc, op, target = _adjoint_case(seed=5)
+    sc, op, target = _adjoint_case(seed=5, model=model)
     x, _, _ = D.newton(op, sc.initial_iterate(), tol=1e-13)
     lam_vec = RNG.normal(size=x.shape) * (op.is_dir == 0)[:, None]
     dmu, dla, _ = O.adjoint_gradients(op, x, lam_vec)
