@@ -173,16 +173,20 @@ def main():
         progress("cpu baseline: %.3e vertex updates/s" % cpu["value"])
     extras = {}
     if not args.no_extras:
-        extras["batched"] = batched_report(pbng, S, torch, stream, args.batched_subset)
-        progress("batched report done")
-        extras["differentiable"] = differentiable_report(pbng, S, torch, stream, args.diff_instances)
-        progress("differentiable report done")
-        extras["muscles"] = muscles_report(pbng, S, torch, stream)
-        progress("muscles report done")
-        extras["paper_blocks"] = paper_boxes_report(pbng, S, torch, stream)
-        progress("paper stretching blocks done")
-        extras["backward_euler"] = dynamics_report(pbng, S, torch, stream)
-        progress("backward Euler report done")
+        reports = [("batched", lambda: batched_report(pbng, S, torch, stream, args.batched_subset)),
+                   ("differentiable",
+                    lambda: differentiable_report(pbng, S, torch, stream, args.diff_instances)),
+                   ("muscles", lambda: muscles_report(pbng, S, torch, stream)),
+                   ("paper_blocks", lambda: paper_boxes_report(pbng, S, torch, stream)),
+                   ("backward_euler", lambda: dynamics_report(pbng, S, torch, stream))]
+        for name, fn in reports:
+            # a failing sub-report is recorded, not fatal to the headline line
+            try:
+                extras[name] = fn()
+            except Exception as e:  # noqa: BLE001
+                extras[name] = {"error": "%s: %s" % (type(e).__name__, e)}
+            torch.cuda.synchronize()
+            progress("%s report done" % name)
 
     sweeps = max(s["sweeps"] for s in last)
     line = {
@@ -368,16 +372,19 @@ def muscles_report(pbng, S, torch, stream):
 
 def paper_boxes_report(pbng, S, torch, stream):
     """The paper's quasistatic stretching blocks (Table 3 rows with 1
-    substep): 32^3 corotated and Neo-Hookean at 40 iterations per frame, 64^3
+    substep): 32^3 corotated, Neo-Hookean and stable Neo-Hookean at 40
+    iterations per frame, 64^3
     at 20, 128^3 at 40.  A frame sets that frame's Dirichlet targets and runs
     the iterations from the previous frame's positions (Chebyshev rho = 0.95,
     relaxation 1.7, FP32), with one FP64 residual at the end.  The paper's
     per-frame times were measured on a 64-core CPU; they are context."""
-    rows = [(32, "corotated", 40, 1300.0), (32, "nh", 40, 825.0), (64, "corotated", 20, 1300.0),
-            (128, "corotated", 40, 61000.0)]
+    rows = [(32, "corotated", 40, 1300.0), (32, "nh", 40, 825.0), (32, "snh", 40, 1300.0),
+            (64, "corotated", 20, 1300.0), (128, "corotated", 40, 61000.0)]
     out = []
     for n, model, iters, paper_ms in rows:
-        sc, frames = S.paper_box_frames(n, model, n_frames=4)
+        # the motion spans 60 frames; frame 1 warms up, frames 2-4 are timed
+        sc, frames = S.paper_box_frames(n, model, n_frames=60)
+        frames = frames[:4]
         ws = pbng.Workspace([pbng.problem_from_scenario(sc)], real="f32")
         so = pbng.solve_opts(max_sweeps=iters, rel_tol=0.0, check_every=iters, accel="chebyshev",
                              rho=0.95, gamma=1.7, safeguard="backtrack")

@@ -54,11 +54,16 @@ extern "C" {
 #define PBNG_ENAN (-5)            /* non-finite input or iterate           */
 #define PBNG_EHIP (-6)            /* HIP runtime failure                   */
 #define PBNG_ENOMEM (-7)          /* allocation failure                    */
-#define PBNG_EUNSUPPORTED (-8)    /* e.g. adjoint of the corotated model   */
+#define PBNG_EUNSUPPORTED (-8)    /* e.g. a workspace too large for 32-bit offsets */
 
 /* ---- enumerations ---------------------------------------------------- */
 #define PBNG_NEOHOOKEAN 0   /* Eq. nh: 1/2 mu |F|^2 + lhat/2 (J - 1 - mu/lhat)^2, lhat = mu + lambda */
 #define PBNG_COROTATED 1    /* Eq. cor: mu |F - R(F)|^2 + lambda/2 (J - 1)^2 */
+/* Eq. snh with the Lame lambda on its volume term (the printed equation
+ * lacks it; with it the rest state is stress free):
+ * 1/2 mu (|F|^2 - 3) + 1/2 lambda (J - 1 - 3 mu / (4 lambda))^2 - 1/2 mu log(1 + |F|^2).
+ * Needs lambda > 0. */
+#define PBNG_STABLE_NEOHOOKEAN 2
 
 #define PBNG_F32 0    /* positions and sweep arithmetic in float             */
 #define PBNG_F64 1    /* positions and sweep arithmetic in double            */
@@ -83,7 +88,8 @@ extern "C" {
  *  rest_pos  [n_verts][3]  rest positions X_i (double)
  *  tets      [n_tets][4]   vertex indices; every tet must have positive rest
  *                          volume det[X1-X0, X2-X0, X3-X0] / 6 > 0
- *  model                PBNG_NEOHOOKEAN or PBNG_COROTATED
+ *  model                PBNG_NEOHOOKEAN, PBNG_COROTATED or PBNG_STABLE_NEOHOOKEAN
+ *                       (one model per workspace)
  *  mu, lambda           uniform Lame parameters (Eq. lame), used when
  *                       mu_tet / lambda_tet are NULL
  *  mu_tet, lambda_tet   optional [n_tets] per-tet Lame parameters
@@ -295,19 +301,26 @@ int32_t pbng_residual(pbng_workspace* ws, const void* x, double* res_norm, doubl
                       double* r_out, void* hip_stream);
 
 /*
- * Adjoint of the equilibrium (Neo-Hookean only).  At an equilibrium x_eq
+ * Adjoint of the equilibrium.  At an equilibrium x_eq
  * (device, workspace real type), solve H lam = dL/dx restricted to free
  * vertices, H the true energy Hessian (Eq. hess with the exact density), by
- * block Gauss-Seidel over the same colouring, then assemble
- *   dL/dmu_e     = -V0_e < F_e + (J_e - 2) cof F_e , Lam_e >
+ * block Gauss-Seidel over the same colouring (diagonal blocks: the true
+ * H_ii for Neo-Hookean, the modified A_ii >= H_ii for the corotated and
+ * stable Neo-Hookean models, whose H_ii need not be positive away from a
+ * stable equilibrium; the corotated rotation derivative is singular where
+ * two signed singular values sum to zero, so inverted elements are not
+ * supported there), then assemble
+ *   dL/dmu_e     = -V0_e < dP/dmu (F_e) , Lam_e >
  *   dL/dlambda_e = -V0_e < (J_e - 1) cof F_e , Lam_e >
+ * with dP/dmu = F + (J - 2) cof F (Neo-Hookean), 2 (F - R) (corotated),
+ * (1 - 1/(1 + |F|^2)) F - 3/4 cof F (stable Neo-Hookean), and
  *   dL/dx_k      = (dL/dx)_k - (H lam)_k  for Dirichlet vertices k
  * (the first term because x*_k = x_D,k), Lam_e = sum_j lam_j dN_j^T.
  * dL_dx: device [sum n_verts][3] (workspace real type).  Outputs (device, double, any may be
  * NULL): dL_dxD [sum n_dirichlet][3] in creation order, dL_dmu and
  * dL_dlambda [sum n_tets], lam_out [sum n_verts][3] (zero on Dirichlet
  * rows).  stats [n_instances] (host, may be NULL): sweeps, residuals of
- * the adjoint system.  Errors: PBNG_EUNSUPPORTED for the corotated model.
+ * the adjoint system.
  */
 int32_t pbng_adjoint(pbng_workspace* ws, const void* x_eq, const void* dL_dx, double* dL_dxD,
                      double* dL_dmu, double* dL_dlambda, double* lam_out,

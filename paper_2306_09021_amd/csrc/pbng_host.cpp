@@ -141,7 +141,7 @@ void validate_problem(const pbng_problem* p, int q)
     if (p->n_verts <= 0 || p->n_tets < 0) fail(PBNG_EINVAL, "problem %d: bad sizes", q);
     if (!p->rest_pos) fail(PBNG_EINVAL, "problem %d: rest_pos is null", q);
     if (p->n_tets > 0 && !p->tets) fail(PBNG_EINVAL, "problem %d: tets is null", q);
-    if (p->model != PBNG_NEOHOOKEAN && p->model != PBNG_COROTATED)
+    if (p->model != PBNG_NEOHOOKEAN && p->model != PBNG_COROTATED && p->model != PBNG_STABLE_NEOHOOKEAN)
         fail(PBNG_EINVAL, "problem %d: unknown model %d", q, p->model);
     if (!finite_arr(p->rest_pos, 3ll * p->n_verts)) fail(PBNG_ENAN, "problem %d: non-finite rest_pos", q);
     for (int64_t e = 0; e < p->n_tets; ++e) {
@@ -451,7 +451,7 @@ VisitBuild<R> visit_build(pbng_workspace* ws)
     b.rv = ws->rv.as<int>();
     b.vptr = ws->vptr.as<int>();
     b.n_free = int(ws->nfree);
-    b.model = ws->model == PBNG_NEOHOOKEAN ? 0 : 1;
+    b.model = ws->model;
     b.jv = ws->jv.as<int4>();
     b.ma = ws->ma.as<typename R4t<R>::T>();
     b.mb = ws->mb.as<typename R4t<R>::T>();
@@ -547,7 +547,10 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     {
         bool lam_ge_mu = true;
         for (int64_t e = 0; e < nt; ++e) lam_ge_mu = lam_ge_mu && lam[e] >= mu[e];
-        ws->safeguard_inactive = ws->n_planes == 0 && (ws->model == PBNG_COROTATED || lam_ge_mu);
+        // (the stable Neo-Hookean step has no such guarantee: its volume term
+        // has a curvature along x_i that the modified Hessian does not bound)
+        ws->safeguard_inactive = ws->n_planes == 0 &&
+                                 (ws->model == PBNG_COROTATED || (ws->model == PBNG_NEOHOOKEAN && lam_ge_mu));
     }
 
     // internal order
@@ -759,7 +762,7 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
         const size_t r = ws->math64() ? sizeof(double) : sizeof(float);
         ws->ma.alloc(size_t(ws->nvis) * 4 * r);
         ws->mb.alloc(size_t(ws->nvis) * 4 * r);
-        ws->mc.alloc(ws->model == PBNG_COROTATED ? size_t(ws->nvis) * 2 * r : 0);
+        ws->mc.alloc(ws->model != PBNG_NEOHOOKEAN ? size_t(ws->nvis) * 2 * r : 0);
         ws->vmu.alloc(ws->math64() ? size_t(ws->nvis) * r : 0);
         ws->Sv.alloc(size_t(nfree) * r);
     }
@@ -1218,7 +1221,7 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
         omega_prev = omega;
         const AdjArgs<R, PR> a = adj_args<R, PR>(ws, omega, accel ? o->gamma : 1.0);
         for (int c = 0; c < ws->ncol; ++c)
-            hipchk(launch_adjoint_phase<R, PR>(a, pick_lanes(ws, o->lanes, c), accel, ws->any_wc || ws->inertia, ws->col_ptr[c],
+            hipchk(launch_adjoint_phase<R, PR>(a, ws->model, pick_lanes(ws, o->lanes, c), accel, ws->any_wc || ws->inertia, ws->col_ptr[c],
                                            ws->col_ptr[c + 1], s),
                    "adjoint launch");
         if (accel) std::swap(ws->L.p, ws->LN.p);
@@ -1630,7 +1633,6 @@ int32_t pbng_adjoint(pbng_workspace* ws, const void* x_eq, const void* dL_dx, do
     return guard([&] {
         check_ws(ws);
         if (!x_eq || !dL_dx || !o) fail(PBNG_EINVAL, "null argument");
-        if (ws->model != PBNG_NEOHOOKEAN) fail(PBNG_EUNSUPPORTED, "the adjoint supports the Neo-Hookean model only");
         if (o->max_sweeps < 0 || o->check_every < 1) fail(PBNG_EINVAL, "bad adjoint sweep counts");
         if (o->accel != PBNG_ACCEL_NONE && o->accel != PBNG_ACCEL_CHEBYSHEV)
             fail(PBNG_EINVAL, "adjoint acceleration must be none or Chebyshev");

@@ -238,7 +238,7 @@ struct AdjArgs {
     PR omega, gamma;
 };
 template <class R, class PR>
-hipError_t launch_adjoint_phase(const AdjArgs<R, PR>& a, int lanes, bool accel, bool wc, int vbeg,
-                                int vend, hipStream_t s);
+hipError_t launch_adjoint_phase(const AdjArgs<R, PR>& a, int model, int lanes, bool accel, bool wc,
+                                int vbeg, int vend, hipStream_t s);
 
 }  // namespace pbng

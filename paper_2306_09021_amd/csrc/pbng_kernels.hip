@@ -22,6 +22,7 @@ namespace pbng {
 
 constexpr int kNeo = 0;
 constexpr int kCor = 1;
+constexpr int kSnh = 2;
 constexpr int kBlock = 256;
 
 // Element i of an array through a 32-bit byte offset, so that the load takes
@@ -177,6 +178,76 @@ __device__ __forceinline__ R corot_energy(const Cols<R>& F, const Cols<R>& Rm, R
     return vm * (dot(d0, d0) + dot(d1, d1) + dot(d2, d2)) + R(0.5) * vl * (J - R(1)) * (J - R(1));
 }
 
+// Stable Neo-Hookean energy density times V0 (Eq. snh with the Lame lambda
+// on the volume term): with vm = V0 mu, vl = V0 lambda,
+// 1/2 vm (|F|^2 - 3) + 1/2 vl (J - alpha)^2 - 1/2 vm log(1 + |F|^2),
+// alpha = 1 + 3 mu / (4 lambda), i.e. vl (J - alpha) = vl (J - 1) - 3/4 vm.
+template <class R>
+__device__ __forceinline__ R snh_energy(const Cols<R>& F, R J, R vm, R vl)
+{
+    const R ic = frob2(F);
+    const R q = vl * (J - R(1)) - R(0.75) * vm;
+    return R(0.5) * vm * (ic - R(3)) + R(0.5) * q * q / vl - R(0.5) * vm * log(R(1) + ic);
+}
+
+// Stress differential dP[L] (the true Hessian density of Eq. hess applied
+// to L) for the corotated and stable Neo-Hookean models, with (m, l) =
+// (mu, lambda) or (V0 mu, V0 lambda), C = cof F, J = det F:
+//   dcof[L] columns: L_1 x F_2 + F_1 x L_2, L_2 x F_0 + F_2 x L_0, L_0 x F_1 + F_0 x L_1
+//   stable NH: m (1 - 1/(1+|F|^2)) L + 2 m (F:L)/(1+|F|^2)^2 F + l (C:L) C
+//              + (l (J - 1) - 3/4 m) dcof[L]
+//   corotated: 2 m (L - dR) + l (C:L) C + l (J - 1) dcof[L], with F = R S,
+//              dR = R [w]x and ((tr S) I - S) w = axial(R^T L - L^T R).
+template <class R, int MODEL>
+__device__ __forceinline__ Cols<R> stress_diff(const Cols<R>& F, const Cols<R>& C, R J,
+                                               const Cols<R>& L, R m, R l)
+{
+    const R cofL = dot(C.c0, L.c0) + dot(C.c1, L.c1) + dot(C.c2, L.c2);
+    const V3<R> d0 = cross(L.c1, F.c2) + cross(F.c1, L.c2);
+    const V3<R> d1 = cross(L.c2, F.c0) + cross(F.c2, L.c0);
+    const V3<R> d2 = cross(L.c0, F.c1) + cross(F.c0, L.c1);
+    const R lc = l * cofL;
+    Cols<R> out;
+    if constexpr (MODEL == kSnh) {
+        const R den = R(1) + frob2(F);
+        const R a = m * (R(1) - rcp(den));
+        const R b = R(2) * m * (dot(F.c0, L.c0) + dot(F.c1, L.c1) + dot(F.c2, L.c2)) * rcp(den * den);
+        const R q = l * (J - R(1)) - R(0.75) * m;
+        out.c0 = a * L.c0 + b * F.c0 + lc * C.c0 + q * d0;
+        out.c1 = a * L.c1 + b * F.c1 + lc * C.c1 + q * d1;
+        out.c2 = a * L.c2 + b * F.c2 + lc * C.c2 + q * d2;
+    } else {
+        const Cols<R> Rm = rotation_of(F);
+        // S = R^T F and R^T L (entry (i, j) = R_i . X_j for columns R_i, X_j)
+        const R s00 = dot(Rm.c0, F.c0), s11 = dot(Rm.c1, F.c1), s22 = dot(Rm.c2, F.c2);
+        const R s01 = R(0.5) * (dot(Rm.c0, F.c1) + dot(Rm.c1, F.c0));
+        const R s02 = R(0.5) * (dot(Rm.c0, F.c2) + dot(Rm.c2, F.c0));
+        const R s12 = R(0.5) * (dot(Rm.c1, F.c2) + dot(Rm.c2, F.c1));
+        const V3<R> w = mk(dot(Rm.c2, L.c1) - dot(Rm.c1, L.c2), dot(Rm.c0, L.c2) - dot(Rm.c2, L.c0),
+                           dot(Rm.c1, L.c0) - dot(Rm.c0, L.c1));
+        const R tr = s00 + s11 + s22;
+        // M = (tr S) I - S (symmetric): w_rot = cof(M) w / det M
+        const R m00 = tr - s00, m11 = tr - s11, m22 = tr - s22;
+        const R k00 = m11 * m22 - s12 * s12, k11 = m00 * m22 - s02 * s02, k22 = m00 * m11 - s01 * s01;
+        const R k01 = s01 * m22 + s12 * s02;   // cofactors of M = [[m00,-s01,-s02],...]
+        const R k02 = s01 * s12 + s02 * m11;
+        const R k12 = m00 * s12 + s01 * s02;
+        const R det = m00 * k00 - s01 * k01 - s02 * k02;
+        const R id = rcp(det);
+        const V3<R> om = id * mk(k00 * w.x + k01 * w.y + k02 * w.z, k01 * w.x + k11 * w.y + k12 * w.z,
+                                 k02 * w.x + k12 * w.y + k22 * w.z);
+        // dR = R [om]x: column j of [om]x is om x e_j
+        const V3<R> dr0 = om.z * Rm.c1 - om.y * Rm.c2;   // R (0, om_z, -om_y)
+        const V3<R> dr1 = om.x * Rm.c2 - om.z * Rm.c0;   // R (-om_z, 0, om_x)
+        const V3<R> dr2 = om.y * Rm.c0 - om.x * Rm.c1;   // R (om_y, -om_x, 0)
+        const R q = l * (J - R(1));
+        out.c0 = (R(2) * m) * (L.c0 - dr0) + lc * C.c0 + q * d0;
+        out.c1 = (R(2) * m) * (L.c1 - dr1) + lc * C.c1 + q * d1;
+        out.c2 = (R(2) * m) * (L.c2 - dr2) + lc * C.c2 + q * d2;
+    }
+    return out;
+}
+
 // Raw record of one visit (loaded before any arithmetic so that the loads of
 // several visits are in flight together).
 //
@@ -269,9 +340,9 @@ struct Acc {
     V3<R> g;     // elastic + weak-constraint gradient
     Sym<R> Aw;   // sum V0 lambda c c^T + sum s^2 K
     Sym<R> Cm;   // Neo-Hookean safeguard: sum V0 mu c c^T
-    V3<R> gw;    // corotated safeguard: weak-constraint part of g
-    Sym<R> Kw;   // corotated safeguard: sum s^2 K
-    R E0, E0a;   // corotated safeguard: elastic energy and sum of |terms|
+    V3<R> gw;    // corotated / stable NH safeguard: quadratic (weak, inertia) part of g
+    Sym<R> Kw;   // corotated / stable NH safeguard: its Hessian
+    R E0, E0a;   // corotated / stable NH safeguard: elastic energy and sum of |terms|
 };
 
 // Neo-Hookean visit: V0 P dN_i with P = mu F + (lhat (J - 1) - mu) cof F,
@@ -311,6 +382,36 @@ __device__ __forceinline__ void visit_cor(Acc<R>& q, const VisitRaw<R>& r, V3<R>
     }
 }
 
+// Stable Neo-Hookean visit: V0 P dN_i with
+// P = mu (1 - 1/(1 + |F|^2)) F + (lambda (J - 1) - 3/4 mu) cof F.
+template <class R, bool SAFE>
+__device__ __forceinline__ void visit_snh(Acc<R>& q, const VisitRaw<R>& r, V3<R> e1, V3<R> e2, V3<R> e3)
+{
+    const Cols<R> F = edge_F(e1, e2, e3, r.m);
+    const V3<R> av = mk(-(r.m[0] + r.m[3] + r.m[6]), -(r.m[1] + r.m[4] + r.m[7]),
+                        -(r.m[2] + r.m[5] + r.m[8]));
+    const Cols<R> C = cofactor(F);
+    const R J = dot(F.c0, C.c0);
+    const V3<R> c = apply(C, av);
+    const V3<R> p = apply(F, av);
+    const R vm = r.vm, vl = r.vl;
+    sym_add_outer(q.Aw, vl, c);
+    const R a = vm * (R(1) - rcp(R(1) + frob2(F)));
+    q.g = q.g + a * p + (vl * (J - R(1)) - R(0.75) * vm) * c;
+    if (SAFE) {
+        const R e = snh_energy(F, J, vm, vl);
+        q.E0 += e;
+        q.E0a += abs_(e);
+    }
+}
+
+template <class R, int MODEL, bool SAFE>
+__device__ __forceinline__ void visit_full(Acc<R>& q, const VisitRaw<R>& r, V3<R> e1, V3<R> e2, V3<R> e3)
+{
+    if constexpr (MODEL == kSnh) visit_snh<R, SAFE>(q, r, e1, e2, e3);
+    else visit_cor<R, SAFE>(q, r, e1, e2, e3);
+}
+
 // Visits of one lane: two per pass while any lane of the wave still has two,
 // else one; the branch conditions are uniform over the wave, and lanes with
 // fewer visits sit a visit out under the execution mask.  A lane without a
@@ -344,13 +445,14 @@ __device__ __forceinline__ void lane_visits(const A& a, Acc<R>& q, int kb, int k
                     const VisitRaw<R> r1 = load_raw<R>(a, k1);
                     const auto p01 = at(a.W, r0.i1), p02 = at(a.W, r0.i2), p03 = at(a.W, r0.i3);
                     const auto p11 = at(a.W, r1.i1), p12 = at(a.W, r1.i2), p13 = at(a.W, r1.i3);
-                    visit_cor<R, SAFE>(q, r0, rel<R>(p01, xi), rel<R>(p02, xi), rel<R>(p03, xi));
-                    if (h1) visit_cor<R, SAFE>(q, r1, rel<R>(p11, xi), rel<R>(p12, xi), rel<R>(p13, xi));
+                    visit_full<R, MODEL, SAFE>(q, r0, rel<R>(p01, xi), rel<R>(p02, xi), rel<R>(p03, xi));
+                    if (h1)
+                        visit_full<R, MODEL, SAFE>(q, r1, rel<R>(p11, xi), rel<R>(p12, xi), rel<R>(p13, xi));
                 }
             } else if (h0) {
                 const VisitRaw<R> r0 = load_raw<R>(a, k);
-                visit_cor<R, SAFE>(q, r0, rel<R>(at(a.W, r0.i1), xi), rel<R>(at(a.W, r0.i2), xi),
-                                   rel<R>(at(a.W, r0.i3), xi));
+                visit_full<R, MODEL, SAFE>(q, r0, rel<R>(at(a.W, r0.i1), xi), rel<R>(at(a.W, r0.i2), xi),
+                                           rel<R>(at(a.W, r0.i3), xi));
             }
         }
     }
@@ -411,7 +513,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
             const V3<R> gk = s * symK_mul(K, Cc);
             g = g + gk;
             sym_add_scaled(Aw, s * s, K);
-            if (SAFE && MODEL == kCor) {
+            if (SAFE && MODEL != kNeo) {
                 gw = gw + gk;
                 sym_add_scaled(Kw, s * s, K);
             }
@@ -421,7 +523,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
         lsum3<LANES>(g);
         lsum6<LANES>(Aw);
         if (SAFE && MODEL == kNeo) lsum6<LANES>(Cm);
-        if (SAFE && MODEL == kCor) {
+        if (SAFE && MODEL != kNeo) {
             E0 = lsum<LANES>(E0);
             E0a = lsum<LANES>(E0a);
             if (WC) {
@@ -439,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
         Aw.xx += c;
         Aw.yy += c;
         Aw.zz += c;
-        if (SAFE && MODEL == kCor) {
+        if (SAFE && MODEL != kNeo) {
             gw = gw + c * dx;
             Kw.xx += c;
             Kw.yy += c;
@@ -538,7 +640,8 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
                     ab += e0 + e1;
                 }
             }
-            if constexpr (MODEL == kCor) {
+            if constexpr (MODEL != kNeo) {
+                // exact elastic energy of the incident tets at the trial point
                 R E1 = R(0), E1a = R(0);
                 for (int k = kb + lane; k < ke; k += LANES) {
                     Cols<R> F;
@@ -550,7 +653,9 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
                     F.c1 = F.c1 + av.y * ad;
                     F.c2 = F.c2 + av.z * ad;
                     const R J1 = dot(F.c0, cross(F.c1, F.c2));
-                    const R e = corot_energy(F, rotation_of(F), J1, vm, vl);
+                    R e;
+                    if constexpr (MODEL == kCor) e = corot_energy(F, rotation_of(F), J1, vm, vl);
+                    else e = snh_energy(F, J1, vm, vl);
                     E1 += e;
                     E1a += abs_(e);
                 }
@@ -634,6 +739,7 @@ hipError_t launch_phase(const SweepArgs<R, PR>& a, int model, int lanes, bool ac
                         bool wc, int vbeg, int vend, hipStream_t s)
 {
     if (model == kNeo) return dispatch_lanes<R, PR, kNeo>(a, lanes, accel, safe, wc, vbeg, vend, s);
+    if (model == kSnh) return dispatch_lanes<R, PR, kSnh>(a, lanes, accel, safe, wc, vbeg, vend, s);
     return dispatch_lanes<R, PR, kCor>(a, lanes, accel, safe, wc, vbeg, vend, s);
 }
 
@@ -647,8 +753,13 @@ hipError_t launch_phase(const SweepArgs<R, PR>& a, int model, int lanes, bool ac
 // The diagonal block is H_ii = sum_e V0 (mu |dN_i|^2 I + lhat c c^T) + weak
 // + planes, c = cof F dN_i (along x_i alone the Neo-Hookean energy is
 // exactly quadratic).  Each update: lam_i += H_ii^{-1} (b_i - (H lam)_i).
+// The corotated and stable Neo-Hookean models take dP[L] from stress_diff
+// and use the modified block A_ii = sum V0 (2 mu |dN_i|^2 I + lambda c c^T)
+// in place of H_ii: A_ii bounds H_ii from above (for the corotated model A
+// is the Hessian of a majoriser), so 2 A_ii - H_ii is positive definite and
+// the block Gauss-Seidel iteration converges wherever H is.
 // ---------------------------------------------------------------------------
-template <class R, class PR, int LANES, bool ACCEL, bool WC>
+template <class R, class PR, int MODEL, int LANES, bool ACCEL, bool WC>
 __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg, int vend)
 {
     using P4 = typename R4t<PR>::T;
@@ -666,7 +777,22 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg
     // lambda, X_k = cof D columns): Lam dN_i = sum alpha_a l_a,
     // cof F : Lam = delta sum_k X_k . l_k and dcof[Lam] dN_i =
     // sum_k beta_k (derivative of X_k along l).
-    for (int k = kb + lane; k < ke; k += LANES) {
+    if constexpr (MODEL != kNeo) {
+        for (int k = kb + lane; k < ke; k += LANES) {
+            const VisitRaw<R> q = load_raw<R>(a, k);
+            const Cols<R> F = edge_F(rel<R>(at(a.X, q.i1), xi), rel<R>(at(a.X, q.i2), xi),
+                                     rel<R>(at(a.X, q.i3), xi), q.m);
+            const Cols<R> Lm = edge_F(rel<R>(at(a.L, q.i1), li), rel<R>(at(a.L, q.i2), li),
+                                      rel<R>(at(a.L, q.i3), li), q.m);
+            const V3<R> av = mk(-(q.m[0] + q.m[3] + q.m[6]), -(q.m[1] + q.m[4] + q.m[7]),
+                                -(q.m[2] + q.m[5] + q.m[8]));
+            const Cols<R> C = cofactor(F);
+            const R J = dot(F.c0, C.c0);
+            r = r + apply(stress_diff<R, MODEL>(F, C, J, Lm, q.vm, q.vl), av);
+            sym_add_outer(Hc, q.vl, apply(C, av));
+        }
+    }
+    for (int k = kb + lane; MODEL == kNeo && k < ke; k += LANES) {
         const VisitNH<R> q = load_nh<R>(a, k);
         const V3<R> e1 = rel<R>(at(a.X, q.i1), xi), e2 = rel<R>(at(a.X, q.i2), xi),
                     e3 = rel<R>(at(a.X, q.i3), xi);
@@ -712,9 +838,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg
         Hc.yy += c;
         Hc.zz += c;
     }
-    Hc.xx += S;
-    Hc.yy += S;
-    Hc.zz += S;
+    const R Sd = MODEL == kNeo ? S : R(2) * S;
+    Hc.xx += Sd;
+    Hc.yy += Sd;
+    Hc.zz += Sd;
     if (WC) {
         for (int q = a.plane_ptr[inst]; q < a.plane_ptr[inst + 1]; ++q) {
             const R* pl = a.planes + 5 * q;
@@ -742,43 +869,52 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg
     }
 }
 
-template <class R, class PR, int LANES, bool ACCEL, bool WC>
+template <class R, class PR, int MODEL, int LANES, bool ACCEL, bool WC>
 static hipError_t launch_adj_t(const AdjArgs<R, PR>& a, int vb, int ve, hipStream_t s)
 {
     const int64_t threads = int64_t(ve - vb) * LANES;
     if (threads <= 0) return hipSuccess;
     const int blocks = int((threads + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL((k_adj_phase<R, PR, LANES, ACCEL, WC>), dim3(blocks), dim3(kBlock), 0, s, a,
-                       vb, ve);
+    hipLaunchKernelGGL((k_adj_phase<R, PR, MODEL, LANES, ACCEL, WC>), dim3(blocks), dim3(kBlock), 0,
+                       s, a, vb, ve);
     return hipGetLastError();
 }
 
-template <class R, class PR, int LANES>
+template <class R, class PR, int MODEL, int LANES>
 static hipError_t adj_flags(const AdjArgs<R, PR>& a, bool accel, bool wc, int vb, int ve,
                             hipStream_t s)
 {
     if (accel) {
-        return wc ? launch_adj_t<R, PR, LANES, true, true>(a, vb, ve, s)
-                  : launch_adj_t<R, PR, LANES, true, false>(a, vb, ve, s);
+        return wc ? launch_adj_t<R, PR, MODEL, LANES, true, true>(a, vb, ve, s)
+                  : launch_adj_t<R, PR, MODEL, LANES, true, false>(a, vb, ve, s);
     }
-    return wc ? launch_adj_t<R, PR, LANES, false, true>(a, vb, ve, s)
-              : launch_adj_t<R, PR, LANES, false, false>(a, vb, ve, s);
+    return wc ? launch_adj_t<R, PR, MODEL, LANES, false, true>(a, vb, ve, s)
+              : launch_adj_t<R, PR, MODEL, LANES, false, false>(a, vb, ve, s);
+}
+
+template <class R, class PR, int MODEL>
+static hipError_t adj_lanes(const AdjArgs<R, PR>& a, int lanes, bool accel, bool wc, int vbeg,
+                            int vend, hipStream_t s)
+{
+    switch (lanes) {
+    case 1: return adj_flags<R, PR, MODEL, 1>(a, accel, wc, vbeg, vend, s);
+    case 2: return adj_flags<R, PR, MODEL, 2>(a, accel, wc, vbeg, vend, s);
+    case 4: return adj_flags<R, PR, MODEL, 4>(a, accel, wc, vbeg, vend, s);
+    case 8: return adj_flags<R, PR, MODEL, 8>(a, accel, wc, vbeg, vend, s);
+    case 16: return adj_flags<R, PR, MODEL, 16>(a, accel, wc, vbeg, vend, s);
+    case 32: return adj_flags<R, PR, MODEL, 32>(a, accel, wc, vbeg, vend, s);
+    case 64: return adj_flags<R, PR, MODEL, 64>(a, accel, wc, vbeg, vend, s);
+    default: return hipErrorInvalidValue;
+    }
 }
 
 template <class R, class PR>
-hipError_t launch_adjoint_phase(const AdjArgs<R, PR>& a, int lanes, bool accel, bool wc, int vbeg,
-                                int vend, hipStream_t s)
+hipError_t launch_adjoint_phase(const AdjArgs<R, PR>& a, int model, int lanes, bool accel, bool wc,
+                                int vbeg, int vend, hipStream_t s)
 {
-    switch (lanes) {
-    case 1: return adj_flags<R, PR, 1>(a, accel, wc, vbeg, vend, s);
-    case 2: return adj_flags<R, PR, 2>(a, accel, wc, vbeg, vend, s);
-    case 4: return adj_flags<R, PR, 4>(a, accel, wc, vbeg, vend, s);
-    case 8: return adj_flags<R, PR, 8>(a, accel, wc, vbeg, vend, s);
-    case 16: return adj_flags<R, PR, 16>(a, accel, wc, vbeg, vend, s);
-    case 32: return adj_flags<R, PR, 32>(a, accel, wc, vbeg, vend, s);
-    case 64: return adj_flags<R, PR, 64>(a, accel, wc, vbeg, vend, s);
-    default: return hipErrorInvalidValue;
-    }
+    if (model == kNeo) return adj_lanes<R, PR, kNeo>(a, lanes, accel, wc, vbeg, vend, s);
+    if (model == kSnh) return adj_lanes<R, PR, kSnh>(a, lanes, accel, wc, vbeg, vend, s);
+    return adj_lanes<R, PR, kCor>(a, lanes, accel, wc, vbeg, vend, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -848,7 +984,14 @@ __global__ __launch_bounds__(kBlock) void k_tet_stress(ResArgs<R> a)
     const double J = dot(F.c0, C.c0);
     Cols<double> P;
     double psi;
-    if (MODEL == kNeo) {
+    if constexpr (MODEL == kSnh) {
+        const double a = G.mu * (1.0 - 1.0 / (1.0 + frob2(F)));
+        const double q = G.lam * (J - 1.0) - 0.75 * G.mu;
+        P.c0 = a * F.c0 + q * C.c0;
+        P.c1 = a * F.c1 + q * C.c1;
+        P.c2 = a * F.c2 + q * C.c2;
+        psi = snh_energy(F, J, G.mu, G.lam);
+    } else if constexpr (MODEL == kNeo) {
         const double lh = G.mu + G.lam;
         const double q = J - 1.0 - G.mu / lh;
         P.c0 = G.mu * F.c0 + (lh * q) * C.c0;
@@ -943,6 +1086,8 @@ hipError_t launch_residual(const ResArgs<R>& a, double* rsq, double* r_out, hipS
     if (a.n_tets > 0) {
         if (a.model == kNeo)
             hipLaunchKernelGGL((k_tet_stress<R, kNeo>), dim3(nblk(a.n_tets)), dim3(kBlock), 0, s, a);
+        else if (a.model == kSnh)
+            hipLaunchKernelGGL((k_tet_stress<R, kSnh>), dim3(nblk(a.n_tets)), dim3(kBlock), 0, s, a);
         else
             hipLaunchKernelGGL((k_tet_stress<R, kCor>), dim3(nblk(a.n_tets)), dim3(kBlock), 0, s, a);
     }
@@ -956,7 +1101,7 @@ hipError_t launch_residual(const ResArgs<R>& a, double* rsq, double* r_out, hipS
 // Adjoint assembly in FP64: per tet V0 dP[Lam] (into vp) and the parameter
 // gradients; per vertex (H lam)_i, the adjoint residual b - H lam on free
 // vertices and dL/dx_D = -(H lam)_k on Dirichlet vertices.
-template <class R>
+template <class R, int MODEL>
 __global__ __launch_bounds__(kBlock) void k_tet_adjoint(ResArgs<R> a,
                                                         const typename R4t<R>::T* L,
                                                         double* dmu, double* dlam)
@@ -970,17 +1115,32 @@ __global__ __launch_bounds__(kBlock) void k_tet_adjoint(ResArgs<R> a,
     const Cols<double> Lm = edge_F(x64(L[t.y]) - l0, x64(L[t.z]) - l0, x64(L[t.w]) - l0, G.dm);
     const Cols<double> C = cofactor(F);
     const double J = dot(F.c0, C.c0);
-    const double lh = G.mu + G.lam;
-    const double qq = lh * (J - 1.0) - G.mu;
     const double cofL = dot(C.c0, Lm.c0) + dot(C.c1, Lm.c1) + dot(C.c2, Lm.c2);
     const double FL = dot(F.c0, Lm.c0) + dot(F.c1, Lm.c1) + dot(F.c2, Lm.c2);
     Cols<double> dP;
-    dP.c0 = G.mu * Lm.c0 + (lh * cofL) * C.c0 + qq * (cross(Lm.c1, F.c2) + cross(F.c1, Lm.c2));
-    dP.c1 = G.mu * Lm.c1 + (lh * cofL) * C.c1 + qq * (cross(Lm.c2, F.c0) + cross(F.c2, Lm.c0));
-    dP.c2 = G.mu * Lm.c2 + (lh * cofL) * C.c2 + qq * (cross(Lm.c0, F.c1) + cross(F.c0, Lm.c1));
+    double dPdmu;   // <dP/dmu, Lam>
+    if constexpr (MODEL == kNeo) {
+        const double lh = G.mu + G.lam;
+        const double qq = lh * (J - 1.0) - G.mu;
+        dP.c0 = G.mu * Lm.c0 + (lh * cofL) * C.c0 + qq * (cross(Lm.c1, F.c2) + cross(F.c1, Lm.c2));
+        dP.c1 = G.mu * Lm.c1 + (lh * cofL) * C.c1 + qq * (cross(Lm.c2, F.c0) + cross(F.c2, Lm.c0));
+        dP.c2 = G.mu * Lm.c2 + (lh * cofL) * C.c2 + qq * (cross(Lm.c0, F.c1) + cross(F.c0, Lm.c1));
+        // dP/dmu = F + (J - 2) cof F
+        dPdmu = FL + (J - 2.0) * cofL;
+    } else {
+        dP = stress_diff<double, MODEL>(F, C, J, Lm, G.mu, G.lam);
+        if constexpr (MODEL == kSnh) {
+            // dP/dmu = (1 - 1/(1 + |F|^2)) F - 3/4 cof F
+            dPdmu = (1.0 - 1.0 / (1.0 + frob2(F))) * FL - 0.75 * cofL;
+        } else {
+            // dP/dmu = 2 (F - R)
+            const Cols<double> Rm = rotation_of(F);
+            dPdmu = 2.0 * (FL - dot(Rm.c0, Lm.c0) - dot(Rm.c1, Lm.c1) - dot(Rm.c2, Lm.c2));
+        }
+    }
     store_slot_forces(a.vp + 12 * int64_t(e), G, dP);
-    // dP/dmu = F + (J - 2) cof F, dP/dlambda = (J - 1) cof F
-    if (dmu) dmu[e] = -G.V0 * (FL + (J - 2.0) * cofL);
+    // dP/dlambda = (J - 1) cof F for every model
+    if (dmu) dmu[e] = -G.V0 * dPdmu;
     if (dlam) dlam[e] = -G.V0 * (J - 1.0) * cofL;
 }
 
@@ -1024,9 +1184,17 @@ hipError_t launch_adjoint_assembly(const ResArgs<R>& a, const typename R4t<R>::T
                                    const typename R4t<R>::T* b, double* rsq, double* dmu,
                                    double* dlam, double* dxd, const int* dir_pos, hipStream_t s)
 {
-    if (a.n_tets > 0)
-        hipLaunchKernelGGL((k_tet_adjoint<R>), dim3(nblk(a.n_tets)), dim3(kBlock), 0, s, a, lam,
-                           dmu, dlam);
+    if (a.n_tets > 0) {
+        if (a.model == kNeo)
+            hipLaunchKernelGGL((k_tet_adjoint<R, kNeo>), dim3(nblk(a.n_tets)), dim3(kBlock), 0, s, a,
+                               lam, dmu, dlam);
+        else if (a.model == kSnh)
+            hipLaunchKernelGGL((k_tet_adjoint<R, kSnh>), dim3(nblk(a.n_tets)), dim3(kBlock), 0, s, a,
+                               lam, dmu, dlam);
+        else
+            hipLaunchKernelGGL((k_tet_adjoint<R, kCor>), dim3(nblk(a.n_tets)), dim3(kBlock), 0, s, a,
+                               lam, dmu, dlam);
+    }
     if (a.n_verts > 0)
         hipLaunchKernelGGL((k_vertex_adjoint<R>), dim3(nblk(a.n_verts)), dim3(kBlock), 0, s, a,
                            lam, b, rsq, dxd, dir_pos);
@@ -1356,8 +1524,8 @@ hipError_t launch_set_inertia(const double* x_n, const double* x_prev, const int
 #define PBNG_INST_SWEEP(R, PR)                                                                    \
     template hipError_t launch_phase<R, PR>(const SweepArgs<R, PR>&, int, int, bool, bool, bool,  \
                                             int, int, hipStream_t);                               \
-    template hipError_t launch_adjoint_phase<R, PR>(const AdjArgs<R, PR>&, int, bool, bool, int,  \
-                                                    int, hipStream_t);                            \
+    template hipError_t launch_adjoint_phase<R, PR>(const AdjArgs<R, PR>&, int, int, bool, bool,  \
+                                                    int, int, hipStream_t);                            \
     template hipError_t launch_set_inertia<R, PR>(const double*, const double*, const int*,       \
                                                   const double*, int, double, R*, R4t<PR>::T*,    \
                                                   double*, double*, hipStream_t);

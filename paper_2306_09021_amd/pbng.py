@@ -20,7 +20,7 @@ LIB_PATH = os.environ.get("PBNG_LIBRARY") or os.path.join(_HERE, "libpbng.so")
 OK, NOT_CONVERGED = 0, 1
 ERRORS = {-1: "EINVAL", -2: "EMESH", -3: "EMATERIAL", -4: "ECOLOR", -5: "ENAN", -6: "EHIP",
           -7: "ENOMEM", -8: "EUNSUPPORTED"}
-MODEL = {"nh": 0, "corotated": 1}
+MODEL = {"nh": 0, "corotated": 1, "snh": 2}
 REAL = {"f32": 0, "f64": 1, "mixed": 2}
 ACCEL = {"none": 0, "chebyshev": 1, "sor": 2}
 SAFEGUARD = {"none": 0, "backtrack": 1}

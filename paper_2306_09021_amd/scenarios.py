@@ -177,7 +177,7 @@ def twist_box(n: int = 10, model: str = COROTATED, E: float = 1e4, nu: float = 0
                                real="f64", rel_tol=0.0))
 
 
-def paper_box_frames(n: int, model: str = COROTATED, n_frames: int = 4, E: float = 1e5,
+def paper_box_frames(n: int, model: str = COROTATED, n_frames: int = 60, E: float = 1e5,
                      nu: float = 0.3, density: float = 10.0, twist_deg: float = 90.0,
                      stretch: float = 1.5):
     """The paper's stretching block (Sec. "Examples", "Stretching Block"):

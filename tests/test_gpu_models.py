@@ -1,0 +1,123 @@
+"""The stable Neo-Hookean model (Eq. snh, Lame lambda on the volume term)
+and the adjoint of the corotated and stable Neo-Hookean models on the GPU,
+against the FP64 oracle.  Tolerances as elsewhere: FP64 sweeps 1e-10
+relative, FP32 1e-5, residual and energy 1e-10, FP64 adjoint 1e-8, FP32
+adjoint 1e-4."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import dense as D
+from paper_2306_09021_amd import pbng
+from paper_2306_09021_amd import scenarios as S
+
+from .gpu_util import announce, dev_x, host, rel_err, require_gpu, workspace
+from .test_oracle_solve import small_twist, with_extras
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def run_both(sc, real, sweeps, **kw):
+    op = O.make_problem(sc)
+    col, _ = O.color(op)
+    xo, sto = O.solve(op, col, sc.initial_iterate(), max_sweeps=sweeps, **kw)
+    ws = workspace([sc], real)
+    x = dev_x(sc.initial_iterate(), real)
+    rc, st = ws.solve(x, max_sweeps=sweeps, rel_tol=0.0, check_every=sweeps, **kw)
+    return host(x), xo, st[0], sto
+
+
+@pytest.mark.parametrize("real,tol", [("f64", 1e-10), ("f32", 1e-5), ("mixed", 1e-5)])
+@pytest.mark.parametrize("kw", [dict(accel="none", safeguard="backtrack"),
+                                dict(accel="chebyshev", rho=0.9, gamma=1.3, safeguard="backtrack"),
+                                dict(accel="sor", omega=1.4, safeguard="none")])
+def test_stable_neohookean_parity(real, tol, kw):
+    sc = S.twist_box(6, "snh", 1e4, 0.3, 60.0, 1.2, 0.01, seed=4)
+    announce("stable NH twist6 %s %s" % (real, kw))
+    xg, xo, st, sto = run_both(sc, real, 40, **kw)
+    print(real, kw, rel_err(xg, xo), "oracle halvings", sto["halvings"])
+    assert rel_err(xg, xo) <= tol
+
+
+def test_stable_neohookean_general_kernel_parity():
+    """Weak constraints, a contact plane, gravity and nodal loads through the
+    general kernel, FP64 (the safeguard's accept/halve choice is taken in the
+    oracle's precision)."""
+    sc = with_extras(small_twist(5, "snh"))
+    announce("stable NH weak+contact f64")
+    xg, xo, st, sto = run_both(sc, "f64", 40, accel="chebyshev", rho=0.9, gamma=1.2,
+                               safeguard="backtrack")
+    assert rel_err(xg, xo) <= 1e-10
+
+
+def test_stable_neohookean_residual_and_energy():
+    sc = with_extras(small_twist(5, "snh"))
+    op = O.make_problem(sc)
+    x = sc.initial_iterate() + 1e-3 * np.random.default_rng(2).normal(size=(sc.n_verts, 3))
+    x[sc.dirichlet_idx] = sc.dirichlet_x
+    n_o, E_o, r_o = O.residual(op, x)
+    announce("stable NH residual f64")
+    ws = workspace([sc], "f64")
+    rn, E, r = ws.residual(dev_x(x, "f64"), want_r=True)
+    assert abs(rn[0] - n_o) <= 1e-10 * n_o
+    assert abs(E[0] - E_o) <= 1e-10 * abs(E_o)
+    assert np.abs(host(r) - r_o).max() <= 1e-10 * np.abs(r_o).max()
+
+
+@pytest.mark.parametrize("model", ["corotated", "snh"])
+@pytest.mark.parametrize("real,tol", [("f64", 1e-8), ("f32", 1e-4)])
+def test_adjoint_matches_dense_solve(model, real, tol):
+    """H lam = dL/dx at a Newton equilibrium of a tiny mesh with per-tet
+    materials: GPU block Gauss-Seidel (modified diagonal blocks) and
+    gradient assembly against the oracle's dense solve and assembly."""
+    rng = np.random.default_rng(11)
+    sc = S.random_cube(rng, 4, model, 1e4, 0.3, 15.0, 0.9, 1.1, "adj")
+    sc.E = 1e4 * np.exp(0.3 * rng.normal(size=sc.n_tets))
+    sc.nu = rng.uniform(0.25, 0.42, size=sc.n_tets)
+    target = sc.rest_pos + 0.05 * rng.normal(size=sc.rest_pos.shape)
+    op = O.make_problem(sc)
+    x, it, rel = D.newton(op, sc.initial_iterate(), tol=1e-14)
+    if real == "f32":
+        x = x.astype(np.float32).astype(np.float64)
+    free = (op.is_dir == 0)[:, None]
+    g = 2.0 * (x - target) * free
+    g[op.dirichlet_idx] = 0.3
+    lam_d = D.adjoint_dense(op, x, g)
+    dmu, dla, dxd = O.adjoint_gradients(op, x, lam_d)
+    dxd = dxd[op.dirichlet_idx] + g[op.dirichlet_idx]
+    announce("adjoint %s dense parity %s" % (model, real))
+    ws = workspace([sc], real)
+    o = pbng.adjoint_opts(rel_tol=1e-12 if real == "f64" else 1e-6, max_sweeps=40000,
+                          check_every=20, accel="chebyshev", rho=0.9, gamma=1.0)
+    rc, out, st = ws.adjoint(dev_x(x, real), dev_x(g, real), o)
+    out = {k: host(v) for k, v in out.items()}
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    print(model, real, "sweeps", st[0]["sweeps"], "rel", st[0]["rel_residual"],
+          rel(out["lam_vec"], lam_d), rel(out["mu"], dmu))
+    assert st[0]["rel_residual"] <= (1e-11 if real == "f64" else 2e-6)
+    # the FD Hessian of the corotated dense reference carries ~1e-8 error
+    t = max(tol, 1e-7) if model == "corotated" else tol
+    assert rel(out["lam_vec"], lam_d) <= t
+    assert rel(out["mu"], dmu) <= t
+    assert rel(out["lam"], dla) <= t
+    assert rel(out["xd"], dxd) <= t
+
+
+def test_stable_neohookean_safeguard_active_parity():
+    """A stiff contact plane through the middle of a stable Neo-Hookean box:
+    the backtracking safeguard halves steps at the penalty's kink (FP64, the
+    oracle's precision for the accept/halve decisions)."""
+    sc = with_extras(small_twist(5, "snh"))
+    sc.planes[0, 4] = 1e5
+    sc.planes[0, 3] = sc.x0[:, 1].min() + 0.5
+    announce("stable NH stiff plane safeguard f64")
+    xg, xo, st, sto = run_both(sc, "f64", 40, accel="chebyshev", rho=0.9, gamma=1.2,
+                               safeguard="backtrack")
+    print("halvings", sto["halvings"])
+    assert sto["halvings"] > 0
+    assert rel_err(xg, xo) <= 1e-10
