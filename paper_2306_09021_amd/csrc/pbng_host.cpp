@@ -352,6 +352,11 @@ struct pbng_workspace {
     // sweep data
     Dev W, P, N, Wres;
     Dev jv, ma, mb, mc, vmu, Sv, flag, vptr, fext, vinst, active, rejected;
+    // model id of the sweep and adjoint kernels: the public model, or 3 for
+    // Neo-Hookean workspaces whose instances each have one (mu, lambda)
+    // (40-byte records; instance parameters in imu / ilam)
+    int kmodel = PBNG_NEOHOOKEAN;
+    Dev imu, ilam, t_off_dev;
     // backward-Euler inertia (off until pbng_workspace_set_inertia)
     bool inertia = false;
     Dev mass64, inert, xhat, inert64, xhat64;
@@ -443,6 +448,20 @@ SegPlan make_plan(const std::vector<int64_t>& seg, Dev& cb, Dev& ce, Dev& qp, De
     return P;
 }
 
+// Record streams for the workspace's kernel model: 40-byte Neo-Hookean
+// (jv, ma, mc), 48-byte Neo-Hookean (jv, ma, mb) or full (jv, ma, mb, mc);
+// FP64 workspaces add vmu.
+void alloc_records(pbng_workspace* ws)
+{
+    const size_t r = ws->math64() ? sizeof(double) : sizeof(float);
+    const size_t nv = size_t(ws->nvis);
+    const bool u = ws->kmodel == 3, nh = ws->kmodel == PBNG_NEOHOOKEAN;
+    ws->ma.alloc(nv * 4 * r);
+    ws->mb.alloc(u ? 0 : nv * 4 * r);
+    ws->mc.alloc(nh ? 0 : nv * 2 * r);
+    ws->vmu.alloc(ws->math64() ? nv * r : 0);
+}
+
 template <class R>
 VisitBuild<R> visit_build(pbng_workspace* ws)
 {
@@ -451,7 +470,7 @@ VisitBuild<R> visit_build(pbng_workspace* ws)
     b.rv = ws->rv.as<int>();
     b.vptr = ws->vptr.as<int>();
     b.n_free = int(ws->nfree);
-    b.model = ws->model;
+    b.model = ws->kmodel;
     b.jv = ws->jv.as<int4>();
     b.ma = ws->ma.as<typename R4t<R>::T>();
     b.mb = ws->mb.as<typename R4t<R>::T>();
@@ -506,6 +525,7 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     std::vector<double> dminv(9 * nt), V0(nt), mu(nt), lam(nt);
     std::vector<double> fext(3 * nv, 0.0);
     std::vector<double> mass(nv, 0.0);
+    std::vector<double> inst_mu, inst_lam;
     std::vector<char> isdir(nv, 0);
     std::vector<int> valence(nv, 0);
     std::vector<Incidence> inc(n);
@@ -551,6 +571,21 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
         // has a curvature along x_i that the modified Hessian does not bound)
         ws->safeguard_inactive = ws->n_planes == 0 &&
                                  (ws->model == PBNG_COROTATED || (ws->model == PBNG_NEOHOOKEAN && lam_ge_mu));
+        bool uniform = true;
+        for (int q = 0; q < n && uniform; ++q)
+            for (int64_t e = ws->t_off[q] + 1; e < ws->t_off[q + 1]; ++e)
+                if (mu[e] != mu[ws->t_off[q]] || lam[e] != lam[ws->t_off[q]]) {
+                    uniform = false;
+                    break;
+                }
+        ws->kmodel = (ws->model == PBNG_NEOHOOKEAN && uniform) ? 3 : ws->model;
+        inst_mu.assign(n, 0.0);
+        inst_lam.assign(n, 0.0);
+        for (int q = 0; q < n; ++q)
+            if (ws->t_off[q + 1] > ws->t_off[q]) {
+                inst_mu[q] = mu[ws->t_off[q]];
+                inst_lam[q] = lam[ws->t_off[q]];
+            }
     }
 
     // internal order
@@ -758,14 +793,11 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     std::vector<int> vptr_free(rvptr.begin(), rvptr.begin() + nfree + 1);
     ws->vptr.upload(vptr_free);
     ws->jv.upload(JV);
-    {
-        const size_t r = ws->math64() ? sizeof(double) : sizeof(float);
-        ws->ma.alloc(size_t(ws->nvis) * 4 * r);
-        ws->mb.alloc(size_t(ws->nvis) * 4 * r);
-        ws->mc.alloc(ws->model != PBNG_NEOHOOKEAN ? size_t(ws->nvis) * 2 * r : 0);
-        ws->vmu.alloc(ws->math64() ? size_t(ws->nvis) * r : 0);
-        ws->Sv.alloc(size_t(nfree) * r);
-    }
+    alloc_records(ws);
+    ws->Sv.alloc(size_t(nfree) * (ws->math64() ? sizeof(double) : sizeof(float)));
+    upR(ws->imu, inst_mu);
+    upR(ws->ilam, inst_lam);
+    ws->t_off_dev.upload(ws->t_off);
     upR(ws->fext, fext_free);
     ws->mass64.upload(mass_free);
     std::vector<int> vinst_free(vinst_all.begin(), vinst_all.begin() + nfree);
@@ -831,6 +863,8 @@ SweepArgs<R, PR> sweep_args(pbng_workspace* ws, double omega, double gamma, int 
     a.mc = ws->mc.as<typename R2t<R>::T>();
     a.vmu = ws->vmu.as<R>();
     a.Sv = ws->Sv.as<R>();
+    a.imu = ws->imu.as<R>();
+    a.ilam = ws->ilam.as<R>();
     a.fext = ws->fext.as<R4>();
     a.vinst = ws->vinst.as<int>();
     a.active = ws->active.as<int>();
@@ -956,7 +990,7 @@ void launch_sweep(pbng_workspace* ws, const pbng_solve_opts* o, double omega, do
     const bool accel = o->accel != PBNG_ACCEL_NONE;
     const SweepArgs<R, PR> a = sweep_args<R, PR>(ws, omega, gamma, o->max_halvings);
     for (int c = 0; c < ws->ncol; ++c)
-        hipchk(launch_phase<R, PR>(a, ws->model, pick_lanes(ws, o->lanes, c), accel,
+        hipchk(launch_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, c), accel,
                                safe_effective(ws, o), ws->general(), ws->col_ptr[c],
                                ws->col_ptr[c + 1], s),
                "sweep launch");
@@ -1145,6 +1179,8 @@ AdjArgs<R, PR> adj_args(pbng_workspace* ws, double omega, double gamma)
     a.mc = ws->mc.as<typename R2t<R>::T>();
     a.vmu = ws->vmu.as<R>();
     a.Sv = ws->Sv.as<R>();
+    a.imu = ws->imu.as<R>();
+    a.ilam = ws->ilam.as<R>();
     a.vinst = ws->vinst.as<int>();
     a.wvptr = ws->wvptr.as<int>();
     a.wv_c = ws->wv_c.as<int>();
@@ -1221,7 +1257,7 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
         omega_prev = omega;
         const AdjArgs<R, PR> a = adj_args<R, PR>(ws, omega, accel ? o->gamma : 1.0);
         for (int c = 0; c < ws->ncol; ++c)
-            hipchk(launch_adjoint_phase<R, PR>(a, ws->model, pick_lanes(ws, o->lanes, c), accel, ws->any_wc || ws->inertia, ws->col_ptr[c],
+            hipchk(launch_adjoint_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, c), accel, ws->any_wc || ws->inertia, ws->col_ptr[c],
                                            ws->col_ptr[c + 1], s),
                    "adjoint launch");
         if (accel) std::swap(ws->L.p, ws->LN.p);
@@ -1327,7 +1363,7 @@ void autotune_t(pbng_workspace* ws, const void* x, const pbng_solve_opts* o, pbn
             for (int trial = 0; trial < 3; ++trial) {
                 hipchk(hipEventRecord(ev.a, s), "record");
                 for (int r = 0; r < 8; ++r)
-                    hipchk(launch_phase<R, PR>(a, ws->model, L, accel, safe, ws->general(), vb, ve, s), "phase");
+                    hipchk(launch_phase<R, PR>(a, ws->kmodel, L, accel, safe, ws->general(), vb, ve, s), "phase");
                 hipchk(hipEventRecord(ev.b, s), "record");
                 t = std::min(t, ev.ms());
             }
@@ -1508,17 +1544,32 @@ int32_t pbng_workspace_set_materials(pbng_workspace* ws, const double* mu_dev, c
         check_ws(ws);
         if (!mu_dev || !lambda_dev) fail(PBNG_EINVAL, "null material arrays");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        hipchk(build_visits(ws, mu_dev, lambda_dev, s), "set materials");
-        // the Neo-Hookean step is a descent step without the safeguard only
-        // while lambda >= mu in every tet: re-check on the device
         if (ws->model == PBNG_NEOHOOKEAN) {
-            if (!ws->flag.p) ws->flag.alloc(sizeof(int));
-            hipchk(launch_lam_ge_mu(mu_dev, lambda_dev, int(ws->nt), ws->flag.as<int>(), s), "material check");
-            int h = 0;
-            hipchk(hipMemcpyAsync(&h, ws->flag.p, sizeof(int), hipMemcpyDeviceToHost, s), "material check");
+            // The Neo-Hookean step is a descent step without the safeguard
+            // only while lambda >= mu in every tet, and the 40-byte records
+            // need one (mu, lambda) per instance: re-check both on the device.
+            if (!ws->flag.p) ws->flag.alloc(2 * sizeof(int));
+            hipError_t e = ws->math64()
+                               ? launch_material_flags<double>(mu_dev, lambda_dev, ws->t_off_dev.as<int64_t>(),
+                                                               ws->n_inst, int(ws->nt), ws->flag.as<int>(),
+                                                               ws->imu.as<double>(), ws->ilam.as<double>(), s)
+                               : launch_material_flags<float>(mu_dev, lambda_dev, ws->t_off_dev.as<int64_t>(),
+                                                              ws->n_inst, int(ws->nt), ws->flag.as<int>(),
+                                                              ws->imu.as<float>(), ws->ilam.as<float>(), s);
+            hipchk(e, "material check");
+            int h[2] = {0, 0};
+            hipchk(hipMemcpyAsync(h, ws->flag.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "material check");
             hipchk(hipStreamSynchronize(s), "material check");
-            ws->safeguard_inactive = ws->n_planes == 0 && h != 0;
+            ws->safeguard_inactive = ws->n_planes == 0 && h[0] != 0;
+            const int km = h[1] ? 3 : PBNG_NEOHOOKEAN;
+            if (km != ws->kmodel) {
+                // the record form changes: new streams, new kernel variant
+                ws->kmodel = km;
+                alloc_records(ws);
+                ws->drop_graph();
+            }
         }
+        hipchk(build_visits(ws, mu_dev, lambda_dev, s), "set materials");
         return PBNG_OK;
     });
 }
@@ -1735,15 +1786,15 @@ int32_t pbng_phase(pbng_workspace* ws, int32_t color, const pbng_solve_opts* o, 
         const int c0 = ws->col_ptr[color], c1 = ws->col_ptr[color + 1];
         if (ws->real == PBNG_F64)
             hipchk(launch_phase<double, double>(sweep_args<double, double>(ws, 1.0, 1.0, o->max_halvings),
-                                                ws->model, lanes, accel, safe, ws->general(), c0, c1, s),
+                                                ws->kmodel, lanes, accel, safe, ws->general(), c0, c1, s),
                    "phase");
         else if (ws->real == PBNG_MIXED)
             hipchk(launch_phase<float, double>(sweep_args<float, double>(ws, 1.0, 1.0, o->max_halvings),
-                                               ws->model, lanes, accel, safe, ws->general(), c0, c1, s),
+                                               ws->kmodel, lanes, accel, safe, ws->general(), c0, c1, s),
                    "phase");
         else
             hipchk(launch_phase<float, float>(sweep_args<float, float>(ws, 1.0, 1.0, o->max_halvings),
-                                              ws->model, lanes, accel, safe, ws->general(), c0, c1, s),
+                                              ws->kmodel, lanes, accel, safe, ws->general(), c0, c1, s),
                    "phase");
         return PBNG_OK;
     });

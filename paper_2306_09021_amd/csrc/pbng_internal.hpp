@@ -15,7 +15,10 @@
 //   mb[k] = {m4, m5, m6, m7}  shape-function gradients (so that
 //   mc[k] = {m8, V0 lambda}   F = sum (x_j - x_i) dN_j^T)
 //   vmu[k] = V0 mu             FP64 workspaces only
-// In float: 16 + 16 + 16 + 8 = 56 bytes per visit.  Kernels address every
+// In float: 16 + 16 + 16 + 8 = 56 bytes per visit.  Neo-Hookean workspaces
+// store cof(M) dN_i and det M instead of m[9] (48 bytes), or, when every tet
+// of an instance has the same (mu, lambda), V0 alpha, beta and delta (40
+// bytes: jv, ma and mc, with delta in jv.w or vmu).  Kernels address every
 // stream with 32-bit byte offsets; the host rejects workspaces whose streams
 // exceed 4 GiB.
 #pragma once
@@ -70,6 +73,8 @@ struct SweepArgs {
     const R2* mc;
     const R* vmu;          // FP64 only
     const R* Sv;           // [n_free] sum V0 mu |dN_i|^2 per vertex
+    const R* imu;          // [n_inst] mu, lambda of each instance (40-byte
+    const R* ilam;         //          Neo-Hookean records only)
     const R4* fext;        // [n_free] lumped external force
     const int* vinst;      // [n_free] instance of each free vertex
     const int* active;     // [n_inst] 1 while the instance iterates
@@ -177,8 +182,13 @@ struct VisitBuild {
 };
 template <class R>
 hipError_t launch_build_visits(const VisitBuild<R>& b, hipStream_t s);
-// flag (device int) = 1 if lambda >= mu in every tet, else 0.
-hipError_t launch_lam_ge_mu(const double* mu, const double* lam, int n, int* flag, hipStream_t s);
+// Material flags after an update: flag[0] = 1 if lambda >= mu in every
+// tet, flag[1] = 1 if every instance has a single (mu, lambda); imu, ilam
+// receive the parameters of each instance's first tet.  t_off: [n_inst + 1]
+// tet offsets.
+template <class R>
+hipError_t launch_material_flags(const double* mu, const double* lam, const int64_t* t_off, int n_inst,
+                                 int n_tets, int* flag, R* imu, R* ilam, hipStream_t s);
 // Material update: TetGeo mu/lambda, then the visit records.
 template <class R>
 hipError_t launch_set_materials(const double* mu, const double* lam, TetGeo* geo, int n_tets,
@@ -224,6 +234,8 @@ struct AdjArgs {
     const R2* mc;
     const R* vmu;          // FP64 only
     const R* Sv;
+    const R* imu;
+    const R* ilam;
     const int* vinst;
     const int* wvptr;
     const int* wv_c;

@@ -23,6 +23,11 @@ namespace pbng {
 constexpr int kNeo = 0;
 constexpr int kCor = 1;
 constexpr int kSnh = 2;
+// Neo-Hookean with one (mu, lambda) per instance: the 40-byte record form
+// (internal model id; the public model is Neo-Hookean)
+constexpr int kNeoU = 3;
+template <int M>
+constexpr bool is_nh = M == kNeo || M == kNeoU;
 constexpr int kBlock = 256;
 
 // Element i of an array through a 32-bit byte offset, so that the load takes
@@ -259,7 +264,10 @@ __device__ __forceinline__ Cols<R> stress_diff(const Cols<R>& F, const Cols<R>& 
 //   cof F dN_i = cof D (cof M dN_i) = sum_k beta_k X_k,
 //                X_1 = e2 x e3, X_2 = e3 x e1, X_3 = e1 x e2,  beta = cof M dN_i
 //   J = det F  = delta (e1 . X_1),              delta = det M
-// and the record holds a = V0 mu alpha, V0 lambda, beta and delta.
+// and the record holds a = V0 mu alpha, V0 lambda, beta and delta.  Where
+// every tet of an instance has the same (mu, lambda), |delta| = 1 / (6 V0)
+// gives V0, so the record shrinks to V0 alpha, beta and delta (40 bytes in
+// FP32) and V0 mu, V0 lambda come from the instance's parameters.
 template <class R>
 struct VisitRaw {
     int i1, i2, i3;
@@ -300,21 +308,35 @@ __device__ __forceinline__ VisitRaw<R> load_raw(const A& a, int k)
     return r;
 }
 
-template <class R, class A>
-__device__ __forceinline__ VisitNH<R> load_nh(const A& a, int k)
+// Neo-Hookean record k; mu, lam are the instance's parameters (used by the
+// 40-byte form only).
+template <class R, int MODEL, class A>
+__device__ __forceinline__ VisitNH<R> load_nh(const A& a, int k, R mu, R lam)
 {
     VisitNH<R> r;
     const int4 j = at(a.jv, k);
     const auto p = at(a.ma, k);
-    const auto q = at(a.mb, k);
     r.i1 = j.x;
     r.i2 = j.y;
     r.i3 = j.z;
-    r.a = mk(p.x, p.y, p.z);
-    r.vl = p.w;
-    r.beta = mk(q.x, q.y, q.z);
-    r.delta = q.w;
-    r.vm = vm_of<R>(j, a.vmu, k);
+    if constexpr (MODEL == kNeoU) {
+        // jv.w (FP32) or vmu (FP64) = delta; ma = (V0 alpha, beta_1); mc = (beta_2, beta_3)
+        const auto t = at(a.mc, k);
+        const R delta = vm_of<R>(j, a.vmu, k);
+        const R V0 = rcp(R(6) * abs_(delta));
+        r.delta = delta;
+        r.vm = mu * V0;
+        r.vl = lam * V0;
+        r.a = mu * mk(p.x, p.y, p.z);
+        r.beta = mk(p.w, t.x, t.y);
+    } else {
+        const auto q = at(a.mb, k);
+        r.a = mk(p.x, p.y, p.z);
+        r.vl = p.w;
+        r.beta = mk(q.x, q.y, q.z);
+        r.delta = q.w;
+        r.vm = vm_of<R>(j, a.vmu, k);
+    }
     return r;
 }
 
@@ -417,24 +439,25 @@ __device__ __forceinline__ void visit_full(Acc<R>& q, const VisitRaw<R>& r, V3<R
 // fewer visits sit a visit out under the execution mask.  A lane without a
 // second visit loads its first one twice and skips the second accumulation.
 template <class R, int MODEL, bool SAFE, int LANES, class A, class PR>
-__device__ __forceinline__ void lane_visits(const A& a, Acc<R>& q, int kb, int ke, int lane, V3<PR> xi)
+__device__ __forceinline__ void lane_visits(const A& a, Acc<R>& q, int kb, int ke, int lane, V3<PR> xi,
+                                            R imu, R ilam)
 {
     for (int k = kb + lane; __any(k < ke); k += 2 * LANES) {
         const bool h0 = k < ke;
         const bool h1 = k + LANES < ke;
         const int k1 = h1 ? k + LANES : k;
-        if constexpr (MODEL == kNeo) {
+        if constexpr (is_nh<MODEL>) {
             if (__any(h1)) {
                 if (h0) {
-                    const VisitNH<R> r0 = load_nh<R>(a, k);
-                    const VisitNH<R> r1 = load_nh<R>(a, k1);
+                    const VisitNH<R> r0 = load_nh<R, MODEL>(a, k, imu, ilam);
+                    const VisitNH<R> r1 = load_nh<R, MODEL>(a, k1, imu, ilam);
                     const auto p01 = at(a.W, r0.i1), p02 = at(a.W, r0.i2), p03 = at(a.W, r0.i3);
                     const auto p11 = at(a.W, r1.i1), p12 = at(a.W, r1.i2), p13 = at(a.W, r1.i3);
                     visit_nh<R, SAFE>(q, r0, rel<R>(p01, xi), rel<R>(p02, xi), rel<R>(p03, xi));
                     if (h1) visit_nh<R, SAFE>(q, r1, rel<R>(p11, xi), rel<R>(p12, xi), rel<R>(p13, xi));
                 }
             } else if (h0) {
-                const VisitNH<R> r0 = load_nh<R>(a, k);
+                const VisitNH<R> r0 = load_nh<R, MODEL>(a, k, imu, ilam);
                 visit_nh<R, SAFE>(q, r0, rel<R>(at(a.W, r0.i1), xi), rel<R>(at(a.W, r0.i2), xi),
                                   rel<R>(at(a.W, r0.i3), xi));
             }
@@ -492,7 +515,12 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
     q.E0a = R(0);
 
     // lane l takes visits kb + l, kb + l + LANES, ...
-    lane_visits<R, MODEL, SAFE, LANES>(a, q, kb, ke, lane, xi);
+    R imu = R(0), ilam = R(0);
+    if constexpr (MODEL == kNeoU) {
+        imu = at(a.imu, inst);
+        ilam = at(a.ilam, inst);
+    }
+    lane_visits<R, MODEL, SAFE, LANES>(a, q, kb, ke, lane, xi, imu, ilam);
     V3<R>& g = q.g;
     const R S = at(a.Sv, v);  // sum V0 mu |dN_i|^2 of the vertex
     Sym<R>& Aw = q.Aw;
@@ -513,7 +541,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
             const V3<R> gk = s * symK_mul(K, Cc);
             g = g + gk;
             sym_add_scaled(Aw, s * s, K);
-            if (SAFE && MODEL != kNeo) {
+            if (SAFE && !is_nh<MODEL>) {
                 gw = gw + gk;
                 sym_add_scaled(Kw, s * s, K);
             }
@@ -522,8 +550,8 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
     if (LANES > 1) {
         lsum3<LANES>(g);
         lsum6<LANES>(Aw);
-        if (SAFE && MODEL == kNeo) lsum6<LANES>(Cm);
-        if (SAFE && MODEL != kNeo) {
+        if (SAFE && is_nh<MODEL>) lsum6<LANES>(Cm);
+        if (SAFE && !is_nh<MODEL>) {
             E0 = lsum<LANES>(E0);
             E0a = lsum<LANES>(E0a);
             if (WC) {
@@ -541,7 +569,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
         Aw.xx += c;
         Aw.yy += c;
         Aw.zz += c;
-        if (SAFE && MODEL != kNeo) {
+        if (SAFE && !is_nh<MODEL>) {
             gw = gw + c * dx;
             Kw.xx += c;
             Kw.yy += c;
@@ -608,7 +636,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
             }
             bound_ok = dE <= R(8) * u * ab;
         }
-        if constexpr (MODEL == kNeo) {
+        if constexpr (is_nh<MODEL>) {
             // Along x_i + alpha d the Neo-Hookean energy of the incident tets
             // is exactly quadratic: |F|^2 is quadratic and det F affine in x_i
             // (a rank-one update), with Hessian sum V0 (mu |dN_i|^2 I + lhat
@@ -640,7 +668,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
                     ab += e0 + e1;
                 }
             }
-            if constexpr (MODEL != kNeo) {
+            if constexpr (!is_nh<MODEL>) {
                 // exact elastic energy of the incident tets at the trial point
                 R E1 = R(0), E1a = R(0);
                 for (int k = kb + lane; k < ke; k += LANES) {
@@ -739,6 +767,7 @@ hipError_t launch_phase(const SweepArgs<R, PR>& a, int model, int lanes, bool ac
                         bool wc, int vbeg, int vend, hipStream_t s)
 {
     if (model == kNeo) return dispatch_lanes<R, PR, kNeo>(a, lanes, accel, safe, wc, vbeg, vend, s);
+    if (model == kNeoU) return dispatch_lanes<R, PR, kNeoU>(a, lanes, accel, safe, wc, vbeg, vend, s);
     if (model == kSnh) return dispatch_lanes<R, PR, kSnh>(a, lanes, accel, safe, wc, vbeg, vend, s);
     return dispatch_lanes<R, PR, kCor>(a, lanes, accel, safe, wc, vbeg, vend, s);
 }
@@ -777,7 +806,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg
     // lambda, X_k = cof D columns): Lam dN_i = sum alpha_a l_a,
     // cof F : Lam = delta sum_k X_k . l_k and dcof[Lam] dN_i =
     // sum_k beta_k (derivative of X_k along l).
-    if constexpr (MODEL != kNeo) {
+    R imu = R(0), ilam = R(0);
+    if constexpr (MODEL == kNeoU) {
+        const int q0 = at(a.vinst, v);   // batched workspaces need not take the WC path
+        imu = at(a.imu, q0);
+        ilam = at(a.ilam, q0);
+    }
+    if constexpr (!is_nh<MODEL>) {
         for (int k = kb + lane; k < ke; k += LANES) {
             const VisitRaw<R> q = load_raw<R>(a, k);
             const Cols<R> F = edge_F(rel<R>(at(a.X, q.i1), xi), rel<R>(at(a.X, q.i2), xi),
@@ -792,8 +827,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg
             sym_add_outer(Hc, q.vl, apply(C, av));
         }
     }
-    for (int k = kb + lane; MODEL == kNeo && k < ke; k += LANES) {
-        const VisitNH<R> q = load_nh<R>(a, k);
+    for (int k = kb + lane; is_nh<MODEL> && k < ke; k += LANES) {
+        const VisitNH<R> q = load_nh<R, MODEL>(a, k, imu, ilam);
         const V3<R> e1 = rel<R>(at(a.X, q.i1), xi), e2 = rel<R>(at(a.X, q.i2), xi),
                     e3 = rel<R>(at(a.X, q.i3), xi);
         const V3<R> l1 = rel<R>(at(a.L, q.i1), li), l2 = rel<R>(at(a.L, q.i2), li),
@@ -838,7 +873,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg
         Hc.yy += c;
         Hc.zz += c;
     }
-    const R Sd = MODEL == kNeo ? S : R(2) * S;
+    const R Sd = is_nh<MODEL> ? S : R(2) * S;
     Hc.xx += Sd;
     Hc.yy += Sd;
     Hc.zz += Sd;
@@ -913,6 +948,7 @@ hipError_t launch_adjoint_phase(const AdjArgs<R, PR>& a, int model, int lanes, b
                                 int vbeg, int vend, hipStream_t s)
 {
     if (model == kNeo) return adj_lanes<R, PR, kNeo>(a, lanes, accel, wc, vbeg, vend, s);
+    if (model == kNeoU) return adj_lanes<R, PR, kNeoU>(a, lanes, accel, wc, vbeg, vend, s);
     if (model == kSnh) return adj_lanes<R, PR, kSnh>(a, lanes, accel, wc, vbeg, vend, s);
     return adj_lanes<R, PR, kCor>(a, lanes, accel, wc, vbeg, vend, s);
 }
@@ -1405,10 +1441,19 @@ __global__ __launch_bounds__(kBlock) void k_build_visits(VisitBuild<R> b)
         if constexpr (sizeof(R) == 4) b.jv[k].w = __float_as_int(float(vm));
         else b.vmu[k] = vm;
         using R4 = typename R4t<R>::T;
-        if (b.model == kNeo) {
+        if (b.model == kNeo || b.model == kNeoU) {
             // rows of cof M are m2 x m3, m3 x m1, m1 x m2
             const V3<double> c1 = cross(m[1], m[2]), c2 = cross(m[2], m[0]), c3 = cross(m[0], m[1]);
             const double delta = dot(m[0], c1);
+            if (b.model == kNeoU) {
+                // 40-byte form: delta in jv.w (FP32) or vmu (FP64), V0 alpha, beta
+                if constexpr (sizeof(R) == 4) b.jv[k].w = __float_as_int(float(delta));
+                else b.vmu[k] = delta;
+                b.ma[k] = R4{R(G.V0 * dot(m[0], av)), R(G.V0 * dot(m[1], av)), R(G.V0 * dot(m[2], av)),
+                             R(dot(c1, av))};
+                b.mc[k] = typename R2t<R>::T{R(dot(c2, av)), R(dot(c3, av))};
+                continue;
+            }
             b.ma[k] = R4{R(vm * dot(m[0], av)), R(vm * dot(m[1], av)), R(vm * dot(m[2], av)), R(vl)};
             b.mb[k] = R4{R(dot(c1, av)), R(dot(c2, av)), R(dot(c3, av)), R(delta)};
         } else {
@@ -1421,14 +1466,55 @@ __global__ __launch_bounds__(kBlock) void k_build_visits(VisitBuild<R> b)
 }
 
 #if PBNG_KERNEL_SET == 0
-// flag = 1 while lambda >= mu in every tet (NaN counts as a violation)
-__global__ __launch_bounds__(kBlock) void k_flag_one(int* flag) { *flag = 1; }
+// Material flags (see launch_material_flags): one thread per tet, its
+// instance found by bisection over the tet offsets.  NaN parameters count
+// as violations.
+__global__ __launch_bounds__(kBlock) void k_flags_one(int* flag)
+{
+    if (threadIdx.x < 2) flag[threadIdx.x] = 1;
+}
 
-__global__ __launch_bounds__(kBlock) void k_lam_ge_mu(const double* mu, const double* lam, int n,
-                                                      int* flag)
+__global__ __launch_bounds__(kBlock) void k_material_flags(const double* mu, const double* lam,
+                                                           const int64_t* t_off, int n_inst, int n,
+                                                           int* flag)
 {
     const int e = blockIdx.x * kBlock + threadIdx.x;
-    if (e < n && !(lam[e] >= mu[e])) *flag = 0;
+    if (e >= n) return;
+    if (!(lam[e] >= mu[e])) flag[0] = 0;
+    int lo = 0, hi = n_inst;   // t_off[lo] <= e < t_off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (t_off[mid] <= e) lo = mid;
+        else hi = mid;
+    }
+    const int64_t f = t_off[lo];
+    if (!(mu[e] == mu[f]) || !(lam[e] == lam[f])) flag[1] = 0;
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlock) void k_inst_materials(const double* mu, const double* lam,
+                                                           const int64_t* t_off, int n_inst, R* imu,
+                                                           R* ilam)
+{
+    const int q = blockIdx.x * kBlock + threadIdx.x;
+    if (q >= n_inst) return;
+    const bool has = t_off[q + 1] > t_off[q];
+    imu[q] = has ? R(mu[t_off[q]]) : R(0);
+    ilam[q] = has ? R(lam[t_off[q]]) : R(0);
+}
+
+template <class R>
+hipError_t launch_material_flags(const double* mu, const double* lam, const int64_t* t_off, int n_inst,
+                                 int n_tets, int* flag, R* imu, R* ilam, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_flags_one, dim3(1), dim3(kBlock), 0, s, flag);
+    if (n_tets > 0)
+        hipLaunchKernelGGL(k_material_flags, dim3(nblk(n_tets)), dim3(kBlock), 0, s, mu, lam, t_off,
+                           n_inst, n_tets, flag);
+    if (n_inst > 0)
+        hipLaunchKernelGGL((k_inst_materials<R>), dim3(nblk(n_inst)), dim3(kBlock), 0, s, mu, lam,
+                           t_off, n_inst, imu, ilam);
+    return hipGetLastError();
 }
 #endif
 
@@ -1536,12 +1622,10 @@ template hipError_t launch_set_materials<float>(const double*, const double*, Te
                                                 const VisitBuild<float>&, hipStream_t);
 template hipError_t launch_set_materials<double>(const double*, const double*, TetGeo*, int,
                                                  const VisitBuild<double>&, hipStream_t);
-hipError_t launch_lam_ge_mu(const double* mu, const double* lam, int n, int* flag, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_flag_one, dim3(1), dim3(1), 0, s, flag);
-    if (n > 0) hipLaunchKernelGGL(k_lam_ge_mu, dim3(nblk(n)), dim3(kBlock), 0, s, mu, lam, n, flag);
-    return hipGetLastError();
-}
+template hipError_t launch_material_flags<float>(const double*, const double*, const int64_t*, int,
+                                                 int, int*, float*, float*, hipStream_t);
+template hipError_t launch_material_flags<double>(const double*, const double*, const int64_t*, int,
+                                                  int, int*, double*, double*, hipStream_t);
 template hipError_t launch_build_visits<float>(const VisitBuild<float>&, hipStream_t);
 template hipError_t launch_build_visits<double>(const VisitBuild<double>&, hipStream_t);
 PBNG_INST_SWEEP(float, float)

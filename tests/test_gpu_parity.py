@@ -411,3 +411,31 @@ def test_material_update_reenables_safeguard():
         x = dev_x(soft.initial_iterate(), real)
         ws.solve(x, max_sweeps=40, rel_tol=0.0, check_every=40, safeguard="backtrack")
         assert rel_err(host(x), xo) <= tol
+
+
+def test_record_form_follows_material_updates():
+    """A Neo-Hookean workspace with one (mu, lambda) per instance streams the
+    40-byte records; a material update to per-tet values switches it to the
+    48-byte form and a uniform update switches it back.  Every solve matches
+    the oracle with the same materials (FP64 and FP32)."""
+    sc = S.twist_box(6, "nh", 1e4, 0.3, 60.0, 1.2, 0.01, seed=9)
+    nt = sc.tets.shape[0]
+    rng = np.random.default_rng(9)
+    mu0, lam0 = O.lame(1e4, 0.3)
+    cases = [(np.full(nt, mu0 * 1.5), np.full(nt, lam0 * 0.8)),
+             (mu0 * np.exp(0.3 * rng.normal(size=nt)), lam0 * np.exp(0.3 * rng.normal(size=nt))),
+             (np.full(nt, mu0), np.full(nt, lam0))]
+    for real, tol in (("f64", 1e-10), ("f32", 1e-5)):
+        ws = workspace([sc], real)
+        for k, (mu, lam) in enumerate(cases):
+            announce("record form after material update %d %s" % (k, real))
+            ws.set_materials(torch.tensor(mu, dtype=torch.float64, device="cuda"),
+                             torch.tensor(lam, dtype=torch.float64, device="cuda"))
+            x = dev_x(sc.initial_iterate(), real)
+            ws.solve(x, max_sweeps=30, rel_tol=0.0, check_every=30, accel="chebyshev", rho=0.9,
+                     gamma=1.3, safeguard="backtrack")
+            op = O.make_problem(sc, mu=mu, lam=lam)
+            col, _ = O.color(op)
+            xo, _ = O.solve(op, col, sc.initial_iterate(), max_sweeps=30, accel="chebyshev", rho=0.9,
+                            gamma=1.3, safeguard="backtrack")
+            assert rel_err(host(x), xo) <= tol, (k, real)
