@@ -86,6 +86,8 @@ def lib():
         L.or_lumped_mass.argtypes = [C.c_int32, C.c_int32, _ip, _dp, C.c_double, _dp]
         L.or_color.argtypes = [C.POINTER(_Problem), _ip]
         L.or_color.restype = C.c_int32
+        L.or_recolor.argtypes = [C.POINTER(_Problem), C.c_int32, _ip, _ip]
+        L.or_recolor.restype = C.c_int32
         L.or_residual.argtypes = [C.POINTER(_Problem), _dp, _dp, _dp]
         L.or_residual.restype = C.c_double
         L.or_chebyshev_weights.argtypes = [C.c_double, C.c_int32, _dp]
@@ -287,6 +289,18 @@ def make_problem(sc, mu=None, lam=None) -> OracleProblem:
                          V0=V0[:nt], dN=dN[:nt],
                          dirichlet_idx=np.asarray(sc.dirichlet_idx, np.int32),
                          dirichlet_x=np.asarray(sc.dirichlet_x, np.float64), mass=mass)
+
+
+def recolor(op: OracleProblem, colors, nodes):
+    """Incremental recolouring after new weak constraints (the problem
+    already holds them): returns (colours, number of colours)."""
+    s = op.struct()
+    out = np.ascontiguousarray(np.array(colors, dtype=np.int32))
+    nodes = np.ascontiguousarray(nodes, np.int32)
+    nc = lib().or_recolor(C.byref(s), nodes.size, _i(nodes), _i(out))
+    if nc < 0:
+        raise ValueError("oracle recolouring failed (%d)" % nc)
+    return out, int(nc)
 
 
 def color(op: OracleProblem):

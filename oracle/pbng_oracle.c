@@ -585,6 +585,53 @@ int32_t or_color(const or_problem* p, int32_t* colors)
     return ncol;
 }
 
+/* Incremental recolouring (Sec. "Collision Coloring"): after new weak
+ * constraints were added to p, the free vertices incident to them -- given
+ * in `nodes`, processed in the order given -- each keep their colour from
+ * `colors` if no other vertex sharing a tet or a weak constraint with them
+ * uses it (the union of the colour sets S_c of their elements and
+ * constraints, their own entry left out), and otherwise take the least
+ * colour not in that union.  `colors` is updated in place, so later nodes
+ * see earlier changes.  Returns the number of colours, or < 0 on error. */
+int32_t or_recolor(const or_problem* p, int32_t n_nodes, const int32_t* nodes, int32_t* colors)
+{
+    or_adj A;
+    int rc = adj_build(p, &A);
+    if (rc) return rc;
+    int cap = 1;
+    for (int i = 0; i < p->nv; ++i)
+        if (colors[i] + 2 > cap) cap = colors[i] + 2;
+    cap += n_nodes;
+    char* used = (char*)malloc((size_t)cap);
+    for (int k = 0; k < n_nodes; ++k) {
+        int i = nodes[k];
+        if (p->is_dir[i]) continue;
+        memset(used, 0, (size_t)cap);
+        for (int m = A.tptr[i]; m < A.tptr[i + 1]; ++m) {
+            const int32_t* t = p->tets + 4 * A.tlist[m];
+            for (int j = 0; j < 4; ++j)
+                if (t[j] != i && colors[t[j]] >= 0) used[colors[t[j]]] = 1;
+        }
+        for (int m = A.cptr[i]; m < A.cptr[i + 1]; ++m) {
+            int c = A.clist[m];
+            for (int s = p->wc_ptr[c]; s < p->wc_ptr[c + 1]; ++s) {
+                int v = p->wc_vert[s];
+                if (v != i && colors[v] >= 0) used[colors[v]] = 1;
+            }
+        }
+        if (colors[i] >= 0 && !used[colors[i]]) continue;
+        int col = 0;
+        while (used[col]) ++col;
+        colors[i] = col;
+    }
+    int ncol = 0;
+    for (int i = 0; i < p->nv; ++i)
+        if (colors[i] + 1 > ncol) ncol = colors[i] + 1;
+    free(used);
+    adj_free(&A);
+    return ncol;
+}
+
 /* ------------------------------------------------------------------ */
 /* Energy, forces and the local step                                     */
 /* ------------------------------------------------------------------ */

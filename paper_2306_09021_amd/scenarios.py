@@ -212,6 +212,27 @@ def paper_box_frames(n: int, model: str = COROTATED, n_frames: int = 60, E: floa
     return sc, frames
 
 
+def two_blocks(n: int = 8, gap: float = 0.02, model: str = COROTATED, E: float = 1000.0,
+               nu: float = 0.3, density: float = 10.0, drive: float = 0.1) -> Scenario:
+    """The paper's two colliding blocks (Sec. "Collisions", "Two Blocks
+    Colliding"): two unit cubes of n^3 vertices side by side along x with a
+    gap, one instance with two connected parts, R0 = 10, E = 1000.  The outer
+    face of each block is clamped; the right block's is moved by `drive`
+    toward the left block.  Starts at rest."""
+    h = 1.0 / (n - 1)
+    X1, T1 = box_mesh(n, n, n, h)
+    X2 = X1 + np.array([1.0 + gap, 0.0, 0.0])
+    X = np.concatenate([X1, X2])
+    T = np.concatenate([T1, T1 + X1.shape[0]]).astype(np.int32)
+    left = _layer(X1, n, 0, 0.0)
+    right = _layer(X2, n, 0, 2.0 + gap) + X1.shape[0]
+    didx = np.concatenate([left, right]).astype(np.int32)
+    dx = np.concatenate([X[left], X[right] - np.array([drive, 0.0, 0.0])])
+    return Scenario(name=f"two_blocks_{n}", rest_pos=X, tets=T, model=model,
+                    E=np.asarray(E, np.float64), nu=np.asarray(nu, np.float64),
+                    dirichlet_idx=didx, dirichlet_x=dx, x0=X.copy(), density=density)
+
+
 def config_plain_f64() -> Scenario:
     """Plain PBNG in FP64: 10^3-vertex unit cube (3,645 tets), fixed-corotated,
     E = 1e4, nu = 0.3, bottom pinned, top stretched 1.3x and twisted 90 deg,
