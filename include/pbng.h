@@ -276,6 +276,43 @@ int32_t pbng_workspace_set_dirichlet(pbng_workspace* ws, const double* xd_dev, v
 int32_t pbng_workspace_set_inertia(pbng_workspace* ws, double dt, const double* x_n_dev,
                                    const double* x_prev_dev, void* hip_stream);
 
+/* Dynamic weak constraints (Sec. "Weak Constraints" with Sec. "Collisions"
+ * and "Collision Coloring"): replaces the workspace's contact set by n
+ * vertex-vertex contacts, each the weak constraint C = y_a - y_b with the
+ * anisotropic stiffness K = k_n n n^T (n normalised here; the tangential
+ * stiffness is 0), next to the problems' static weak constraints.
+ * pairs_dev: device int32 [n][2] of caller vertex indices over the whole
+ * workspace (both vertices of one instance, distinct); normals_dev: device
+ * double [n][3].  Then recolours as the paper prescribes: every free vertex
+ * incident to a contact, in ascending caller index, keeps its colour unless
+ * a vertex sharing a tet or a weak constraint with it has it, and otherwise
+ * takes the least colour none of them has.  Vertices keep their storage;
+ * a recoloured vertex runs in its new colour's phase.  Synchronises
+ * hip_stream.  n = 0 removes the contacts (colours stay valid).
+ * Errors: PBNG_EINVAL (bad pairs, normals or stiffness), PBNG_EHIP. */
+int32_t pbng_workspace_set_contacts(pbng_workspace* ws, int32_t n, const int32_t* pairs_dev,
+                                    const double* normals_dev, double k_n, void* hip_stream);
+
+/* Vertex-vertex proximity detection for pbng_workspace_set_contacts: all
+ * pairs (a, b), a < b in caller order, of surface vertices (vertices of a
+ * face that belongs to one tet) of different connected parts of one
+ * instance whose distance is at most radius and positive, not both
+ * Dirichlet, at the positions x_dev (device [n_verts][3] of the position
+ * type: float for PBNG_F32, double otherwise, caller order).  Outputs
+ * (device): pairs_dev int32 [max_pairs][2] sorted by (a, b), normals_dev
+ * double [max_pairs][3] = (x_b - x_a) / |x_b - x_a|; *n_found (host) the
+ * number of pairs.  Uses a uniform grid of cell size radius (sorted cell
+ * keys, 27-cell search); allocates its scratch on first use or growth.
+ * Synchronises hip_stream.  Errors: PBNG_EINVAL (bad radius or arrays, or
+ * more than max_pairs pairs: *n_found then holds the count), PBNG_EHIP. */
+int32_t pbng_detect_contacts(pbng_workspace* ws, const void* x_dev, double radius, int32_t max_pairs,
+                             int32_t* pairs_dev, double* normals_dev, int32_t* n_found,
+                             void* hip_stream);
+
+/* The current colouring: colors_out host int32 [n_verts] in the caller's
+ * order, -1 on Dirichlet vertices. */
+int32_t pbng_workspace_colors(const pbng_workspace* ws, int32_t* colors_out);
+
 /*
  * Solve (Eq. pbgn_update / pbgn_dx over the colours, with the optional
  * Chebyshev / SOR blend of Sec. "Acceleration Techniques").  x_inout

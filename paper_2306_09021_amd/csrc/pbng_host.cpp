@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -357,6 +358,37 @@ struct pbng_workspace {
     // (40-byte records; instance parameters in imu / ilam)
     int kmodel = PBNG_NEOHOOKEAN;
     Dev imu, ilam, t_off_dev;
+    // host copies for re-installing weak constraints (static ones from the
+    // problems, in internal vertex indices, plus dynamic contacts)
+    std::vector<int> h_wc_ptr, h_wc_vert, h_wc_inst;
+    std::vector<double> h_wc_w, h_wc_K;
+    struct Contact {
+        int a, b, inst;
+        double K[6];
+    };
+    std::vector<Contact> contacts;
+    std::vector<int> h_int_of, h_orig_of;
+    // current colouring (internal order, -1 on Dirichlet vertices), the
+    // host incidence it is checked against, and the launch plan of a sweep:
+    // per colour the home range (skipping vertices recoloured away) and
+    // the list of vertices recoloured into it
+    std::vector<int> h_color, h_rvptr, h_rv, h_vinst;
+    std::vector<int4> h_tet;
+    struct PhaseSpec {
+        int color, vb, ve;
+        bool list;
+    };
+    std::vector<PhaseSpec> phases;
+    bool moved_any = false;
+    int ncol_dyn = 0;
+    Dev pcol, xlist;
+    // proximity detection: candidate surface vertices (built on first use)
+    // and scratch sized for n_cand candidates and det_cap pairs
+    int n_cand = -1;
+    Dev cand_caller, cand_inst, cand_body, cand_dir;
+    int det_cap = -1;
+    Dev d_keys_in, d_keys_out, d_vals_in, d_vals_out, d_pairs, d_pkeys_in, d_pkeys_out, d_count, d_tmp;
+    size_t d_tmp_bytes = 0;
     // backward-Euler inertia (off until pbng_workspace_set_inertia)
     bool inertia = false;
     Dev mass64, inert, xhat, inert64, xhat64;
@@ -492,6 +524,173 @@ hipError_t build_visits(pbng_workspace* ws, const double* mu, const double* lam,
     if (mu) return launch_set_materials<float>(mu, lam, ws->geo.as<TetGeo>(), int(ws->nt),
                                                visit_build<float>(ws), s);
     return launch_build_visits<float>(visit_build<float>(ws), s);
+}
+
+// Launch plan of a sweep from the current colouring: colour c runs its home
+// range [col_ptr[c], col_ptr[c+1]) (vertices recoloured away are skipped on
+// the device) and then, if any, the list of vertices recoloured into c.
+void rebuild_phases(pbng_workspace* ws)
+{
+    const int nf = int(ws->nfree);
+    int ncol = ws->ncol;
+    std::vector<std::vector<int>> moved_in;
+    ws->moved_any = false;
+    for (int c = 0; c < ws->ncol; ++c)
+        for (int k = ws->col_ptr[c]; k < ws->col_ptr[c + 1]; ++k)
+            if (ws->h_color[k] != c) {
+                const int cn = ws->h_color[k];
+                if (cn + 1 > int(moved_in.size())) moved_in.resize(cn + 1);
+                moved_in[cn].push_back(k);
+                ncol = std::max(ncol, cn + 1);
+                ws->moved_any = true;
+            }
+    ws->ncol_dyn = ncol;
+    ws->phases.clear();
+    std::vector<int> list;
+    for (int c = 0; c < ncol; ++c) {
+        if (c < ws->ncol && ws->col_ptr[c + 1] > ws->col_ptr[c])
+            ws->phases.push_back({c, ws->col_ptr[c], ws->col_ptr[c + 1], false});
+        if (c < int(moved_in.size()) && !moved_in[c].empty()) {
+            const int b = int(list.size());
+            list.insert(list.end(), moved_in[c].begin(), moved_in[c].end());
+            ws->phases.push_back({c, b, int(list.size()), true});
+        }
+    }
+    if (ws->moved_any) {
+        std::vector<int> pc(ws->h_color.begin(), ws->h_color.begin() + nf);
+        ws->pcol.upload(pc);
+        ws->xlist.upload(list);
+    }
+}
+
+// Incremental recolouring after new weak constraints (Sec. "Collision
+// Coloring"): every free vertex incident to a dynamic constraint, in
+// ascending caller index, keeps its colour unless another vertex sharing a
+// tet or a weak constraint with it has that colour; then it takes the least
+// colour none of them has.  Colours of vertices processed earlier count.
+void recolor_contacts(pbng_workspace* ws)
+{
+    const int nv = int(ws->nv), nf = int(ws->nfree);
+    // weak-constraint incidence per internal vertex (static and dynamic)
+    std::vector<std::vector<int>> nb(nv);
+    auto link = [&](const int* m, int cnt) {
+        for (int i = 0; i < cnt; ++i)
+            for (int j = 0; j < cnt; ++j)
+                if (i != j) nb[m[i]].push_back(m[j]);
+    };
+    for (size_t c = 0; c + 1 < ws->h_wc_ptr.size(); ++c)
+        link(ws->h_wc_vert.data() + ws->h_wc_ptr[c], ws->h_wc_ptr[c + 1] - ws->h_wc_ptr[c]);
+    std::vector<int> extra;
+    for (const auto& ct : ws->contacts) {
+        const int m[2] = {ct.a, ct.b};
+        link(m, 2);
+        for (int v : m)
+            if (v < nf) extra.push_back(v);
+    }
+    std::sort(extra.begin(), extra.end(), [&](int x, int y) { return ws->h_orig_of[x] < ws->h_orig_of[y]; });
+    extra.erase(std::unique(extra.begin(), extra.end()), extra.end());
+    std::vector<char> used;
+    for (int v : extra) {
+        used.assign(used.size(), 0);
+        auto mark = [&](int u) {
+            const int c = ws->h_color[u];
+            if (c < 0) return;
+            if (c >= int(used.size())) used.resize(c + 1, 0);
+            used[c] = 1;
+        };
+        for (int k = ws->h_rvptr[v]; k < ws->h_rvptr[v + 1]; ++k) {
+            const int4 t = ws->h_tet[ws->h_rv[k] >> 2];
+            for (int u : {t.x, t.y, t.z, t.w})
+                if (u != v) mark(u);
+        }
+        for (int u : nb[v])
+            if (u != v) mark(u);
+        const int cur = ws->h_color[v];
+        if (cur >= 0 && (cur >= int(used.size()) || !used[cur])) continue;
+        int c = 0;
+        while (c < int(used.size()) && used[c]) ++c;
+        ws->h_color[v] = c;
+    }
+}
+
+// Weak constraints of the workspace: the static ones from the problems and
+// the dynamic contacts (two members, weights +1 / -1), instance by
+// instance: the global constraint list, the per-vertex CSR (constraint,
+// weight), and the instance-major energy slots (tets, vertices,
+// constraints of each instance) with their segmented-sum plan.
+void install_constraints(pbng_workspace* ws)
+{
+    const int n = ws->n_inst;
+    const int64_t nv = ws->nv, nt = ws->nt;
+    const int n_static = int(ws->h_wc_inst.size());
+    std::vector<std::vector<int>> dyn_of(n);
+    for (int k = 0; k < int(ws->contacts.size()); ++k) dyn_of[ws->contacts[k].inst].push_back(k);
+    std::vector<std::vector<int>> stat_of(n);
+    for (int c = 0; c < n_static; ++c) stat_of[ws->h_wc_inst[c]].push_back(c);
+    std::vector<int> wc_ptr(1, 0), wc_vert, wvptr(nv + 1, 0), wv_c, wc_eidx;
+    std::vector<double> wc_w, wc_K, wv_s;
+    std::vector<int> tet_eidx(nt), vert_eidx(nv);
+    std::vector<int64_t> seg_e(n + 1);
+    std::vector<std::vector<std::pair<int, double>>> per(nv);
+    int64_t eo = 0;
+    for (int q = 0; q < n; ++q) {
+        const int64_t vo = ws->v_off[q], to = ws->t_off[q];
+        const int64_t ntq = ws->t_off[q + 1] - to, nvq = ws->v_off[q + 1] - vo;
+        seg_e[q] = eo;
+        for (int64_t e = 0; e < ntq; ++e) tet_eidx[to + e] = int(eo + e);
+        for (int64_t i = 0; i < nvq; ++i) vert_eidx[vo + i] = int(eo + ntq + i);
+        int64_t slot = eo + ntq + nvq;
+        auto add = [&](const int* verts, const double* w, int m, const double* K) {
+            const int gc = int(wc_ptr.size()) - 1;
+            for (int j = 0; j < m; ++j) {
+                wc_vert.push_back(verts[j]);
+                wc_w.push_back(w[j]);
+                per[verts[j]].push_back({gc, w[j]});
+            }
+            wc_ptr.push_back(int(wc_vert.size()));
+            for (int j = 0; j < 6; ++j) wc_K.push_back(K[j]);
+            wc_eidx.push_back(int(slot++));
+        };
+        for (int c : stat_of[q])
+            add(ws->h_wc_vert.data() + ws->h_wc_ptr[c], ws->h_wc_w.data() + ws->h_wc_ptr[c],
+                ws->h_wc_ptr[c + 1] - ws->h_wc_ptr[c], ws->h_wc_K.data() + 6 * c);
+        for (int k : dyn_of[q]) {
+            const auto& ct = ws->contacts[k];
+            const int verts[2] = {ct.a, ct.b};
+            const double w[2] = {1.0, -1.0};
+            add(verts, w, 2, ct.K);
+        }
+        eo = slot;
+    }
+    seg_e[n] = eo;
+    for (int64_t k = 0; k < nv; ++k) {
+        for (auto& pr : per[k]) {
+            wv_c.push_back(pr.first);
+            wv_s.push_back(pr.second);
+        }
+        wvptr[k + 1] = int(wv_c.size());
+    }
+    ws->n_wc = int(wc_ptr.size()) - 1;
+    ws->any_wc = ws->n_wc > 0 || ws->n_planes > 0;
+    auto upR = [&](Dev& d, const std::vector<double>& v) {
+        if (ws->math64()) upload_real<double>(d, v);
+        else upload_real<float>(d, v);
+    };
+    ws->wvptr.upload(wvptr);
+    ws->wv_c.upload(wv_c);
+    upR(ws->wv_s, wv_s);
+    ws->wc_ptr.upload(wc_ptr);
+    ws->wc_vert.upload(wc_vert);
+    upR(ws->wc_w, wc_w);
+    upR(ws->wc_K, wc_K);
+    ws->wv_s64.upload(wv_s);
+    ws->wc_w64.upload(wc_w);
+    ws->wc_K64.upload(wc_K);
+    ws->wc_eidx.upload(wc_eidx);
+    ws->tet_eidx.upload(tet_eidx);
+    ws->vert_eidx.upload(vert_eidx);
+    ws->ebuf.alloc(std::max<int64_t>(1, eo) * sizeof(double));
+    ws->plan_e = make_plan(seg_e, ws->seg_e_cb, ws->seg_e_ce, ws->seg_e_q, ws->seg_e_part);
 }
 
 void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const int32_t* colors_in)
@@ -702,33 +901,28 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
             for (int a = 0; a < 3; ++a) fext_free[4 * k + a] = fext[3 * gv + a];
     }
 
-    // weak constraints: global list with internal members, per-vertex CSR
-    std::vector<int> wc_ptr(ws->n_wc + 1, 0), wc_vert, wvptr(nv + 1, 0), wv_c;
-    std::vector<double> wc_w, wc_K, wv_s;
-    {
-        std::vector<std::vector<std::pair<int, double>>> per(nv);
-        for (int q = 0; q < n; ++q) {
-            const pbng_problem* p = ps + q;
-            for (int c = 0; c < p->n_wc; ++c) {
-                const int gc = int(c_off[q] + c);
-                for (int k = p->wc_ptr[c]; k < p->wc_ptr[c + 1]; ++k) {
-                    const int iv = int_of[ws->v_off[q] + p->wc_vert[k]];
-                    wc_vert.push_back(iv);
-                    wc_w.push_back(p->wc_w[k]);
-                    per[iv].push_back({gc, p->wc_w[k]});
-                }
-                wc_ptr[gc + 1] = int(wc_vert.size());
-                for (int j = 0; j < 6; ++j) wc_K.push_back(p->wc_K[6 * c + j]);
+    // static weak constraints with internal members (installed, together
+    // with any contacts, by install_constraints)
+    ws->h_wc_ptr.assign(1, 0);
+    ws->h_wc_vert.clear();
+    ws->h_wc_w.clear();
+    ws->h_wc_K.clear();
+    ws->h_wc_inst.clear();
+    for (int q = 0; q < n; ++q) {
+        const pbng_problem* p = ps + q;
+        for (int c = 0; c < p->n_wc; ++c) {
+            for (int k = p->wc_ptr[c]; k < p->wc_ptr[c + 1]; ++k) {
+                ws->h_wc_vert.push_back(int_of[ws->v_off[q] + p->wc_vert[k]]);
+                ws->h_wc_w.push_back(p->wc_w[k]);
             }
-        }
-        for (int64_t k = 0; k < nv; ++k) {
-            for (auto& pr : per[k]) {
-                wv_c.push_back(pr.first);
-                wv_s.push_back(pr.second);
-            }
-            wvptr[k + 1] = int(wv_c.size());
+            ws->h_wc_ptr.push_back(int(ws->h_wc_vert.size()));
+            for (int j = 0; j < 6; ++j) ws->h_wc_K.push_back(p->wc_K[6 * c + j]);
+            ws->h_wc_inst.push_back(q);
         }
     }
+    ws->h_int_of = int_of;
+    ws->h_orig_of = orig_of;
+    ws->h_vinst = vinst_all;
     std::vector<int> plane_ptr(n + 1, 0);
     std::vector<double> planes;
     for (int q = 0; q < n; ++q) {
@@ -739,14 +933,12 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     // FP64 tet data and energy slots
     std::vector<int4> tet(nt);
     std::vector<TetGeo> geo(nt);
-    std::vector<int> tet_eidx(nt), vert_eidx(nv), wc_eidx(ws->n_wc), vorder(nv);
-    std::vector<int64_t> seg_r(n + 1), seg_e(n + 1);
+    std::vector<int> vorder(nv);
+    std::vector<int64_t> seg_r(n + 1);
     for (int q = 0; q < n; ++q) {
         const pbng_problem* p = ps + q;
         const int64_t vo = ws->v_off[q], to = ws->t_off[q];
-        const int64_t eo = to + vo + c_off[q];
         seg_r[q] = vo;
-        seg_e[q] = eo;
         for (int64_t e = 0; e < p->n_tets; ++e) {
             const int32_t* t = p->tets + 4 * e;
             tet[to + e] = int4{int_of[vo + t[0]], int_of[vo + t[1]], int_of[vo + t[2]], int_of[vo + t[3]]};
@@ -755,16 +947,10 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
             G.V0 = V0[to + e];
             G.mu = mu[to + e];
             G.lam = lam[to + e];
-            tet_eidx[to + e] = int(eo + e);
         }
-        for (int i = 0; i < p->n_verts; ++i) {
-            vorder[vo + i] = int_of[vo + i];
-            vert_eidx[vo + i] = int(eo + p->n_tets + i);
-        }
-        for (int c = 0; c < p->n_wc; ++c) wc_eidx[c_off[q] + c] = int(eo + p->n_tets + p->n_verts + c);
+        for (int i = 0; i < p->n_verts; ++i) vorder[vo + i] = int_of[vo + i];
     }
     seg_r[n] = nv;
-    seg_e[n] = nt + nv + ws->n_wc;
 
     // Dirichlet targets
     std::vector<int> dir_internal(ws->nd), dir_pos(nv - nfree);
@@ -804,30 +990,19 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     ws->vinst.upload(vinst_free);
     ws->active.alloc(n * sizeof(int));
     ws->rejected.alloc(n * sizeof(int));
-    ws->wvptr.upload(wvptr);
-    ws->wv_c.upload(wv_c);
-    upR(ws->wv_s, wv_s);
-    ws->wc_ptr.upload(wc_ptr);
-    ws->wc_vert.upload(wc_vert);
-    upR(ws->wc_w, wc_w);
-    upR(ws->wc_K, wc_K);
     ws->plane_ptr.upload(plane_ptr);
     upR(ws->planes, planes);
     ws->tet.upload(tet);
+    ws->h_tet = tet;
+    ws->h_rvptr = rvptr;
+    ws->h_rv = rv;
     ws->geo.upload(geo);
     ws->vp.alloc(std::max<int64_t>(1, nt) * 12 * sizeof(double));
-    ws->ebuf.alloc(std::max<int64_t>(1, nt + nv + ws->n_wc) * sizeof(double));
-    ws->tet_eidx.upload(tet_eidx);
     ws->vorder.upload(vorder);
-    ws->vert_eidx.upload(vert_eidx);
     ws->rvptr.upload(rvptr);
     ws->rv.upload(rv);
     ws->fext64.upload(fext_int);
     ws->vinst_all.upload(vinst_all);
-    ws->wv_s64.upload(wv_s);
-    ws->wc_w64.upload(wc_w);
-    ws->wc_K64.upload(wc_K);
-    ws->wc_eidx.upload(wc_eidx);
     ws->planes64.upload(planes);
     ws->orig_of.upload(orig_of);
     ws->rsq.alloc(std::max<int64_t>(1, nv) * sizeof(double));
@@ -835,7 +1010,7 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     ws->dir_internal.upload(dir_internal);
     ws->dir_pos.upload(dir_pos);
     ws->plan_r = make_plan(seg_r, ws->seg_r_cb, ws->seg_r_ce, ws->seg_r_q, ws->seg_r_part);
-    ws->plan_e = make_plan(seg_e, ws->seg_e_cb, ws->seg_e_ce, ws->seg_e_q, ws->seg_e_part);
+    install_constraints(ws);
     ws->out_r.alloc(n * sizeof(double));
     ws->out_e.alloc(n * sizeof(double));
     ws->W.alloc(nv * ws->r4());
@@ -845,6 +1020,10 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     hipchk(hipDeviceSynchronize(), "upload");
     hipchk(build_visits(ws, nullptr, nullptr, nullptr), "visit records");
     hipchk(hipDeviceSynchronize(), "visit records");
+    ws->h_color.assign(nv, -1);
+    for (int c = 0; c < ws->ncol; ++c)
+        for (int k = ws->col_ptr[c]; k < ws->col_ptr[c + 1]; ++k) ws->h_color[k] = c;
+    rebuild_phases(ws);
 }
 
 template <class R, class PR>
@@ -880,6 +1059,9 @@ SweepArgs<R, PR> sweep_args(pbng_workspace* ws, double omega, double gamma, int 
     a.rejected = ws->rejected.as<int>();
     a.inert = ws->inertia ? ws->inert.as<R>() : nullptr;
     a.xhat = ws->inertia ? ws->xhat.as<P4>() : nullptr;
+    a.vlist = nullptr;
+    a.pcol = nullptr;
+    a.pcolor = 0;
     a.omega = PR(omega);
     a.gamma = PR(gamma);
     a.max_halvings = max_halvings;
@@ -988,12 +1170,15 @@ template <class R, class PR>
 void launch_sweep(pbng_workspace* ws, const pbng_solve_opts* o, double omega, double gamma, hipStream_t s)
 {
     const bool accel = o->accel != PBNG_ACCEL_NONE;
-    const SweepArgs<R, PR> a = sweep_args<R, PR>(ws, omega, gamma, o->max_halvings);
-    for (int c = 0; c < ws->ncol; ++c)
-        hipchk(launch_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, c), accel,
-                               safe_effective(ws, o), ws->general(), ws->col_ptr[c],
-                               ws->col_ptr[c + 1], s),
+    SweepArgs<R, PR> a = sweep_args<R, PR>(ws, omega, gamma, o->max_halvings);
+    for (const auto& ph : ws->phases) {
+        a.vlist = ph.list ? ws->xlist.as<int>() : nullptr;
+        a.pcol = (!ph.list && ws->moved_any) ? ws->pcol.as<int>() : nullptr;
+        a.pcolor = ph.color;
+        hipchk(launch_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, ph.color), accel,
+                                   safe_effective(ws, o), ws->general(), ph.vb, ph.ve, s),
                "sweep launch");
+    }
     if (accel) std::swap(ws->W.p, ws->N.p);
 }
 
@@ -1192,6 +1377,9 @@ AdjArgs<R, PR> adj_args(pbng_workspace* ws, double omega, double gamma)
     a.plane_ptr = ws->plane_ptr.as<int>();
     a.planes = ws->planes.as<R>();
     a.inert = ws->inertia ? ws->inert.as<R>() : nullptr;
+    a.vlist = nullptr;
+    a.pcol = nullptr;
+    a.pcolor = 0;
     a.omega = PR(omega);
     a.gamma = PR(gamma);
     return a;
@@ -1255,11 +1443,15 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
         double omega = 1.0;
         if (accel) omega = chebyshev_next(sw, o->rho, omega_prev);
         omega_prev = omega;
-        const AdjArgs<R, PR> a = adj_args<R, PR>(ws, omega, accel ? o->gamma : 1.0);
-        for (int c = 0; c < ws->ncol; ++c)
-            hipchk(launch_adjoint_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, c), accel, ws->any_wc || ws->inertia, ws->col_ptr[c],
-                                           ws->col_ptr[c + 1], s),
+        AdjArgs<R, PR> a = adj_args<R, PR>(ws, omega, accel ? o->gamma : 1.0);
+        for (const auto& ph : ws->phases) {
+            a.vlist = ph.list ? ws->xlist.as<int>() : nullptr;
+            a.pcol = (!ph.list && ws->moved_any) ? ws->pcol.as<int>() : nullptr;
+            a.pcolor = ph.color;
+            hipchk(launch_adjoint_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, ph.color), accel,
+                                               ws->any_wc || ws->inertia, ph.vb, ph.ve, s),
                    "adjoint launch");
+        }
         if (accel) std::swap(ws->L.p, ws->LN.p);
         for (int q = 0; q < n; ++q) sweeps[q] += act[q];
         if ((sw + 1) % o->check_every == 0 || sw + 1 == o->max_sweeps) {
@@ -1332,6 +1524,23 @@ struct Events {
 
 // Measured choice of the lanes per vertex of every colour (the tile of the
 // colour-phase kernel) and of the sweeps per captured graph.
+// The launches of one colour (its home range and the list of vertices
+// recoloured into it), with the blend weights 1.
+template <class R, class PR>
+void phase_t(pbng_workspace* ws, const pbng_solve_opts* o, int color, hipStream_t s)
+{
+    SweepArgs<R, PR> a = sweep_args<R, PR>(ws, 1.0, 1.0, o->max_halvings);
+    for (const auto& ph : ws->phases) {
+        if (ph.color != color) continue;
+        a.vlist = ph.list ? ws->xlist.as<int>() : nullptr;
+        a.pcol = (!ph.list && ws->moved_any) ? ws->pcol.as<int>() : nullptr;
+        a.pcolor = ph.color;
+        hipchk(launch_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, color), o->accel != PBNG_ACCEL_NONE,
+                                   safe_effective(ws, o), ws->general(), ph.vb, ph.ve, s),
+               "phase");
+    }
+}
+
 template <class R, class PR>
 void autotune_t(pbng_workspace* ws, const void* x, const pbng_solve_opts* o, pbng_solve_opts* tuned,
                 hipStream_t s)
@@ -1530,7 +1739,7 @@ int32_t pbng_workspace_info(const pbng_workspace* ws, int64_t* n_verts, int64_t*
         if (n_verts) *n_verts = ws->nv;
         if (n_tets) *n_tets = ws->nt;
         if (n_free) *n_free = ws->nfree;
-        if (n_colors) *n_colors = ws->ncol;
+        if (n_colors) *n_colors = ws->ncol_dyn;
         if (n_visits) *n_visits = ws->nvis;
         if (n_instances) *n_instances = ws->n_inst;
         return PBNG_OK;
@@ -1634,6 +1843,164 @@ int32_t pbng_workspace_set_inertia(pbng_workspace* ws, double dt, const double* 
         // the kernel variant (and its arguments) changes with inertia on or off
         if (was != ws->inertia) ws->drop_graph();
         ws->ring_valid = false;
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_workspace_set_contacts(pbng_workspace* ws, int32_t n, const int32_t* pairs_dev,
+                                    const double* normals_dev, double k_n, void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (n < 0) fail(PBNG_EINVAL, "negative contact count");
+        if (n > 0 && (!pairs_dev || !normals_dev)) fail(PBNG_EINVAL, "null contact arrays");
+        if (n > 0 && !(k_n > 0.0 && std::isfinite(k_n))) fail(PBNG_EINVAL, "contact stiffness must be > 0");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        std::vector<int32_t> pr(2 * size_t(n));
+        std::vector<double> nr(3 * size_t(n));
+        if (n > 0) {
+            hipchk(hipMemcpyAsync(pr.data(), pairs_dev, pr.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s), "d2h");
+            hipchk(hipMemcpyAsync(nr.data(), normals_dev, nr.size() * sizeof(double), hipMemcpyDeviceToHost, s), "d2h");
+            hipchk(hipStreamSynchronize(s), "sync");
+        }
+        std::vector<pbng_workspace::Contact> cts(n);
+        for (int k = 0; k < n; ++k) {
+            const int ga = pr[2 * k], gb = pr[2 * k + 1];
+            if (ga < 0 || gb < 0 || ga >= ws->nv || gb >= ws->nv || ga == gb)
+                fail(PBNG_EINVAL, "contact %d: bad vertex pair", k);
+            const int a = ws->h_int_of[ga], b = ws->h_int_of[gb];
+            if (ws->h_vinst[a] != ws->h_vinst[b]) fail(PBNG_EINVAL, "contact %d joins two instances", k);
+            const double* v = nr.data() + 3 * k;
+            const double len = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            if (!(len > 0.0) || !std::isfinite(len)) fail(PBNG_EINVAL, "contact %d: bad normal", k);
+            const double nx = v[0] / len, ny = v[1] / len, nz = v[2] / len;
+            cts[k].a = a;
+            cts[k].b = b;
+            cts[k].inst = ws->h_vinst[a];
+            const double K[6] = {k_n * nx * nx, k_n * nx * ny, k_n * nx * nz, k_n * ny * ny, k_n * ny * nz, k_n * nz * nz};
+            for (int j = 0; j < 6; ++j) cts[k].K[j] = K[j];
+        }
+        hipchk(hipStreamSynchronize(s), "sync");
+        ws->contacts = std::move(cts);
+        install_constraints(ws);
+        recolor_contacts(ws);
+        rebuild_phases(ws);
+        ws->drop_graph();
+        ws->ring_valid = false;
+        hipchk(hipDeviceSynchronize(), "contacts");
+        return PBNG_OK;
+    });
+}
+
+// Candidates of the proximity detection: vertices of faces that belong to a
+// single tet, with their caller index, instance, connected part (union-find
+// over the tets) and Dirichlet flag.
+void build_candidates(pbng_workspace* ws)
+{
+    const int nv = int(ws->nv);
+    std::vector<int> parent(nv);
+    std::iota(parent.begin(), parent.end(), 0);
+    auto find = [&](int i) {
+        while (parent[i] != i) {
+            parent[i] = parent[parent[i]];
+            i = parent[i];
+        }
+        return i;
+    };
+    std::vector<std::array<int, 3>> faces;
+    faces.reserve(4 * ws->h_tet.size());
+    for (const int4& t : ws->h_tet) {
+        const int v[4] = {t.x, t.y, t.z, t.w};
+        for (int j = 1; j < 4; ++j) {
+            const int a = find(v[0]), b = find(v[j]);
+            if (a != b) parent[b] = a;
+        }
+        for (int skip = 0; skip < 4; ++skip) {
+            std::array<int, 3> f;
+            int m = 0;
+            for (int j = 0; j < 4; ++j)
+                if (j != skip) f[m++] = v[j];
+            std::sort(f.begin(), f.end());
+            faces.push_back(f);
+        }
+    }
+    std::sort(faces.begin(), faces.end());
+    std::vector<char> surf(nv, 0);
+    for (size_t i = 0; i < faces.size();) {
+        size_t j = i + 1;
+        while (j < faces.size() && faces[j] == faces[i]) ++j;
+        if (j - i == 1)
+            for (int v : faces[i]) surf[v] = 1;
+        i = j;
+    }
+    std::vector<int> caller, inst, body, dir;
+    for (int v = 0; v < nv; ++v)
+        if (surf[v]) {
+            caller.push_back(ws->h_orig_of[v]);
+            inst.push_back(ws->h_vinst[v]);
+            body.push_back(find(v));
+            dir.push_back(v >= ws->nfree ? 1 : 0);
+        }
+    ws->n_cand = int(caller.size());
+    ws->cand_caller.upload(caller);
+    ws->cand_inst.upload(inst);
+    ws->cand_body.upload(body);
+    ws->cand_dir.upload(dir);
+}
+
+int32_t pbng_detect_contacts(pbng_workspace* ws, const void* x_dev, double radius, int32_t max_pairs,
+                             int32_t* pairs_dev, double* normals_dev, int32_t* n_found, void* hip_stream)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (!x_dev || !n_found) fail(PBNG_EINVAL, "null argument");
+        if (!(radius > 0.0) || !std::isfinite(radius)) fail(PBNG_EINVAL, "radius must be > 0");
+        if (max_pairs < 0 || (max_pairs > 0 && (!pairs_dev || !normals_dev)))
+            fail(PBNG_EINVAL, "bad output arrays");
+        if (ws->n_inst >= (1 << 18)) fail(PBNG_EUNSUPPORTED, "too many instances for detection");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        if (ws->n_cand < 0) build_candidates(ws);
+        const int cap = std::max(max_pairs, 1);
+        if (ws->det_cap < cap) {
+            const int nc = std::max(ws->n_cand, 1);
+            ws->d_keys_in.alloc(size_t(nc) * 8);
+            ws->d_keys_out.alloc(size_t(nc) * 8);
+            ws->d_vals_in.alloc(size_t(nc) * 4);
+            ws->d_vals_out.alloc(size_t(nc) * 4);
+            ws->d_pairs.alloc(size_t(cap) * 8);
+            ws->d_pkeys_in.alloc(size_t(cap) * 8);
+            ws->d_pkeys_out.alloc(size_t(cap) * 8);
+            ws->d_count.alloc(sizeof(int));
+            ws->d_tmp_bytes = detect_tmp_bytes(nc, cap);
+            ws->d_tmp.alloc(ws->d_tmp_bytes);
+            ws->det_cap = cap;
+        }
+        ContactCand c{ws->n_cand, ws->cand_caller.as<int>(), ws->cand_inst.as<int>(), ws->cand_body.as<int>(),
+                      ws->cand_dir.as<int>()};
+        DetectScratch w{ws->d_keys_in.as<unsigned long long>(), ws->d_keys_out.as<unsigned long long>(),
+                        ws->d_vals_in.as<int>(), ws->d_vals_out.as<int>(), ws->d_pairs.as<int2>(),
+                        ws->d_pkeys_in.as<unsigned long long>(), ws->d_pkeys_out.as<unsigned long long>(),
+                        ws->d_count.as<int>(), ws->d_tmp.p, ws->d_tmp_bytes};
+        int nf = 0;
+        hipError_t e = ws->pos64()
+                           ? launch_detect<double>(static_cast<const double*>(x_dev), c, radius, max_pairs, w,
+                                                   pairs_dev, normals_dev, &nf, s)
+                           : launch_detect<float>(static_cast<const float*>(x_dev), c, radius, max_pairs, w,
+                                                  pairs_dev, normals_dev, &nf, s);
+        hipchk(e, "detect contacts");
+        hipchk(hipStreamSynchronize(s), "detect contacts");
+        *n_found = nf;
+        if (nf > max_pairs) fail(PBNG_EINVAL, "found %d contacts, more than max_pairs = %d", nf, max_pairs);
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng_workspace_colors(const pbng_workspace* ws, int32_t* colors_out)
+{
+    return guard([&] {
+        check_ws(ws);
+        if (!colors_out) fail(PBNG_EINVAL, "null colours array");
+        for (int64_t k = 0; k < ws->nv; ++k) colors_out[ws->h_orig_of[k]] = ws->h_color[k];
         return PBNG_OK;
     });
 }
@@ -1776,26 +2143,13 @@ int32_t pbng_phase(pbng_workspace* ws, int32_t color, const pbng_solve_opts* o, 
         check_ws(ws);
         check_solve_opts(o);
         if (!ws->ring_valid) fail(PBNG_EINVAL, "call pbng_load first");
-        if (color < 0 || color >= ws->ncol) fail(PBNG_EINVAL, "colour out of range");
+        if (color < 0 || color >= ws->ncol_dyn) fail(PBNG_EINVAL, "colour out of range");
         hipStream_t s = static_cast<hipStream_t>(hip_stream);
-        const int lanes = pick_lanes(ws, o->lanes, color);
-        const bool safe = safe_effective(ws, o);
-        const bool accel = o->accel != PBNG_ACCEL_NONE;
         // with acceleration the phase blends with omega = 1 and gamma = 1 and
         // does not advance the ring (measurement of the fused kernel only)
-        const int c0 = ws->col_ptr[color], c1 = ws->col_ptr[color + 1];
-        if (ws->real == PBNG_F64)
-            hipchk(launch_phase<double, double>(sweep_args<double, double>(ws, 1.0, 1.0, o->max_halvings),
-                                                ws->kmodel, lanes, accel, safe, ws->general(), c0, c1, s),
-                   "phase");
-        else if (ws->real == PBNG_MIXED)
-            hipchk(launch_phase<float, double>(sweep_args<float, double>(ws, 1.0, 1.0, o->max_halvings),
-                                               ws->kmodel, lanes, accel, safe, ws->general(), c0, c1, s),
-                   "phase");
-        else
-            hipchk(launch_phase<float, float>(sweep_args<float, float>(ws, 1.0, 1.0, o->max_halvings),
-                                              ws->kmodel, lanes, accel, safe, ws->general(), c0, c1, s),
-                   "phase");
+        if (ws->real == PBNG_F64) phase_t<double, double>(ws, o, color, s);
+        else if (ws->real == PBNG_MIXED) phase_t<float, double>(ws, o, color, s);
+        else phase_t<float, float>(ws, o, color, s);
         return PBNG_OK;
     });
 }
@@ -1823,10 +2177,12 @@ int32_t pbng_phase_bytes(const pbng_workspace* ws, int32_t color, int64_t* bytes
 {
     return guard([&] {
         check_ws(ws);
-        if (color < 0 || color >= ws->ncol) fail(PBNG_EINVAL, "colour out of range");
-        if (bytes) *bytes = ws->phase_bytes[color];
-        if (vertices) *vertices = ws->phase_verts[color];
-        if (visits) *visits = ws->phase_visits[color];
+        if (color < 0 || color >= ws->ncol_dyn) fail(PBNG_EINVAL, "colour out of range");
+        // the figures of the colour's home range (as packed at creation)
+        const bool home = color < ws->ncol;
+        if (bytes) *bytes = home ? ws->phase_bytes[color] : 0;
+        if (vertices) *vertices = home ? ws->phase_verts[color] : 0;
+        if (visits) *visits = home ? ws->phase_visits[color] : 0;
         return PBNG_OK;
     });
 }

@@ -90,6 +90,12 @@ struct SweepArgs {
     int* rejected;         // [n_inst]
     const R* inert;        // [n_free] m_ii / dt^2 (backward Euler), or null
     const P4* xhat;        // [n_free] 2 x^n - x^{n-1}
+    // recoloured vertices (general kernel only): a list launch takes its
+    // vertices from vlist[vbeg, vend); a range launch skips vertices whose
+    // current colour pcol[v] is not pcolor (pcol null: none moved)
+    const int* vlist;
+    const int* pcol;
+    int pcolor;
     PR omega, gamma;
     int max_halvings;
 };
@@ -215,6 +221,35 @@ hipError_t launch_set_inertia(const double* x_n, const double* x_prev, const int
                               typename R4t<PR>::T* xhat, double* inert64, double* xhat64,
                               hipStream_t s);
 
+// Proximity detection (pbng_contacts.hip): the candidate surface vertices
+// with their caller index, instance, connected part and Dirichlet flag.
+struct ContactCand {
+    int n;
+    const int* caller;
+    const int* inst;
+    const int* body;
+    const int* dir;
+};
+struct DetectScratch {
+    unsigned long long* keys_in;
+    unsigned long long* keys_out;
+    int* vals_in;
+    int* vals_out;
+    int2* pairs;
+    unsigned long long* pkeys_in;
+    unsigned long long* pkeys_out;
+    int* count;
+    void* tmp;
+    size_t tmp_bytes;
+};
+// Pairs within r, sorted, with normals, into pairs_out [max_pairs][2] and
+// normals_out [max_pairs][3]; *n_found = number of pairs (outputs written
+// only when it does not exceed max_pairs).  Synchronises s.
+template <class P>
+hipError_t launch_detect(const P* x, const ContactCand& c, double r, int max_pairs, DetectScratch& w,
+                         int* pairs_out, double* normals_out, int* n_found, hipStream_t s);
+size_t detect_tmp_bytes(int n, int max_pairs);
+
 // Adjoint block Gauss-Seidel phase: L holds lambda (internal order), B the
 // right-hand side dL/dx (internal order, free vertices), X the equilibrium.
 template <class R, class PR = R>
@@ -247,6 +282,9 @@ struct AdjArgs {
     const int* plane_ptr;
     const R* planes;
     const R* inert;        // [n_free] m_ii / dt^2, or null
+    const int* vlist;      // as in SweepArgs
+    const int* pcol;
+    int pcolor;
     PR omega, gamma;
 };
 template <class R, class PR>

@@ -490,9 +490,15 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
     using P4 = typename R4t<PR>::T;
     constexpr bool WC = GEN;
     const int gid = xcd_block() * kBlock + threadIdx.x;
-    const int v = vbeg + gid / LANES;
+    int v = vbeg + gid / LANES;
     const int lane = gid & (LANES - 1);
     if (v >= vend) return;
+    if (GEN) {
+        // vertices recoloured after new weak constraints (whole lane groups
+        // return together)
+        if (a.vlist) v = at(a.vlist, v);
+        else if (a.pcol && at(a.pcol, v) != a.pcolor) return;
+    }
     const int kb = at(a.vptr, v), ke = at(a.vptr, v + 1);
     const P4 xw = at(a.W, v);
     int inst = 0;
@@ -793,9 +799,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg
 {
     using P4 = typename R4t<PR>::T;
     const int gid = xcd_block() * kBlock + threadIdx.x;
-    const int v = vbeg + gid / LANES;
+    int v = vbeg + gid / LANES;
     const int lane = gid & (LANES - 1);
     if (v >= vend) return;
+    if (WC) {
+        if (a.vlist) v = at(a.vlist, v);
+        else if (a.pcol && at(a.pcol, v) != a.pcolor) return;
+    }
     const V3<PR> xi = xyz(at(a.X, v));
     const P4 lw = at(a.L, v);
     const V3<PR> li = xyz(lw);

@@ -96,6 +96,9 @@ def lib():
             "pbng_workspace_set_materials": ([vp, vp, vp, vp], C.c_int32),
             "pbng_workspace_set_dirichlet": ([vp, vp, vp], C.c_int32),
             "pbng_workspace_set_inertia": ([vp, C.c_double, vp, vp, vp], C.c_int32),
+            "pbng_workspace_set_contacts": ([vp, C.c_int32, vp, vp, C.c_double, vp], C.c_int32),
+            "pbng_workspace_colors": ([vp, _ip], C.c_int32),
+            "pbng_detect_contacts": ([vp, vp, C.c_double, C.c_int32, vp, vp, _ip, vp], C.c_int32),
             "pbng_solve": ([vp, vp, C.POINTER(SolveOpts), C.POINTER(Stats), vp], C.c_int32),
             "pbng_residual": ([vp, vp, _dp, _dp, vp, vp], C.c_int32),
             "pbng_adjoint": ([vp, vp, vp, vp, vp, vp, vp, C.POINTER(AdjointOpts),
@@ -121,7 +124,9 @@ def exported_symbols() -> List[str]:
     return ["pbng_version", "pbng_last_error", "pbng_lame", "pbng_default_solve_opts",
             "pbng_default_adjoint_opts", "pbng_color", "pbng_workspace_create",
             "pbng_workspace_destroy", "pbng_workspace_info", "pbng_workspace_set_materials",
-            "pbng_workspace_set_dirichlet", "pbng_workspace_set_inertia", "pbng_solve",
+            "pbng_workspace_set_dirichlet", "pbng_workspace_set_inertia",
+            "pbng_workspace_set_contacts", "pbng_workspace_colors", "pbng_detect_contacts",
+            "pbng_solve",
             "pbng_residual", "pbng_adjoint",
             "pbng_load", "pbng_store", "pbng_sweeps", "pbng_phase", "pbng_phase_bytes",
             "pbng_autotune"]
@@ -393,6 +398,42 @@ class Workspace:
         else:
             _check(lib().pbng_workspace_set_inertia(self.handle, float(dt), None, None,
                                                     _stream(stream)))
+
+    def set_contacts(self, pairs, normals, k_n, stream=None):
+        """Vertex-vertex contacts: pairs int32 cuda [n, 2] (caller indices),
+        normals float64 cuda [n, 3], stiffness k_n; n = 0 removes them."""
+        import torch
+        n = int(pairs.shape[0]) if pairs is not None else 0
+        if n > 0:
+            if pairs.dtype != torch.int32 or not pairs.is_cuda or tuple(pairs.shape) != (n, 2):
+                raise ValueError("pairs must be an int32 cuda tensor [n, 2]")
+            if normals.dtype != torch.float64 or not normals.is_cuda or \
+                    tuple(normals.shape) != (n, 3):
+                raise ValueError("normals must be a float64 cuda tensor [n, 3]")
+            pairs, normals = pairs.contiguous(), normals.contiguous()
+            _check(lib().pbng_workspace_set_contacts(self.handle, n, _ptr(pairs), _ptr(normals),
+                                                     float(k_n), _stream(stream)))
+        else:
+            _check(lib().pbng_workspace_set_contacts(self.handle, 0, None, None, float(k_n),
+                                                     _stream(stream)))
+
+    def detect_contacts(self, x, radius, max_pairs=1 << 20, stream=None):
+        """Proximity pairs at positions x: (pairs int32 cuda [n, 2], normals
+        float64 cuda [n, 3])."""
+        import torch
+        self._check_x(x)
+        pairs = torch.empty((max_pairs, 2), dtype=torch.int32, device=x.device)
+        normals = torch.empty((max_pairs, 3), dtype=torch.float64, device=x.device)
+        n = C.c_int32(0)
+        _check(lib().pbng_detect_contacts(self.handle, _ptr(x), float(radius), int(max_pairs),
+                                          _ptr(pairs), _ptr(normals), C.byref(n), _stream(stream)))
+        return pairs[:n.value], normals[:n.value]
+
+    def colors(self):
+        """Current colour of every vertex (caller order, -1 on Dirichlet)."""
+        out = np.zeros(self.n_verts, np.int32)
+        _check(lib().pbng_workspace_colors(self.handle, out.ctypes.data_as(_ip)))
+        return out
 
     # measurement access ---------------------------------------------------
     def load(self, x, stream=None):

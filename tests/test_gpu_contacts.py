@@ -1,0 +1,121 @@
+"""Dynamic weak constraints on the GPU: proximity detection against a brute
+force reference, the incremental recolouring against the oracle's (bit
+exact), and solves, residuals and backward-Euler steps with contacts
+against the oracle run with the workspace's colouring.  Tolerances as for
+the other parity tests: FP64 1e-10 relative, FP32 1e-5."""
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_2306_09021_amd import scenarios as S
+
+from .gpu_util import announce, dev_x, host, rel_err, require_gpu, torch, workspace
+from .test_oracle_contacts import add_contacts, brute_contacts
+from .test_oracle_solve import check_valid_coloring
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def near_blocks(n=5, gap=0.05, shift=0.04, model="corotated"):
+    sc = S.two_blocks(n, gap=gap, model=model, drive=0.02)
+    x = sc.initial_iterate()
+    half = sc.n_verts // 2
+    x[half:, 0] -= shift                       # the right block moved toward the left one
+    x[sc.dirichlet_idx] = sc.dirichlet_x
+    return sc, x
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_detection_matches_brute_force(real):
+    sc, x = near_blocks()
+    xr = x.astype(np.float32).astype(np.float64) if real == "f32" else x
+    op = O.make_problem(sc)
+    ref_p, ref_n = brute_contacts(xr, sc.tets, op.is_dir, 0.05)
+    announce("contact detection %s" % real)
+    ws = workspace([sc], real)
+    pairs, normals = ws.detect_contacts(dev_x(xr, real), 0.05, max_pairs=4096)
+    assert ref_p.shape[0] > 10
+    assert np.array_equal(host(pairs).astype(np.int64), ref_p.astype(np.int64))
+    assert np.abs(host(normals) - ref_n).max() <= 1e-12
+
+
+def test_recolouring_matches_oracle():
+    sc, x = near_blocks()
+    op = O.make_problem(sc)
+    pairs, normals = brute_contacts(x, sc.tets, op.is_dir, 0.05)
+    col0, _ = O.color(op)
+    op2 = O.make_problem(add_contacts(sc, pairs, normals, 1e3))
+    nodes = np.unique(pairs.reshape(-1))
+    nodes = nodes[op2.is_dir[nodes] == 0]
+    ref, _ = O.recolor(op2, col0, nodes)
+    announce("recolouring after contacts")
+    ws = workspace([sc], "f64")
+    assert np.array_equal(ws.colors(), col0)
+    ws.set_contacts(torch.tensor(pairs, dtype=torch.int32, device="cuda"),
+                    torch.tensor(normals, dtype=torch.float64, device="cuda"), 1e3)
+    got = ws.colors()
+    assert np.array_equal(got, ref)
+    check_valid_coloring(op2, got)
+    assert np.any(got != col0)          # the contacts forced some vertex to move
+
+
+@pytest.mark.parametrize("real,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_quasistatic_solve_with_contacts(real, tol):
+    sc, x = near_blocks(model="nh")
+    op = O.make_problem(sc)
+    pairs, normals = brute_contacts(x, sc.tets, op.is_dir, 0.05)
+    sc2 = add_contacts(sc, pairs, normals, 1e3)
+    announce("solve with contacts %s" % real)
+    ws = workspace([sc], real)
+    ws.set_contacts(torch.tensor(pairs, dtype=torch.int32, device="cuda"),
+                    torch.tensor(normals, dtype=torch.float64, device="cuda"), 1e3)
+    col = ws.colors()
+    op2 = O.make_problem(sc2)
+    kw = dict(accel="chebyshev", rho=0.9, gamma=1.3, safeguard="backtrack")
+    xo, sto = O.solve(op2, col, x, max_sweeps=40, **kw)
+    xg = dev_x(x, real)
+    ws.solve(xg, max_sweeps=40, rel_tol=0.0, check_every=40, **kw)
+    assert rel_err(host(xg), xo) <= tol
+    # FP64 residual and energy include the contact terms
+    if real == "f64":
+        n_o, E_o, r_o = O.residual(op2, xo)
+        rn, E, r = ws.residual(xg, want_r=True)
+        assert abs(rn[0] - n_o) <= 1e-9 * n_o
+        assert abs(E[0] - E_o) <= 1e-9 * abs(E_o)
+
+
+def test_backward_euler_steps_with_detection():
+    """The paper's collision loop: every step detects contacts at the
+    current positions, installs them (stiffness 1e8, anisotropic along the
+    pair's normal) and takes a backward-Euler step (dt = 0.002); FP64
+    against the oracle with the same contacts and colouring."""
+    sc = S.two_blocks(5, gap=0.02, model="corotated", drive=0.06)
+    op = O.make_problem(sc)
+    ws = workspace([sc], "f64")
+    dt, kn, radius = 0.002, 1e8, 0.03
+    x_prev = sc.initial_iterate()
+    x_n = x_prev.copy()
+    announce("backward Euler with detection, 5 steps")
+    n_contacts = []
+    for step in range(5):
+        xg = dev_x(x_n, "f64")
+        pairs, normals = ws.detect_contacts(xg, radius, max_pairs=4096)
+        p_h, n_h = host(pairs).astype(np.int64), host(normals)
+        ref_p, ref_n = brute_contacts(x_n, sc.tets, op.is_dir, radius)
+        assert np.array_equal(p_h, ref_p.astype(np.int64))
+        n_contacts.append(p_h.shape[0])
+        ws.set_contacts(pairs, normals, kn)
+        ws.set_inertia(dt, torch.tensor(x_n, device="cuda"), torch.tensor(x_prev, device="cuda"))
+        ws.solve(xg, max_sweeps=30, rel_tol=0.0, check_every=30, accel="none",
+                 safeguard="backtrack")
+        op2 = O.make_problem(add_contacts(sc, ref_p, ref_n, kn))
+        op2.set_inertia(dt, x_n, x_prev)
+        xo, _ = O.solve(op2, ws.colors(), x_n, max_sweeps=30, accel="none", safeguard="backtrack")
+        assert rel_err(host(xg), xo) <= 1e-10, step
+        x_prev, x_n = x_n, xo
+    assert max(n_contacts) > 0
