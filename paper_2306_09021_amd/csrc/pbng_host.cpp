@@ -1332,7 +1332,7 @@ int32_t solve_t(pbng_workspace* ws, void* x, const pbng_solve_opts* o, pbng_stat
         if (st) {
             st[q].sweeps = sweeps[q];
             st[q].converged = conv[q];
-            st[q].n_colors = ws->ncol_inst[q];
+            st[q].n_colors = ws->moved_any ? std::max(ws->ncol_inst[q], ws->ncol_dyn) : ws->ncol_inst[q];
             st[q].rejected = rej[q];
             st[q].residual0 = r0[q];
             st[q].residual = rr[q];
@@ -1484,7 +1484,7 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
             st[q] = pbng_stats{};
             st[q].sweeps = sweeps[q];
             st[q].converged = conv[q];
-            st[q].n_colors = ws->ncol_inst[q];
+            st[q].n_colors = ws->moved_any ? std::max(ws->ncol_inst[q], ws->ncol_dyn) : ws->ncol_inst[q];
             st[q].residual0 = b0[q];
             st[q].residual = rr[q];
             st[q].rel_residual = b0[q] > 0 ? rr[q] / b0[q] : 0.0;
