@@ -21,6 +21,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "pbng_oracle.c")
+_SRCS = (_SRC, os.path.join(_HERE, "pbng_oracle2d.c"))
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 NEOHOOKEAN, COROTATED, STABLE_NEOHOOKEAN = 0, 1, 2
@@ -56,10 +57,11 @@ class _Stats(C.Structure):
 
 def build(force: bool = False) -> str:
     """Compile liboracle.so with gcc (IEEE double, no fast-math, no FMA)."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if (force or not os.path.exists(_LIB)
+            or os.path.getmtime(_LIB) < max(os.path.getmtime(f) for f in _SRCS)):
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call(["gcc", "-O2", "-std=c99", "-fopenmp", "-fPIC", "-shared",
-                               "-ffp-contract=off", "-o", tmp, _SRC, "-lm"])
+                               "-ffp-contract=off", "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 

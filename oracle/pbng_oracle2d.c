@@ -1,0 +1,516 @@
+/*
+ * pbng_oracle2d.c -- plain, serial FP64 reference for PBNG on triangle
+ * meshes (d = 2), the planar case of the same method (Chen, Han, Chen &
+ * Teran, arXiv 2306.09021): piecewise-linear interpolation over triangles
+ * (Sec. "Discretization"), 2x2 deformation gradients, the constitutive
+ * models of Eq. (cor) and Eq. (nh) with d = 2, the modified Hessian of
+ * Eq. (mod_hess_dens) / (mod_hess) with the 2x2 cofactor matrix, and 2x2
+ * local systems in the update of Eq. (pbgn_update) / (pbgn_dx).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Built into oracle/liboracle.so next to the
+ * 3-D oracle and loaded by tests/, __graft_entry__.smoke() and the
+ * cpu_baseline leg of bench.py -- nothing else.  It shares no code with the
+ * HIP library and none with the 3-D oracle file either.  Every quantity is
+ * computed from its definition; colours run in sequence, vertices of one
+ * colour in ascending index.
+ *
+ * Only the Neo-Hookean and corotated models are defined here: the stable
+ * Neo-Hookean density as printed (Eq. snh) carries the 3-D rest-state
+ * constant 3 mu / (4 lambda) and is not stress free at F = I when d = 2.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR2_NEOHOOKEAN 0
+#define OR2_COROTATED 1
+
+#define OR2_ACCEL_NONE 0
+#define OR2_ACCEL_CHEBYSHEV 1
+#define OR2_ACCEL_SOR 2
+
+#define OR2_SAFEGUARD_BACKTRACK 1
+
+/* A planar problem; arrays owned by the caller.  Matrices are row-major
+ * 2x2, M[2 * r + c]. */
+typedef struct {
+    int32_t nv, nt, model;
+    const double* X;        /* [nv][2] rest positions                    */
+    const int32_t* tris;    /* [nt][3], counter-clockwise (area > 0)     */
+    const double* mu;       /* [nt]                                      */
+    const double* lam;      /* [nt] Lame lambda                          */
+    const double* fext;     /* [nv][2] lumped external force             */
+    const uint8_t* is_dir;  /* [nv] 1 = Dirichlet                        */
+} or2_problem;
+
+/* Same field layout as the 3-D oracle's options and statistics. */
+typedef struct {
+    int32_t max_sweeps;
+    int32_t check_every;
+    double rel_tol;
+    int32_t accel;
+    double rho, gamma, omega;
+    int32_t safeguard;
+    int32_t max_halvings;
+    double skip_tol;        /* unused in 2-D                             */
+    int32_t emulate_f32;    /* round every stored position to float      */
+    int32_t n_threads;      /* unused in 2-D                             */
+} or2_opts;
+
+typedef struct {
+    int32_t sweeps;
+    int32_t converged;
+    int64_t rejected;
+    int64_t halvings;
+    double res0, res, rel, energy;
+} or2_stats;
+
+/* ------------------------------------------------------------------ */
+/* 2x2 algebra                                                          */
+/* ------------------------------------------------------------------ */
+static double det2(const double* A) { return A[0] * A[3] - A[1] * A[2]; }
+
+/* cof(A) = det(A) A^{-T}, defined for every A: [[a11, -a10], [-a01, a00]]. */
+static void cofactor2(const double* A, double* C)
+{
+    C[0] = A[3];
+    C[1] = -A[2];
+    C[2] = -A[1];
+    C[3] = A[0];
+}
+
+/* Closest rotation to F (maximiser of tr(R^T F) over proper rotations),
+ * i.e. the rotation of the polar decomposition F = R S for det F > 0 and
+ * of the signed one otherwise.  With R = [[c, -s], [s, c]],
+ * tr(R^T F) = c (F00 + F11) + s (F10 - F01), maximised by (c, s) parallel
+ * to (F00 + F11, F10 - F01); when both vanish every rotation is optimal and
+ * R = I is taken. */
+void or2_rotation(const double* F, double* R)
+{
+    double a = F[0] + F[3], b = F[2] - F[1];
+    double r = sqrt(a * a + b * b);
+    double c = 1.0, s = 0.0;
+    if (r > 0.0) {
+        c = a / r;
+        s = b / r;
+    }
+    R[0] = c;
+    R[1] = -s;
+    R[2] = s;
+    R[3] = c;
+}
+
+/* ------------------------------------------------------------------ */
+/* Constitutive models with d = 2                                        */
+/* ------------------------------------------------------------------ */
+/* Corotated, Eq. (cor): mu |F - R(F)|^2 + lambda/2 (det F - 1)^2.
+ * Neo-Hookean, Eq. (nh): 1/2 mu |F|^2 + lhat/2 (det F - 1 - mu/lhat)^2,
+ * lhat = mu + lambda. */
+double or2_psi(int model, double mu, double lam, const double* F)
+{
+    double J = det2(F);
+    if (model == OR2_NEOHOOKEAN) {
+        double lh = mu + lam, f2 = 0.0;
+        for (int k = 0; k < 4; ++k) f2 += F[k] * F[k];
+        double q = J - 1.0 - mu / lh;
+        return 0.5 * mu * f2 + 0.5 * lh * q * q;
+    }
+    double R[4], d2 = 0.0;
+    or2_rotation(F, R);
+    for (int k = 0; k < 4; ++k) d2 += (F[k] - R[k]) * (F[k] - R[k]);
+    return mu * d2 + 0.5 * lam * (J - 1.0) * (J - 1.0);
+}
+
+/* P = dPsi/dF; d det F / dF = cof F and d/dF |F - R(F)|^2 = 2 (F - R). */
+void or2_pk1(int model, double mu, double lam, const double* F, double* P)
+{
+    double C[4], J = det2(F);
+    cofactor2(F, C);
+    if (model == OR2_NEOHOOKEAN) {
+        double lh = mu + lam, q = J - 1.0 - mu / lh;
+        for (int k = 0; k < 4; ++k) P[k] = mu * F[k] + lh * q * C[k];
+    } else {
+        double R[4];
+        or2_rotation(F, R);
+        for (int k = 0; k < 4; ++k) P[k] = 2.0 * mu * (F[k] - R[k]) + lam * (J - 1.0) * C[k];
+    }
+}
+
+/* Modified Hessian density, Eq. (mod_hess_dens) with d = 2, as the tensor
+ * Ct[alpha][gamma][beta][delta] (index ((a*2+g)*2+b)*2+d):
+ * 2 mu delta_ab delta_gd + lambda cof(F)_ag cof(F)_bd. */
+void or2_mod_hess_density(double mu, double lam, const double* F, double* Ct)
+{
+    double C[4];
+    cofactor2(F, C);
+    for (int a = 0; a < 2; ++a)
+        for (int g = 0; g < 2; ++g)
+            for (int b = 0; b < 2; ++b)
+                for (int d = 0; d < 2; ++d)
+                    Ct[((a * 2 + g) * 2 + b) * 2 + d] =
+                        2.0 * mu * (a == b) * (g == d) + lam * C[2 * a + g] * C[2 * b + d];
+}
+
+/* ------------------------------------------------------------------ */
+/* Discretisation                                                       */
+/* ------------------------------------------------------------------ */
+/* Per triangle: dN[e][j][:] = dN_j/dX, A0[e] = rest area.  With
+ * Dm = [X1 - X0, X2 - X0] (columns), dN_j (j = 1, 2) is row j-1 of Dm^{-1}
+ * and dN_0 = -(dN_1 + dN_2).  Returns -1 for a triangle of area <= 0, -2
+ * for an index out of range. */
+int or2_prep(int32_t nv, int32_t nt, const double* X, const int32_t* tris, double* dN /* [nt][3][2] */,
+             double* A0 /* [nt] */)
+{
+    for (int e = 0; e < nt; ++e) {
+        const int32_t* t = tris + 3 * e;
+        for (int j = 0; j < 3; ++j)
+            if (t[j] < 0 || t[j] >= nv) return -2;
+        double Dm[4];
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) Dm[2 * r + c] = X[2 * t[c + 1] + r] - X[2 * t[0] + r];
+        double det = det2(Dm);
+        if (!(det > 0.0)) return -1;
+        A0[e] = 0.5 * det;
+        double* g = dN + 6 * e;
+        /* Dm^{-1} = cof(Dm)^T / det */
+        g[2] = Dm[3] / det;
+        g[3] = -Dm[1] / det;
+        g[4] = -Dm[2] / det;
+        g[5] = Dm[0] / det;
+        g[0] = -(g[2] + g[4]);
+        g[1] = -(g[3] + g[5]);
+    }
+    return 0;
+}
+
+/* Lumped body force: a linear basis function integrates to A0 / 3 over a
+ * triangle, so fhat_i += R0 g A0_e / 3 from every incident triangle. */
+void or2_body_force(int32_t nv, int32_t nt, const int32_t* tris, const double* A0, double density,
+                    const double* grav, double* fext /* [nv][2], accumulated */)
+{
+    (void)nv;
+    for (int e = 0; e < nt; ++e)
+        for (int j = 0; j < 3; ++j)
+            for (int c = 0; c < 2; ++c) fext[2 * tris[3 * e + j] + c] += density * grav[c] * A0[e] / 3.0;
+}
+
+static void deformation_gradient(const double* y, const int32_t* t, const double* g, double* F)
+{
+    for (int a = 0; a < 2; ++a)
+        for (int b = 0; b < 2; ++b) {
+            double s = 0.0;
+            for (int j = 0; j < 3; ++j) s += y[2 * t[j] + a] * g[2 * j + b];
+            F[2 * a + b] = s;
+        }
+}
+
+/* vertex -> incident triangles (with local slot) */
+typedef struct {
+    int32_t *tptr, *tlist, *tslot;
+    double *dN, *A0;
+} or2_adj;
+
+static void adj_free(or2_adj* A)
+{
+    free(A->tptr); free(A->tlist); free(A->tslot); free(A->dN); free(A->A0);
+    memset(A, 0, sizeof *A);
+}
+
+static int adj_build(const or2_problem* p, or2_adj* A)
+{
+    memset(A, 0, sizeof *A);
+    int nv = p->nv, nt = p->nt;
+    A->dN = (double*)malloc(sizeof(double) * 6 * (size_t)(nt > 0 ? nt : 1));
+    A->A0 = (double*)malloc(sizeof(double) * (size_t)(nt > 0 ? nt : 1));
+    int rc = or2_prep(nv, nt, p->X, p->tris, A->dN, A->A0);
+    if (rc) { adj_free(A); return rc; }
+    A->tptr = (int32_t*)calloc((size_t)nv + 1, sizeof(int32_t));
+    for (int e = 0; e < nt; ++e)
+        for (int j = 0; j < 3; ++j) A->tptr[p->tris[3 * e + j] + 1]++;
+    for (int i = 0; i < nv; ++i) A->tptr[i + 1] += A->tptr[i];
+    A->tlist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(3 * nt + 1));
+    A->tslot = (int32_t*)malloc(sizeof(int32_t) * (size_t)(3 * nt + 1));
+    int32_t* fill = (int32_t*)calloc((size_t)nv + 1, sizeof(int32_t));
+    for (int e = 0; e < nt; ++e)
+        for (int j = 0; j < 3; ++j) {
+            int v = p->tris[3 * e + j];
+            int k = A->tptr[v] + fill[v]++;
+            A->tlist[k] = e;
+            A->tslot[k] = j;
+        }
+    free(fill);
+    return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Node colouring, Sec. "Coloring and Parallelism"                       */
+/* ------------------------------------------------------------------ */
+/* Free vertices in ascending index each take the least colour used by no
+ * already coloured vertex of an incident triangle (the union of the sets
+ * S_c of those triangles).  Dirichlet vertices get -1.  Returns the number
+ * of colours or < 0 on error. */
+int32_t or2_color(const or2_problem* p, int32_t* colors)
+{
+    or2_adj A;
+    int rc = adj_build(p, &A);
+    if (rc) return rc;
+    int ncol = 0;
+    char used[256];
+    for (int i = 0; i < p->nv; ++i) colors[i] = -1;
+    for (int i = 0; i < p->nv; ++i) {
+        if (p->is_dir[i]) continue;
+        memset(used, 0, sizeof used);
+        for (int k = A.tptr[i]; k < A.tptr[i + 1]; ++k) {
+            const int32_t* t = p->tris + 3 * A.tlist[k];
+            for (int j = 0; j < 3; ++j)
+                if (colors[t[j]] >= 0) used[colors[t[j]]] = 1;
+        }
+        int col = 0;
+        while (used[col]) ++col;
+        if (col >= 255) { adj_free(&A); return -4; }
+        colors[i] = col;
+        if (col + 1 > ncol) ncol = col + 1;
+    }
+    adj_free(&A);
+    return ncol;
+}
+
+/* ------------------------------------------------------------------ */
+/* Local energy, local system and the update                            */
+/* ------------------------------------------------------------------ */
+/* Energy of the terms involving vertex i with y_i replaced by yi: incident
+ * triangles A0 Psi(F) and -yi . fext_i; magnitudes added to *absum. */
+static double local_energy(const or2_problem* p, const or2_adj* A, const double* y, int i,
+                           const double* yi, double* absum)
+{
+    double E = 0.0, ab = 0.0;
+    for (int k = A->tptr[i]; k < A->tptr[i + 1]; ++k) {
+        int e = A->tlist[k];
+        const int32_t* t = p->tris + 3 * e;
+        const double* g = A->dN + 6 * e;
+        double F[4];
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                double s = 0.0;
+                for (int j = 0; j < 3; ++j) {
+                    const double* yj = (t[j] == i) ? yi : y + 2 * t[j];
+                    s += yj[a] * g[2 * j + b];
+                }
+                F[2 * a + b] = s;
+            }
+        double w = A->A0[e] * or2_psi(p->model, p->mu[e], p->lam[e], F);
+        E += w;
+        ab += fabs(w);
+    }
+    double w = -(yi[0] * p->fext[2 * i] + yi[1] * p->fext[2 * i + 1]);
+    E += w;
+    ab += fabs(w);
+    if (absum) *absum += ab;
+    return E;
+}
+
+/* g_i = dE/dy_i and the modified nodal Hessian of Eq. (mod_hess), the
+ * density of Eq. (mod_hess_dens) contracted with dN_i dN_i^T. */
+static void local_system(const or2_problem* p, const or2_adj* A, const double* y, int i, double* gi,
+                         double* Ai)
+{
+    gi[0] = -p->fext[2 * i];
+    gi[1] = -p->fext[2 * i + 1];
+    for (int k = 0; k < 4; ++k) Ai[k] = 0.0;
+    for (int k = A->tptr[i]; k < A->tptr[i + 1]; ++k) {
+        int e = A->tlist[k], slot = A->tslot[k];
+        const int32_t* t = p->tris + 3 * e;
+        const double* g = A->dN + 6 * e;
+        const double* a = g + 2 * slot;
+        double F[4], P[4], Ct[16], V = A->A0[e];
+        deformation_gradient(y, t, g, F);
+        or2_pk1(p->model, p->mu[e], p->lam[e], F, P);
+        for (int r = 0; r < 2; ++r)
+            for (int c = 0; c < 2; ++c) gi[r] += V * P[2 * r + c] * a[c];
+        or2_mod_hess_density(p->mu[e], p->lam[e], F, Ct);
+        for (int al = 0; al < 2; ++al)
+            for (int be = 0; be < 2; ++be) {
+                double s = 0.0;
+                for (int ga = 0; ga < 2; ++ga)
+                    for (int de = 0; de < 2; ++de) s += Ct[((al * 2 + ga) * 2 + be) * 2 + de] * a[ga] * a[de];
+                Ai[2 * al + be] += V * s;
+            }
+    }
+}
+
+static double to_f32(double v) { return (double)(float)v; }
+
+/* One modified-Newton step on vertex i from Delta = 0 (Eq. pbgn_dx with the
+ * 2x2 system A_i Delta = -g_i), optionally halving the step until the local
+ * energy does not increase (slack 8 u sum |summands|); a vertex with no
+ * passing step keeps its position.  Returns the halvings, or -1 when
+ * rejected. */
+static int update_vertex(const or2_problem* p, const or2_adj* A, double* y, int i, const or2_opts* o)
+{
+    double gi[2], Ai[4];
+    local_system(p, A, y, i, gi, Ai);
+    double det = det2(Ai);
+    if (!(det > 0.0)) return -1;
+    double d[2] = {-(Ai[3] * gi[0] - Ai[1] * gi[1]) / det, -(-Ai[2] * gi[0] + Ai[0] * gi[1]) / det};
+    double yi0[2] = {y[2 * i], y[2 * i + 1]};
+    double alpha = 1.0;
+    int halvings = 0;
+    if (o->safeguard == OR2_SAFEGUARD_BACKTRACK) {
+        const double u = 1.1102230246251565e-16; /* 2^-53 */
+        double ab0 = 0.0;
+        double E0 = local_energy(p, A, y, i, yi0, &ab0);
+        for (;;) {
+            double yt[2], ab1 = 0.0;
+            for (int a = 0; a < 2; ++a) {
+                yt[a] = yi0[a] + alpha * d[a];
+                if (o->emulate_f32) yt[a] = to_f32(yt[a]);
+            }
+            double E1 = local_energy(p, A, y, i, yt, &ab1);
+            if (E1 - E0 <= 8.0 * u * (ab0 + ab1)) break;
+            if (halvings >= o->max_halvings) return -1;
+            alpha *= 0.5;
+            ++halvings;
+        }
+    }
+    for (int a = 0; a < 2; ++a) {
+        double v = yi0[a] + alpha * d[a];
+        y[2 * i + a] = o->emulate_f32 ? to_f32(v) : v;
+    }
+    return halvings;
+}
+
+/* r_i = f_i(y) + fhat_i over free vertices (Eq. fem_qs) by scattering the
+ * element forces -A0 P dN_j; total energy sum A0 Psi - y . fhat.  Returns
+ * ||r||_2, or -1 on a mesh error. */
+double or2_residual(const or2_problem* p, const double* y, double* r_out /* nullable [nv][2] */,
+                    double* energy_out)
+{
+    or2_adj A;
+    if (adj_build(p, &A)) return -1.0;
+    double* f = (double*)calloc((size_t)2 * p->nv + 1, sizeof(double));
+    double E = 0.0;
+    for (int e = 0; e < p->nt; ++e) {
+        const int32_t* t = p->tris + 3 * e;
+        const double* g = A.dN + 6 * e;
+        double F[4], P[4];
+        deformation_gradient(y, t, g, F);
+        or2_pk1(p->model, p->mu[e], p->lam[e], F, P);
+        E += A.A0[e] * or2_psi(p->model, p->mu[e], p->lam[e], F);
+        for (int j = 0; j < 3; ++j)
+            for (int r = 0; r < 2; ++r) f[2 * t[j] + r] -= A.A0[e] * (P[2 * r] * g[2 * j] + P[2 * r + 1] * g[2 * j + 1]);
+    }
+    double n2 = 0.0;
+    for (int i = 0; i < p->nv; ++i) {
+        E -= y[2 * i] * p->fext[2 * i] + y[2 * i + 1] * p->fext[2 * i + 1];
+        for (int a = 0; a < 2; ++a) {
+            double r = p->is_dir[i] ? 0.0 : f[2 * i + a] + p->fext[2 * i + a];
+            if (r_out) r_out[2 * i + a] = r;
+            n2 += r * r;
+        }
+    }
+    free(f);
+    adj_free(&A);
+    if (energy_out) *energy_out = E;
+    return sqrt(n2);
+}
+
+/* Sweeps over the colours in sequence with the optional Chebyshev / SOR
+ * blend of Sec. "Acceleration Techniques" on the free vertices, FP64
+ * residual every check_every sweeps (relative residuals into hist when
+ * non-null).  x: initial iterate with Dirichlet rows set; receives the
+ * result. */
+int32_t or2_solve(const or2_problem* p, const int32_t* colors, double* x, const or2_opts* o,
+                  or2_stats* st, double* hist)
+{
+    memset(st, 0, sizeof *st);
+    or2_adj A;
+    int rc = adj_build(p, &A);
+    if (rc) return rc;
+    int nv = p->nv, ncol = 0;
+    for (int i = 0; i < nv; ++i)
+        if (colors[i] + 1 > ncol) ncol = colors[i] + 1;
+    size_t nb = sizeof(double) * 2 * (size_t)(nv > 0 ? nv : 1);
+    double* xl = (double*)malloc(nb);
+    double* xlm1 = (double*)malloc(nb);
+    memcpy(xlm1, x, sizeof(double) * 2 * (size_t)nv);
+    double E = 0.0;
+    double res0 = or2_residual(p, x, NULL, &E);
+    st->res0 = st->res = res0;
+    st->rel = res0 > 0 ? 1.0 : 0.0;
+    st->energy = E;
+    double omega = 1.0;
+    int every = o->check_every > 0 ? o->check_every : 1, nh = 0;
+    for (int l = 0; l < o->max_sweeps; ++l) {
+        if (res0 == 0.0) { st->converged = 1; break; }
+        memcpy(xl, x, sizeof(double) * 2 * (size_t)nv);
+        for (int c = 0; c < ncol; ++c)
+            for (int i = 0; i < nv; ++i) {
+                if (colors[i] != c) continue;
+                int h = update_vertex(p, &A, x, i, o);
+                if (h < 0) st->rejected++;
+                else st->halvings += h;
+            }
+        if (o->accel != OR2_ACCEL_NONE) {
+            double w, gam;
+            if (o->accel == OR2_ACCEL_CHEBYSHEV) {
+                if (l < 2) omega = 1.0;
+                else if (l == 2) omega = 2.0 / (2.0 - o->rho * o->rho);
+                else omega = 4.0 / (4.0 - o->rho * o->rho * omega);
+                w = omega;
+                gam = o->gamma;
+            } else {
+                w = o->omega;
+                gam = 1.0;
+            }
+            for (int i = 0; i < nv; ++i) {
+                if (p->is_dir[i]) continue;
+                for (int a = 0; a < 2; ++a) {
+                    int k = 2 * i + a;
+                    double v = o->accel == OR2_ACCEL_CHEBYSHEV
+                                   ? w * (gam * (x[k] - xl[k]) + xl[k] - xlm1[k]) + xlm1[k]
+                                   : w * (x[k] - xlm1[k]) + xlm1[k];
+                    x[k] = o->emulate_f32 ? to_f32(v) : v;
+                }
+            }
+            double* t = xlm1; xlm1 = xl; xl = t;
+        }
+        st->sweeps = l + 1;
+        if ((l + 1) % every == 0 || l + 1 == o->max_sweeps) {
+            double r = or2_residual(p, x, NULL, &E);
+            st->res = r;
+            st->rel = r / res0;
+            st->energy = E;
+            if (hist && (l + 1) % every == 0) hist[nh++] = st->rel;
+            if (!isfinite(r)) break;
+            if (st->rel <= o->rel_tol) { st->converged = 1; break; }
+        }
+    }
+    free(xl);
+    free(xlm1);
+    adj_free(&A);
+    return 0;
+}
+
+/* Energy change of each single-vertex update of one plain sweep, in sweep
+ * order, into dE [n_free]; returns the number of updates. */
+int32_t or2_sweep_energy_trace(const or2_problem* p, const int32_t* colors, double* x, const or2_opts* o,
+                               double* dE)
+{
+    or2_adj A;
+    if (adj_build(p, &A)) return -1;
+    int ncol = 0, n = 0;
+    for (int i = 0; i < p->nv; ++i)
+        if (colors[i] + 1 > ncol) ncol = colors[i] + 1;
+    for (int c = 0; c < ncol; ++c)
+        for (int i = 0; i < p->nv; ++i) {
+            if (colors[i] != c) continue;
+            double E0, E1;
+            or2_residual(p, x, NULL, &E0);
+            update_vertex(p, &A, x, i, o);
+            or2_residual(p, x, NULL, &E1);
+            dE[n++] = E1 - E0;
+        }
+    adj_free(&A);
+    return n;
+}

@@ -1,0 +1,184 @@
+"""FP64 oracle for PBNG on triangle meshes (d = 2) -- TEST INFRASTRUCTURE ONLY.
+
+Marshals numpy arrays into the plain C of ``pbng_oracle2d.c`` (built into
+the same ``liboracle.so`` as the 3-D oracle).  Same rules as the package:
+only tests/, ``__graft_entry__.smoke()`` and bench.py's ``cpu_baseline`` leg
+may use it.  Positions are [n, 2] arrays; matrices are 2x2.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import ACCEL, SAFEGUARD, _Opts, _Stats, _d, _f64, _i, lame, lib as _lib3
+
+NEOHOOKEAN, COROTATED = 0, 1
+MODEL = {"nh": NEOHOOKEAN, "corotated": COROTATED}
+
+_dp = C.POINTER(C.c_double)
+_ip = C.POINTER(C.c_int32)
+_up = C.POINTER(C.c_uint8)
+
+
+class _Problem2(C.Structure):
+    _fields_ = [("nv", C.c_int32), ("nt", C.c_int32), ("model", C.c_int32), ("X", _dp),
+                ("tris", _ip), ("mu", _dp), ("lam", _dp), ("fext", _dp), ("is_dir", _up)]
+
+
+_ready = False
+
+
+def lib():
+    global _ready
+    L = _lib3()
+    if not _ready:
+        L.or2_rotation.argtypes = [_dp, _dp]
+        L.or2_psi.argtypes = [C.c_int, C.c_double, C.c_double, _dp]
+        L.or2_psi.restype = C.c_double
+        L.or2_pk1.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp]
+        L.or2_mod_hess_density.argtypes = [C.c_double, C.c_double, _dp, _dp]
+        L.or2_prep.argtypes = [C.c_int32, C.c_int32, _dp, _ip, _dp, _dp]
+        L.or2_prep.restype = C.c_int
+        L.or2_body_force.argtypes = [C.c_int32, C.c_int32, _ip, _dp, C.c_double, _dp, _dp]
+        L.or2_color.argtypes = [C.POINTER(_Problem2), _ip]
+        L.or2_color.restype = C.c_int32
+        L.or2_residual.argtypes = [C.POINTER(_Problem2), _dp, _dp, _dp]
+        L.or2_residual.restype = C.c_double
+        L.or2_solve.argtypes = [C.POINTER(_Problem2), _ip, _dp, C.POINTER(_Opts), C.POINTER(_Stats), _dp]
+        L.or2_solve.restype = C.c_int32
+        L.or2_sweep_energy_trace.argtypes = [C.POINTER(_Problem2), _ip, _dp, C.POINTER(_Opts), _dp]
+        L.or2_sweep_energy_trace.restype = C.c_int32
+        _ready = True
+    return L
+
+
+def rotation(F):
+    """Closest proper rotation to a 2x2 F (tr(R^T F) maximal)."""
+    F = _f64(F, (2, 2))
+    R = np.zeros((2, 2))
+    lib().or2_rotation(_d(F), _d(R))
+    return R
+
+
+def psi(model, mu, lam, F):
+    return lib().or2_psi(model, mu, lam, _d(_f64(F, (2, 2))))
+
+
+def pk1(model, mu, lam, F):
+    P = np.zeros((2, 2))
+    lib().or2_pk1(model, mu, lam, _d(_f64(F, (2, 2))), _d(P))
+    return P
+
+
+def mod_hess_density(mu, lam, F):
+    """Ct[alpha, gamma, beta, delta] of Eq. (mod_hess_dens) with d = 2."""
+    out = np.zeros(16)
+    lib().or2_mod_hess_density(mu, lam, _d(_f64(F, (2, 2))), _d(out))
+    return out.reshape(2, 2, 2, 2)
+
+
+@dataclass
+class PlanarProblem:
+    nv: int
+    nt: int
+    model: int
+    X: np.ndarray
+    tris: np.ndarray
+    mu: np.ndarray
+    lam: np.ndarray
+    fext: np.ndarray
+    is_dir: np.ndarray
+    A0: np.ndarray
+    dN: np.ndarray
+    dirichlet_idx: np.ndarray
+    dirichlet_x: np.ndarray
+
+    def struct(self) -> _Problem2:
+        s = _Problem2()
+        s.nv, s.nt, s.model = self.nv, self.nt, self.model
+        s.X, s.tris, s.mu, s.lam, s.fext = (_d(self.X), _i(self.tris), _d(self.mu), _d(self.lam),
+                                            _d(self.fext))
+        s.is_dir = self.is_dir.ctypes.data_as(_up)
+        return s
+
+
+def make_problem(sc, mu=None, lam=None) -> PlanarProblem:
+    """The oracle's view of a Scenario2D (Lame parameters from sc.E, sc.nu
+    unless mu / lam are given, scalar or per triangle)."""
+    L = lib()
+    X = _f64(sc.rest_pos, (-1, 2))
+    T = np.ascontiguousarray(sc.tris, dtype=np.int32).reshape(-1, 3)
+    nv, nt = X.shape[0], T.shape[0]
+    if mu is None or lam is None:
+        m, l_ = lame(sc.E, sc.nu)
+        mu = m if mu is None else mu
+        lam = l_ if lam is None else lam
+    mu = np.ascontiguousarray(np.broadcast_to(np.asarray(mu, np.float64), (nt,)))
+    lam = np.ascontiguousarray(np.broadcast_to(np.asarray(lam, np.float64), (nt,)))
+    dN = np.zeros((max(nt, 1), 3, 2))
+    A0 = np.zeros(max(nt, 1))
+    rc = L.or2_prep(nv, nt, _d(X), _i(T), _d(dN), _d(A0))
+    if rc != 0:
+        raise ValueError("planar oracle: invalid mesh (rc=%d)" % rc)
+    fext = np.zeros((nv, 2))
+    g = np.ascontiguousarray(sc.gravity, dtype=np.float64)
+    if sc.density != 0.0 and nt > 0:
+        L.or2_body_force(nv, nt, _i(T), _d(A0), float(sc.density), _d(g), _d(fext))
+    if sc.nodal_force is not None:
+        fext += np.asarray(sc.nodal_force, np.float64).reshape(nv, 2)
+    is_dir = np.zeros(nv, np.uint8)
+    is_dir[np.asarray(sc.dirichlet_idx, np.int64)] = 1
+    return PlanarProblem(nv=nv, nt=nt, model=MODEL[sc.model], X=X, tris=T, mu=mu, lam=lam,
+                         fext=np.ascontiguousarray(fext), is_dir=is_dir, A0=A0[:nt], dN=dN[:nt],
+                         dirichlet_idx=np.asarray(sc.dirichlet_idx, np.int32),
+                         dirichlet_x=np.asarray(sc.dirichlet_x, np.float64))
+
+
+def color(op: PlanarProblem):
+    out = np.zeros(op.nv, np.int32)
+    n = lib().or2_color(C.byref(op.struct()), _i(out))
+    if n < 0:
+        raise ValueError("planar oracle colour failed (%d)" % n)
+    return out, int(n)
+
+
+def residual(op: PlanarProblem, x):
+    """(||r||_2 over free vertices, energy, r [nv, 2])."""
+    x = _f64(x, (-1, 2))
+    r = np.zeros((op.nv, 2))
+    E = C.c_double()
+    n = lib().or2_residual(C.byref(op.struct()), _d(x), _d(r), C.byref(E))
+    return float(n), float(E.value), r
+
+
+def solve(op: PlanarProblem, colors, x, max_sweeps=100, accel="none", rho=0.95, gamma=1.7, omega=1.7,
+          safeguard="backtrack", max_halvings=8, rel_tol=0.0, check_every=1, emulate_f32=False,
+          history=False):
+    x = np.array(x, dtype=np.float64).reshape(-1, 2)
+    colors = np.ascontiguousarray(colors, np.int32)
+    o = _Opts(max_sweeps=max_sweeps, check_every=check_every, rel_tol=rel_tol, accel=ACCEL[accel],
+              rho=rho, gamma=gamma, omega=omega, safeguard=SAFEGUARD[safeguard],
+              max_halvings=max_halvings, skip_tol=0.0, emulate_f32=int(emulate_f32), n_threads=1)
+    st = _Stats()
+    hist = np.zeros(max(1, max_sweeps // max(1, check_every)))
+    rc = lib().or2_solve(C.byref(op.struct()), _i(colors), _d(x), C.byref(o), C.byref(st), _d(hist))
+    if rc:
+        raise ValueError("planar oracle solve failed (%d)" % rc)
+    stats = dict(sweeps=st.sweeps, converged=bool(st.converged), rejected=int(st.rejected),
+                 halvings=int(st.halvings), res0=st.res0, res=st.res, rel=st.rel, energy=st.energy)
+    if history:
+        return x, stats, hist[: max(0, st.sweeps // max(1, check_every))]
+    return x, stats
+
+
+def sweep_energy_trace(op: PlanarProblem, colors, x, safeguard="backtrack", max_halvings=8):
+    x = np.array(x, dtype=np.float64).reshape(-1, 2)
+    colors = np.ascontiguousarray(colors, np.int32)
+    o = _Opts(max_sweeps=1, check_every=1, rel_tol=0.0, accel=0, rho=0, gamma=1, omega=1,
+              safeguard=SAFEGUARD[safeguard], max_halvings=max_halvings, skip_tol=0.0, emulate_f32=0,
+              n_threads=1)
+    dE = np.zeros(op.nv)
+    n = lib().or2_sweep_energy_trace(C.byref(op.struct()), _i(colors), _d(x), C.byref(o), _d(dE))
+    return dE[:n], x

@@ -446,3 +446,87 @@ def config_muscles(seed: int = 3, n_meshes: int = 8, n_target: int = 40000,
                     planes=planes,
                     solve=dict(accel="chebyshev", rho=0.95, gamma=1.7, max_sweeps=1000,
                                rel_tol=0.0, safeguard="backtrack", real="f32"))
+
+
+# ----------------------------------------------------------------------------
+# planar (d = 2) triangle meshes
+# ----------------------------------------------------------------------------
+def square_mesh(nx: int, ny: int, h=1.0, diagonal: str = "uniform"):
+    """Vertex grid nx*ny (index i + nx j, x <- i, y <- j) with spacing h,
+    every square cell split into two counter-clockwise triangles: along the
+    (0,0)-(1,1) diagonal everywhere ("uniform", six triangles at an interior
+    vertex) or alternating with the other diagonal in a checkerboard
+    ("alternate").  Returns (rest_pos float64 [n, 2], tris int32 [m, 3])."""
+    hx, hy = (h, h) if np.isscalar(h) else h
+    j, i = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    X = np.stack([i.reshape(-1) * hx, j.reshape(-1) * hy], axis=1).astype(np.float64)
+    ci, cj = np.meshgrid(np.arange(nx - 1), np.arange(ny - 1), indexing="xy")
+    ci, cj = ci.reshape(-1), cj.reshape(-1)
+    v00 = ci + nx * cj
+    v10, v01, v11 = v00 + 1, v00 + nx, v00 + nx + 1
+    main = np.stack([np.stack([v00, v10, v11], 1), np.stack([v00, v11, v01], 1)], 1)
+    if diagonal == "uniform":
+        T = main
+    elif diagonal == "alternate":
+        other = np.stack([np.stack([v00, v10, v01], 1), np.stack([v10, v11, v01], 1)], 1)
+        T = np.where(((ci + cj) % 2 == 0)[:, None, None], main, other)
+    else:
+        raise ValueError(diagonal)
+    return X, T.reshape(-1, 3).astype(np.int32)
+
+
+@dataclass
+class Scenario2D:
+    """One planar quasistatic problem (inputs only); positions are [n, 2]."""
+    name: str
+    rest_pos: np.ndarray                       # float64 [n, 2]
+    tris: np.ndarray                           # int32 [m, 3], counter-clockwise
+    model: str                                 # "nh" | "corotated"
+    E: np.ndarray                              # scalar or [m]
+    nu: np.ndarray                             # scalar or [m]
+    dirichlet_idx: np.ndarray                  # int32 [nd]
+    dirichlet_x: np.ndarray                    # float64 [nd, 2]
+    x0: np.ndarray                             # float64 [n, 2] initial iterate
+    density: float = 0.0
+    gravity: tuple = (0.0, 0.0)
+    nodal_force: Optional[np.ndarray] = None   # float64 [n, 2]
+
+    @property
+    def n_verts(self) -> int:
+        return self.rest_pos.shape[0]
+
+    @property
+    def n_tris(self) -> int:
+        return self.tris.shape[0]
+
+    def initial_iterate(self) -> np.ndarray:
+        x = np.array(self.x0, dtype=np.float64, copy=True)
+        x[self.dirichlet_idx] = self.dirichlet_x
+        return x
+
+
+def stretched_square(n: int, model: str = NEOHOOKEAN, stretch: float = 1.5, E: float = 1e4,
+                     nu: float = 0.3, diagonal: str = "uniform", density: float = 0.0,
+                     gravity=(0.0, 0.0), noise: float = 0.0, seed: int = 0) -> Scenario2D:
+    """The planar experiment of Sec. "PBNG vs. PBD and Limited Newton": a
+    unit square block (n x n vertices) whose left and right sides are pulled
+    apart to a total width `stretch` and clamped there (Dirichlet), while the
+    interior starts at its rest position (optionally jittered by `noise`
+    times the spacing, seeded), so the deformation has to propagate inward.
+    The figure shows large, medium and small stretches; the paper gives no
+    sizes or material values, so n, stretch, E and nu are free."""
+    X, T = square_mesh(n, n, 1.0 / (n - 1), diagonal)
+    col = np.arange(n * n) % n
+    left, right = np.nonzero(col == 0)[0], np.nonzero(col == n - 1)[0]
+    idx = np.concatenate([left, right]).astype(np.int32)
+    xd = X[idx].copy()
+    half = 0.5 * (stretch - 1.0)
+    xd[: left.size, 0] -= half
+    xd[left.size:, 0] += half
+    x0 = X.copy()
+    if noise > 0.0:
+        rng = np.random.default_rng(seed)
+        x0 += noise / (n - 1) * rng.uniform(-1.0, 1.0, size=x0.shape)
+    return Scenario2D(name="stretched_square_%d_%s" % (n, model), rest_pos=X, tris=T, model=model,
+                      E=np.asarray(E, np.float64), nu=np.asarray(nu, np.float64), dirichlet_idx=idx,
+                      dirichlet_x=xd, x0=x0, density=density, gravity=tuple(gravity))
