@@ -12,9 +12,10 @@ autotuner, run before the timed region.
 Prints one JSON line: vertex updates per second over the timed steps, the
 roofline of the dominant kernel (the colour-phase vertex update) measured
 live with HIP events on the launch stream, the FP64 oracle timed on the host
-cores on a bounded sample, and two sub-reports: batched cubes (one batched
-solve against per-instance solves, time to 1e-5) and the differentiable
-cubes (forward and adjoint sweeps).
+cores on a bounded sample, and sub-reports: batched cubes (one batched
+solve against per-instance solves, time to 1e-5), the differentiable cubes
+(forward and adjoint sweeps), the muscles, the paper's blocks, backward
+Euler, collisions and the planar (triangle-mesh) square.
 """
 import argparse
 import json
@@ -179,7 +180,8 @@ def main():
                    ("muscles", lambda: muscles_report(pbng, S, torch, stream)),
                    ("paper_blocks", lambda: paper_boxes_report(pbng, S, torch, stream)),
                    ("backward_euler", lambda: dynamics_report(pbng, S, torch, stream)),
-                   ("collisions", lambda: collision_report(pbng, S, torch, stream))]
+                   ("collisions", lambda: collision_report(pbng, S, torch, stream)),
+                   ("planar", lambda: planar_report(torch, stream))]
         for name, fn in reports:
             # a failing sub-report is recorded, not fatal to the headline line
             try:
@@ -488,6 +490,59 @@ def collision_report(pbng, S, torch, stream, frames=8):
             "iterations_per_frame": sub * iters, "ms_per_frame": round(tm * 1e3, 3),
             "contacts_per_frame_end": n_contacts, "colours": n_colors,
             "paper_ms_per_frame_cpu": 1630.0}
+
+
+def planar_report(torch, stream, n=1025, sweeps=200, roof_sweeps=20):
+    """The planar experiment of Sec. "PBNG vs. PBD and Limited Newton" on a
+    triangle mesh: an n x n-vertex unit square whose left and right sides
+    are pulled to 1.5 times its width and clamped, interior starting at rest
+    (Neo-Hookean, E = 1e4, nu = 0.3, uniform diagonals).  Plain FP32 sweeps
+    with the safeguard, FP64 residuals: the experiment compares plain PBNG
+    iterations, and with the initial stretch concentrated in the first
+    column of triangles (F about 250 at this size) the Chebyshev and SOR
+    blends diverge from 257^2 and 129^2 vertices on (oracle and GPU alike).
+    Reports vertex
+    updates per second over `sweeps` sweeps, the FP64 relative residual after
+    50 and after `sweeps` sweeps, and the HBM roofline of the planar
+    colour-phase kernel from HIP events on the launch stream."""
+    from paper_2306_09021_amd import pbng2d
+    from paper_2306_09021_amd import scenarios as S
+    sc = S.stretched_square(n, "nh", 1.5)
+    ws = pbng2d.Workspace2D(pbng2d.problem_from_scenario(sc), real="f32")
+    x0 = torch.tensor(sc.initial_iterate(), dtype=torch.float32, device="cuda")
+    kw = dict(accel="none", safeguard="backtrack", rel_tol=0.0)
+    x = x0.clone()
+    _, st50 = ws.solve(x, max_sweeps=50, check_every=50, stream=stream, **kw)
+    x.copy_(x0)
+    ws.solve(x, max_sweeps=sweeps, check_every=sweeps, stream=stream, **kw)   # warm-up
+    x.copy_(x0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = ws.solve(x, max_sweeps=sweeps, check_every=sweeps, stream=stream, **kw)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    opts = pbng2d.solve_opts(**kw)
+    ws.load(x0, stream=stream)
+    ws.sweeps(3, opts, stream=stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    ws.sweeps(roof_sweeps, opts, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    n_launch = roof_sweeps * ws.n_colors
+    avg = ev0.elapsed_time(ev1) * 1e-3 / n_launch
+    per_sweep = sum(ws.phase_bytes(c)[0] for c in range(ws.n_colors))
+    gbs = per_sweep / ws.n_colors / avg / 1e9
+    return {"workload": "stretched_square_%dx%d_neohookean" % (n, n), "vertices": ws.n_verts,
+            "triangles": ws.n_tris, "free_vertices": ws.n_free, "colours": ws.n_colors,
+            "sweeps": st["sweeps"], "ms_per_sweep": round(1e3 * el / sweeps, 4),
+            "vertex_updates_per_s": round(st["vertex_updates"] / el, 1),
+            "rel_residual_after_50": st50["rel_residual"], "rel_residual_after": st["rel_residual"],
+            "roofline": {"bound": "hbm", "kernel": "k2_phase (planar colour-phase vertex update)",
+                         "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg * 1e6, 2),
+                         "avg_algorithmic_bytes": int(per_sweep / ws.n_colors), "launches_timed": n_launch}}
 
 
 def cpu_baseline(sc, sweeps):

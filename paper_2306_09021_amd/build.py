@@ -18,7 +18,9 @@ UNITS = [("pbng_kernels.hip", ["-DPBNG_KERNEL_SET=0"], "kernels_f32.o"),
          ("pbng_kernels.hip", ["-DPBNG_KERNEL_SET=1"], "kernels_f64.o"),
          ("pbng_kernels.hip", ["-DPBNG_KERNEL_SET=2"], "kernels_mixed.o"),
          ("pbng_contacts.hip", [], "contacts.o"),
-         ("pbng_host.cpp", [], "host.o")]
+         ("pbng2d_kernels.hip", [], "planar_kernels.o"),
+         ("pbng_host.cpp", [], "host.o"),
+         ("pbng2d_host.cpp", [], "planar_host.o")]
 ARCH = os.environ.get("PBNG_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -51,7 +53,7 @@ def build(verbose: bool = False, out: str = LIB, extra=()) -> str:
         cmd += DEVICE if src.endswith(".hip") else ["-D__HIP_PLATFORM_AMD__"]
         cmds.append(cmd)
         objs.append(obj)
-    with ThreadPoolExecutor(max_workers=min(5, os.cpu_count() or 1)) as ex:
+    with ThreadPoolExecutor(max_workers=min(7, os.cpu_count() or 1)) as ex:
         for log in ex.map(_run, cmds):
             if verbose and log.strip():
                 print(log)

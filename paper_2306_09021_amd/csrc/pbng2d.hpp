@@ -1,0 +1,85 @@
+// Internal layout of a planar (triangle-mesh) libpbng workspace and its
+// kernel launchers.
+//
+// Vertex order on the device: free vertices first, grouped by colour, inside
+// a colour by decreasing valence (incident triangles) and then by caller
+// index; Dirichlet vertices follow in caller order.  Positions are R2
+// (float2 / double2) in that order.
+//
+// Per-visit records (one per (free vertex i, incident triangle e), CSR by
+// internal vertex through vptr), three packed streams indexed by visit k:
+//   jk[k] = {j, k}            internal indices of the other two vertices
+//   gm[k] = {dN_j, dN_k}      their rest-state shape-function gradients, so
+//                             that F = (x_j - x_i) dN_j^T + (x_k - x_i) dN_k^T
+//                             and dN_i = -(dN_j + dN_k)
+//   vw[k] = {A0 mu, A0 lambda}
+// 8 + 16 + 8 = 32 bytes per visit in float.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pbng_internal.hpp"
+
+namespace pbng {
+
+constexpr int kPlanarNeo = 0;
+constexpr int kPlanarCor = 1;
+
+// FP64 geometry of a triangle: rows dN_1, dN_2 of Dm^{-1}, rest area, Lame
+// parameters.
+struct TriGeo {
+    double g1x, g1y, g2x, g2y;
+    double A0, mu, lam;
+};
+
+template <class R>
+struct Sweep2Args {
+    using R2 = typename R2t<R>::T;
+    using R4 = typename R4t<R>::T;
+    R2* W;                  // working iterate (Gauss-Seidel, in place)
+    R2* P;                  // x^{l-1}                (acceleration only)
+    R2* N;                  // x^{l+1} being blended  (acceleration only)
+    const int* vptr;        // [n_free + 1]
+    const int2* jk;         // [n_visits]
+    const R4* gm;
+    const R2* vw;
+    const R2* fext;         // [n_free] lumped external force
+    int* rejected;          // [1]
+    R omega, gamma;
+    int max_halvings;
+};
+
+// FP64 residual / energy: per triangle V0 P dN_j (vp) and V0 Psi, per
+// vertex the force balance and -x . fhat.
+template <class R>
+struct Res2Args {
+    using R2 = typename R2t<R>::T;
+    const R2* X;            // internal order
+    const int4* tri;        // [n_tris] internal vertex indices (w unused)
+    const TriGeo* geo;
+    double* vp;             // [n_tris][3][2]
+    double* ebuf;           // [n_tris + n_verts] energy summands
+    const int* rvptr;       // [n_free + 1] visits of every free vertex
+    const int* rv;          // tri * 3 + slot
+    const double* fext64;   // [n_verts][2] internal order
+    const int* orig_of;     // [n_verts]
+    double* rsq;            // [n_verts] squared residual per vertex
+    int n_free, n_verts, n_tris, model;
+};
+
+template <class R>
+hipError_t launch_phase2(const Sweep2Args<R>& a, int model, int lanes, bool accel, bool safe, int vbeg,
+                         int vend, hipStream_t s);
+template <class R>
+hipError_t launch_residual2(const Res2Args<R>& a, double* r_out, hipStream_t s);
+template <class R>
+hipError_t launch_load2(const R* x_user, const int* orig_of, const typename R2t<R>::T* xd_int,
+                        typename R2t<R>::T* d0, typename R2t<R>::T* d1, typename R2t<R>::T* d2, int n_free,
+                        int n_verts, hipStream_t s);
+template <class R>
+hipError_t launch_store2(const typename R2t<R>::T* src, const int* orig_of, R* x_user, int n_verts,
+                         hipStream_t s);
+
+}  // namespace pbng

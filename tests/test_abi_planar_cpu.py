@@ -1,0 +1,82 @@
+"""Host-side checks of the planar C ABI (include/pbng2d.h) that need no GPU:
+every declared symbol is exported, the node colouring equals the planar
+oracle's bit for bit, and invalid problems are rejected with the documented
+status before any device work."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import planar as P
+from paper_2306_09021_amd import pbng, pbng2d
+from paper_2306_09021_amd import scenarios as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    with open(os.path.join(ROOT, "include", "pbng2d.h")) as f:
+        text = f.read()
+    return sorted(set(re.findall(r"^\s*int32_t\s+(pbng2d_\w+)\s*\(", text, re.M)))
+
+
+def test_library_exports_every_planar_symbol():
+    L = ctypes.CDLL(pbng.LIB_PATH)
+    names = header_functions()
+    assert len(names) == 11
+    for n in names:
+        assert hasattr(L, n), n
+    assert sorted(pbng2d.exported_symbols()) == names
+
+
+@pytest.mark.parametrize("diag", ["uniform", "alternate"])
+@pytest.mark.parametrize("n", [5, 17])
+def test_planar_color_bit_exact_vs_oracle(diag, n):
+    sc = S.stretched_square(n, "nh", 1.3, diagonal=diag, noise=0.2, seed=n)
+    c1, n1 = pbng2d.color(pbng2d.problem_from_scenario(sc))
+    c2, n2 = P.color(P.make_problem(sc))
+    assert n1 == n2 and np.array_equal(c1, c2)
+
+
+def _create_err(hp, colors=None, real="f32"):
+    with pytest.raises(pbng.PBNGError) as e:
+        pbng2d.Workspace2D(hp, colors=colors, real=real)
+    return e.value.code
+
+
+def test_planar_workspace_rejects_invalid_problems_before_device_work():
+    def fresh():
+        return pbng2d.problem_from_scenario(S.stretched_square(6, "corotated", 1.2))
+    hp = fresh()
+    hp.tris[0, [1, 2]] = hp.tris[0, [2, 1]]          # clockwise: negative area
+    assert _create_err(hp) == -2
+    hp = fresh()
+    hp.tris[2, 1] = hp.tris[2, 0]                    # repeated vertex
+    assert _create_err(hp) == -2
+    hp = fresh()
+    hp.tris[1, 2] = 10 ** 6                          # index out of range
+    assert _create_err(hp) == -2
+    hp = fresh()
+    hp.lam = 0.0                                      # lambda <= 0
+    assert _create_err(hp) == -3
+    hp = fresh()
+    hp.rest_pos[7, 0] = np.inf                        # non-finite input
+    assert _create_err(hp) == -5
+    hp = fresh()
+    hp.model = 2                                      # stable Neo-Hookean: not for d = 2
+    assert _create_err(hp) == -8
+    hp = fresh()
+    col, _ = pbng2d.color(hp)
+    col = col.copy()
+    t = next(t for t in hp.tris if (col[t] >= 0).sum() >= 2)
+    free = [v for v in t if col[v] >= 0]
+    col[free[1]] = col[free[0]]                       # two same-coloured vertices in a triangle
+    assert _create_err(hp, colors=col) == -4
+    hp = fresh()
+    s = hp.struct()
+    h = ctypes.c_void_p()
+    assert pbng2d.lib().pbng2d_workspace_create(ctypes.byref(s), None, pbng.REAL["mixed"],
+                                                ctypes.byref(h)) == -1
+    assert not h.value

@@ -1,0 +1,190 @@
+"""Planar (triangle-mesh) path on the GPU against the planar FP64 oracle:
+whole solves in FP64 and FP32 with every blend, the lanes-per-vertex
+variants, per-triangle materials and loads, safeguard decisions, the FP64
+residual / energy, degenerate problems, and one sweep plus the residual
+vector element by element at the full 1025 x 1025 size.
+
+Tolerances: FP64 1e-10 relative after the same sweeps (the kernel forms F
+from edge vectors, the oracle from positions: rounding-level differences);
+FP32 1e-5 (float positions and arithmetic against the FP64 oracle); FP64
+residual and energy 1e-10."""
+import numpy as np
+import pytest
+
+from oracle import planar as P
+from paper_2306_09021_amd import pbng2d
+from paper_2306_09021_amd import scenarios as S
+
+from .gpu_util import announce, host, rel_err, require_gpu, torch
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f64": 1e-10, "f32": 1e-5}
+
+
+@pytest.fixture(autouse=True)
+def _gpu():
+    require_gpu()
+
+
+def dev2(x, real):
+    dt = torch.float32 if real == "f32" else torch.float64
+    return torch.tensor(np.asarray(x, np.float64).reshape(-1, 2), dtype=dt, device="cuda").contiguous()
+
+
+def ws2(sc, real):
+    return pbng2d.Workspace2D(pbng2d.problem_from_scenario(sc), real=real)
+
+
+def both(sc, real, sweeps, **kw):
+    ws = ws2(sc, real)
+    op = P.make_problem(sc)
+    col = ws.colors()
+    xo, sto = P.solve(op, col, sc.initial_iterate(), max_sweeps=sweeps, **kw)
+    x = dev2(sc.initial_iterate(), real)
+    rc, st = ws.solve(x, max_sweeps=sweeps, rel_tol=0.0, check_every=sweeps, **kw)
+    return host(x), xo, st, sto, ws
+
+
+CASES = [dict(accel="none", safeguard="backtrack"),
+         dict(accel="chebyshev", rho=0.9, gamma=1.2, safeguard="backtrack"),
+         dict(accel="sor", omega=1.5, safeguard="none")]
+
+
+@pytest.mark.parametrize("model", ["nh", "corotated"])
+@pytest.mark.parametrize("real", ["f64", "f32"])
+@pytest.mark.parametrize("case", range(len(CASES)))
+def test_solve_parity(model, real, case):
+    kw = dict(CASES[case])
+    if real == "f32":
+        kw["safeguard"] = "none"   # FP32 and FP64 energy comparisons may differ at ties
+    sc = S.stretched_square(41, model, 1.5, noise=0.3, seed=case + 1)
+    announce("planar solve %s %s %s" % (model, real, kw))
+    xg, xo, st, sto, ws = both(sc, real, 30, **kw)
+    e = rel_err(xg, xo)
+    print("rel err", e, "oracle rel residual", sto["rel"])
+    assert e <= TOL[real]
+    assert st["sweeps"] == 30 and st["n_colors"] == ws.n_colors
+
+
+@pytest.mark.parametrize("diag", ["uniform", "alternate"])
+def test_lanes_variants_agree(diag):
+    sc = S.stretched_square(33, "nh", 1.4, diagonal=diag, noise=0.2, seed=5)
+    announce("planar lanes %s" % diag)
+    ws = ws2(sc, "f64")
+    op = P.make_problem(sc)
+    xo, _ = P.solve(op, ws.colors(), sc.initial_iterate(), max_sweeps=20, accel="chebyshev", rho=0.9,
+                    gamma=1.0)
+    for lanes in (1, 2, 4, 8, 16):
+        x = dev2(sc.initial_iterate(), "f64")
+        ws.solve(x, max_sweeps=20, rel_tol=0.0, check_every=20, accel="chebyshev", rho=0.9, gamma=1.0,
+                 lanes=lanes)
+        assert rel_err(host(x), xo) <= 1e-10, lanes
+
+
+@pytest.mark.parametrize("model", ["nh", "corotated"])
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_residual_and_energy(model, real):
+    sc = S.stretched_square(29, model, 1.6, density=30.0, gravity=(0.5, -9.8))
+    rng = np.random.default_rng(3)
+    x = sc.initial_iterate() + 0.01 * rng.normal(size=(sc.n_verts, 2))
+    x[sc.dirichlet_idx] = sc.dirichlet_x
+    xr = x.astype(np.float32).astype(np.float64) if real == "f32" else x
+    n_o, E_o, r_o = P.residual(P.make_problem(sc), xr)
+    announce("planar residual %s %s" % (model, real))
+    ws = ws2(sc, real)
+    rn, E, r = ws.residual(dev2(xr, real), want_r=True)
+    assert abs(rn - n_o) <= 1e-10 * n_o
+    assert abs(E - E_o) <= 1e-10 * abs(E_o)
+    assert np.abs(host(r) - r_o).max() <= 1e-10 * np.abs(r_o).max()
+
+
+def test_per_triangle_materials_and_loads():
+    sc = S.stretched_square(31, "nh", 1.3, noise=0.2, seed=7, density=100.0, gravity=(0.0, -9.8))
+    rng = np.random.default_rng(9)
+    sc.E = rng.uniform(5e3, 5e4, sc.n_tris)
+    sc.nu = rng.uniform(0.2, 0.45, sc.n_tris)
+    sc.nodal_force = 0.5 * rng.normal(size=(sc.n_verts, 2))
+    announce("planar per-triangle materials f64")
+    xg, xo, st, sto, _ = both(sc, "f64", 25, accel="chebyshev", rho=0.9, gamma=1.0)
+    assert rel_err(xg, xo) <= 1e-10
+    assert abs(st["residual"] - sto["res"]) <= 1e-8 * sto["res"]
+
+
+@pytest.mark.parametrize("model", ["nh", "corotated"])
+def test_safeguard_decisions_match(model):
+    """A hard start (stretch 2.5 with heavy jitter).  Neo-Hookean with
+    lambda < mu (nu = 0.05), where full steps can raise the local energy: the
+    kernel halves exactly where the oracle does (with lambda >= mu the full
+    step never does).  Corotated: the oracle never needs a halving (the
+    modified matrix majorises the local energy) and the kernel takes every
+    full step."""
+    nu = 0.05 if model == "nh" else 0.45
+    sc = S.stretched_square(25, model, 2.5, E=1e4, nu=nu, noise=0.6, seed=9)
+    announce("planar safeguard %s f64" % model)
+    xg, xo, st, sto, _ = both(sc, "f64", 15, accel="none", safeguard="backtrack")
+    assert rel_err(xg, xo) <= 1e-10
+    assert st["rejected"] == sto["rejected"]
+    if model == "nh":
+        assert sto["halvings"] > 0
+    else:
+        assert sto["halvings"] == 0 and sto["rejected"] == 0
+
+
+def test_convergence_to_tolerance():
+    sc = S.stretched_square(21, "corotated", 1.5)
+    announce("planar convergence f64")
+    ws = ws2(sc, "f64")
+    x = dev2(sc.initial_iterate(), "f64")
+    rc, st = ws.solve(x, max_sweeps=5000, rel_tol=1e-9, check_every=10, accel="chebyshev", rho=0.95,
+                      gamma=1.0)
+    assert rc == 0 and st["converged"] and st["rel_residual"] <= 1e-9
+    n_o, _, _ = P.residual(P.make_problem(sc), host(x))
+    assert n_o <= 1.01e-9 * st["residual0"]
+
+
+def test_degenerate_problems():
+    # every vertex prescribed: nothing to solve, zero residual
+    X, T = S.square_mesh(4, 4, 1.0 / 3)
+    idx = np.arange(16, dtype=np.int32)
+    sc = S.Scenario2D("all_dir", X, T, "nh", np.asarray(1e3), np.asarray(0.3), idx, 1.1 * X, X)
+    announce("planar all-Dirichlet")
+    ws = ws2(sc, "f64")
+    assert ws.n_free == 0 and ws.n_colors == 0
+    x = dev2(sc.initial_iterate(), "f64")
+    rc, st = ws.solve(x, max_sweeps=10, rel_tol=1e-8)
+    assert rc == 0 and st["sweeps"] == 0 and st["residual0"] == 0.0
+    assert np.array_equal(host(x), 1.1 * X)
+    # a single free vertex in the middle of a 3 x 3 patch
+    X, T = S.square_mesh(3, 3, 0.5)
+    bnd = np.array([0, 1, 2, 3, 5, 6, 7, 8], np.int32)
+    sc = S.Scenario2D("one_free", X, T, "corotated", np.asarray(1e3), np.asarray(0.3), bnd, X[bnd] * 1.2,
+                      X + np.array([0.1, -0.05]))
+    announce("planar single free vertex")
+    xg, xo, st, sto, ws = both(sc, "f64", 200)
+    assert ws.n_free == 1 and rel_err(xg, xo) <= 1e-12
+    assert np.abs(xg[4] - 1.2 * X[4]).max() <= 1e-9   # the affine patch solution
+
+
+@pytest.mark.parametrize("real", ["f32", "f64"])
+def test_full_size_one_sweep_and_residual(real):
+    """At the measured size (1025 x 1025 vertices, 2.1M triangles, NH) in the
+    launch configuration the benchmark times: one GPU sweep against one
+    oracle sweep over every vertex, and the FP64 residual vector."""
+    sc = S.stretched_square(1025, "nh", 1.5, noise=0.2, seed=1)
+    op = P.make_problem(sc)
+    announce("planar full size one sweep %s" % real)
+    ws = ws2(sc, real)
+    x0 = sc.initial_iterate()
+    xr = x0.astype(np.float32).astype(np.float64) if real == "f32" else x0
+    xo, _ = P.solve(op, ws.colors(), xr, max_sweeps=1, safeguard="none")
+    x = dev2(xr, real)
+    ws.solve(x, max_sweeps=1, rel_tol=0.0, check_every=1, safeguard="none", accel="none")
+    xg = host(x)
+    d = np.abs(xg - xo).max(axis=1)
+    scale = np.abs(xo - xr).max()
+    assert d.max() <= (1e-10 if real == "f64" else 1e-5) * max(scale, 1e-3) + (0.0 if real == "f64" else 1e-6)
+    rn, E, r = ws.residual(x, want_r=True)
+    n_o, E_o, r_o = P.residual(op, xg)
+    assert abs(rn - n_o) <= 1e-10 * n_o and abs(E - E_o) <= 1e-10 * abs(E_o)
+    assert np.abs(host(r) - r_o).max() <= 1e-9 * np.abs(r_o).max()
