@@ -30,6 +30,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "k_phase_beam_128x32x32_f32_counters.json")
+PLANAR_COUNTERS = os.path.join(ROOT, "profiles", "k2_phase_square_1025x1025_f32_counters.json")
 
 
 def parse():
@@ -52,6 +53,9 @@ def parse():
     ap.add_argument("--batched-subset", type=int, default=32,
                     help="instances solved one by one for the per-instance comparison")
     ap.add_argument("--diff-instances", type=int, default=64)
+    ap.add_argument("--planar-only", action="store_true",
+                    help="run only the planar (triangle-mesh) report and print it (profiling)")
+    ap.add_argument("--planar-sweeps", type=int, default=200)
     return ap.parse_args()
 
 
@@ -61,18 +65,21 @@ def progress(msg):
     print("[bench] %s" % msg, file=sys.stderr, flush=True)
 
 
-def traffic_per_launch():
-    """HBM bytes per k_phase launch from the committed counter profile, or
-    None when the kernel sources changed since it was taken."""
+def traffic_per_launch(path=COUNTERS, kernel="k_phase"):
+    """(HBM bytes per launch of `kernel`, note) from its committed counter
+    profile; bytes are None when the kernel sources changed since it was
+    taken (or there is no profile)."""
     try:
-        with open(COUNTERS) as f:
+        with open(path) as f:
             c = json.load(f)
     except (OSError, ValueError):
-        return None
+        return None, "no counter profile"
     from paper_2306_09021_amd.profsum import kernel_sources_sha256
-    if c.get("sources_sha256") != kernel_sources_sha256():
-        return None
-    return c.get("traffic_bytes_per_launch")
+    if c.get("sources_sha256") != kernel_sources_sha256(kernel):
+        return None, "kernel changed since the counter profile was taken"
+    note = ("bytes per launch from rocprofv3 FETCH_SIZE x%.3f + WRITE_SIZE x%.3f (scales from a copy "
+            "of known size)" % (c["fetch_scale"], c["write_scale"]))
+    return c.get("traffic_bytes_per_launch"), note
 
 
 def main():
@@ -97,6 +104,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.planar_only:
+        print(json.dumps({"planar": planar_report(torch, stream, sweeps=args.planar_sweeps)}))
+        return
 
     sc = S.config_beam_f32()
     # SOR omega = 1.6: the Chebyshev rho = 0.995 / relaxation 1.6 reading
@@ -159,11 +169,11 @@ def main():
         total_bytes += args.roofline_sweeps * (b + 48 * v)
     avg_bytes = total_bytes / n_launch
     achieved = avg_bytes / avg_dur / 1e9
-    tr = traffic_per_launch()
+    tr, tr_note = traffic_per_launch()
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": (int(tr) if tr is not None else None),
-                "traffic_note": "bytes per launch from rocprofv3 FETCH_SIZE x2.0 + WRITE_SIZE x1.0",
+                "traffic_note": tr_note,
                 "kernel": "k_phase (colour-phase vertex update)",
                 "avg_launch_us": round(avg_dur * 1e6, 2),
                 "avg_algorithmic_bytes": int(avg_bytes), "launches_timed": n_launch}
@@ -181,7 +191,7 @@ def main():
                    ("paper_blocks", lambda: paper_boxes_report(pbng, S, torch, stream)),
                    ("backward_euler", lambda: dynamics_report(pbng, S, torch, stream)),
                    ("collisions", lambda: collision_report(pbng, S, torch, stream)),
-                   ("planar", lambda: planar_report(torch, stream))]
+                   ("planar", lambda: planar_report(torch, stream, sweeps=args.planar_sweeps))]
         for name, fn in reports:
             # a failing sub-report is recorded, not fatal to the headline line
             try:
@@ -521,19 +531,27 @@ def planar_report(torch, stream, n=1025, sweeps=200, roof_sweeps=20):
     _, st = ws.solve(x, max_sweeps=sweeps, check_every=sweeps, stream=stream, **kw)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    opts = pbng2d.solve_opts(**kw)
-    ws.load(x0, stream=stream)
-    ws.sweeps(3, opts, stream=stream)
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record(stream)
-    ws.sweeps(roof_sweeps, opts, stream=stream)
-    ev1.record(stream)
-    torch.cuda.synchronize()
+
+    def launch_time(opts, n_sweeps):
+        """Average colour-phase launch duration over n_sweeps back-to-back
+        sweeps, HIP events on the launch stream."""
+        ws.load(x0, stream=stream)
+        ws.sweeps(3, opts, stream=stream)
+        ev0.record(stream)
+        ws.sweeps(n_sweeps, opts, stream=stream)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) * 1e-3 / (n_sweeps * ws.n_colors)
+
+    lanes_us = {l: round(1e6 * launch_time(pbng2d.solve_opts(lanes=l, **kw), 10), 2) for l in (2, 4, 8)}
+    opts = pbng2d.solve_opts(**kw)           # the library's default: 4 lanes per vertex
+    avg = launch_time(opts, roof_sweeps)
     n_launch = roof_sweeps * ws.n_colors
-    avg = ev0.elapsed_time(ev1) * 1e-3 / n_launch
     per_sweep = sum(ws.phase_bytes(c)[0] for c in range(ws.n_colors))
     gbs = per_sweep / ws.n_colors / avg / 1e9
+    tr, tr_note = traffic_per_launch(PLANAR_COUNTERS, "k2_phase")
     return {"workload": "stretched_square_%dx%d_neohookean" % (n, n), "vertices": ws.n_verts,
             "triangles": ws.n_tris, "free_vertices": ws.n_free, "colours": ws.n_colors,
             "sweeps": st["sweeps"], "ms_per_sweep": round(1e3 * el / sweeps, 4),
@@ -541,8 +559,12 @@ def planar_report(torch, stream, n=1025, sweeps=200, roof_sweeps=20):
             "rel_residual_after_50": st50["rel_residual"], "rel_residual_after": st["rel_residual"],
             "roofline": {"bound": "hbm", "kernel": "k2_phase (planar colour-phase vertex update)",
                          "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                         "frac": round(gbs / HBM_PEAK_GBS, 4), "avg_launch_us": round(avg * 1e6, 2),
-                         "avg_algorithmic_bytes": int(per_sweep / ws.n_colors), "launches_timed": n_launch}}
+                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": (int(tr) if tr is not None else None),
+                         "traffic_note": tr_note,
+                         "avg_launch_us": round(avg * 1e6, 2),
+                         "avg_algorithmic_bytes": int(per_sweep / ws.n_colors), "launches_timed": n_launch},
+            "launch_us_by_lanes": lanes_us}
 
 
 def cpu_baseline(sc, sweeps):

@@ -21,12 +21,18 @@ import json
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = ["pbng_kernels.hip", "pbng_math.hpp", "pbng_internal.hpp"]
+# sources that define each profiled kernel (a change to any of them makes the
+# counter profile stale)
+KERNEL_SOURCES = {
+    "k_phase": ["pbng_kernels.hip", "pbng_math.hpp", "pbng_internal.hpp", "pbng_device.hpp"],
+    "k2_phase": ["pbng2d_kernels.hip", "pbng2d.hpp", "pbng_math.hpp", "pbng_internal.hpp",
+                 "pbng_device.hpp"],
+}
 
 
-def kernel_sources_sha256() -> str:
+def kernel_sources_sha256(kernel: str = "k_phase") -> str:
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kernel]:
         with open(os.path.join(HERE, "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()
@@ -68,14 +74,14 @@ def counters(a):
     write = _dispatches(a.write, "WRITE_SIZE")
     fs, fvals = _copy_scale(fetch, copy_kib, "FETCH_SIZE")
     ws, wvals = _copy_scale(write, copy_kib, "WRITE_SIZE")
-    fk = [d for d in fetch if a.kernel in d[1]][-a.last:]
-    wk = [d for d in write if a.kernel in d[1]][-a.last:]
+    fk = [d for d in fetch if (a.kernel + "<") in d[1]][-a.last:]
+    wk = [d for d in write if (a.kernel + "<") in d[1]][-a.last:]
     if len(fk) < a.last or len(wk) < a.last:
         raise RuntimeError("fewer than %d %s dispatches" % (a.last, a.kernel))
     f_mean = sum(d[3] for d in fk) / len(fk) * 1024.0 * fs
     w_mean = sum(d[3] for d in wk) / len(wk) * 1024.0 * ws
-    res = {"kernel": a.kernel + " " + a.workload, "sources": KERNEL_SOURCES,
-           "sources_sha256": kernel_sources_sha256(), "fetch_scale": fs, "write_scale": ws,
+    res = {"kernel": a.kernel + " " + a.workload, "sources": KERNEL_SOURCES[a.kernel],
+           "sources_sha256": kernel_sources_sha256(a.kernel), "fetch_scale": fs, "write_scale": ws,
            "fetch_bytes_per_launch": f_mean, "write_bytes_per_launch": w_mean,
            "traffic_bytes_per_launch": f_mean + w_mean, "launches": a.last}
     with open(a.json, "w") as f:
@@ -90,7 +96,7 @@ def counters(a):
         out = ["| %s: kernel | grid | dispatches | raw KiB per launch | scaled MB per launch |" % title,
                "|---|---|---|---|---|"]
         for (name, grid), (n, s) in agg.items():
-            out.append("| `%s` | %d | %d | %.0f | %.2f |" % (name.split("(")[0], grid, n, s / n,
+            out.append("| `%s` | %d | %d | %.0f | %.2f |" % (short_name(name), grid, n, s / n,
                                                             s / n * 1024 * scale / 1e6))
         return out
 
@@ -112,6 +118,14 @@ def counters(a):
     print(json.dumps(res))
 
 
+def short_name(name: str) -> str:
+    """Kernel name without return type, anonymous namespace and arguments."""
+    name = name.replace("(anonymous namespace)::", "")
+    if name.startswith("void "):
+        name = name[5:]
+    return name.split("(")[0]
+
+
 def stats(a):
     rows = _rows(a.stats, "kernel_stats.csv")
     rows.sort(key=lambda r: -float(r["Percentage"]))
@@ -119,7 +133,7 @@ def stats(a):
              "Kernel statistics (`kernel_stats.csv`), top %d by total time:" % a.top, "",
              "| kernel | calls | avg ns | % time |", "|---|---|---|---|"]
     for r in rows[:a.top]:
-        lines.append("| `%s` | %s | %.0f | %.2f |" % (r["Name"].split("(")[0], r["Calls"],
+        lines.append("| `%s` | %s | %.0f | %.2f |" % (short_name(r["Name"]), r["Calls"],
                                                      float(r["AverageNs"]), float(r["Percentage"])))
     if a.match:
         sel = [r for r in rows if a.match in r["Name"]]
@@ -129,7 +143,7 @@ def stats(a):
                                                                         tot / max(calls, 1))]
         lines += ["", "| variant | calls | avg ns |", "|---|---|---|"]
         for r in sel:
-            lines.append("| `%s` | %s | %.0f |" % (r["Name"].split("(")[0], r["Calls"],
+            lines.append("| `%s` | %s | %.0f |" % (short_name(r["Name"]), r["Calls"],
                                                   float(r["AverageNs"])))
     with open(a.md, "w") as f:
         f.write("\n".join(lines) + "\n")
