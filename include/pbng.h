@@ -364,12 +364,13 @@ int32_t pbng_adjoint(pbng_workspace* ws, const void* x_eq, const void* dL_dx, do
                      const pbng_adjoint_opts* o, pbng_stats* stats, void* hip_stream);
 
 /*
- * Autotuner: on the iterate x (device, position type), times every colour
- * phase of the workspace for each lanes-per-vertex candidate (1 .. 64 around
- * the colour's mean visit count, best of 3 x 8 launches) and keeps the
- * fastest per colour as the workspace's automatic choice (o->lanes = 0),
- * then times 64 sweeps as plain launches and as replays of graphs of 2, 8
- * and 32 sweeps.  *tuned receives *o with lanes = 0 and the chosen
+ * Autotuner: on the iterate x (device, position type), times, colour by
+ * colour, each lanes-per-vertex candidate (1 .. 64 around the colour's mean
+ * visit count) inside whole sweeps (best of 3 x 16 sweeps, the other colours
+ * at their current choice) and keeps a candidate only when it beats the
+ * automatic heuristic by more than 2%; the result becomes the workspace's
+ * automatic choice (o->lanes = 0).  It then times 64 sweeps as plain
+ * launches and as replays of graphs of 2, 8 and 32 sweeps.  *tuned receives *o with lanes = 0 and the chosen
  * sweeps_per_graph; lanes_out [n_colors] (host, nullable) the lanes per
  * colour.  hip_stream must not be NULL.  The workspace's internal iterate is
  * left undefined (the next pbng_solve reloads it).

@@ -1480,26 +1480,34 @@ void autotune_t(pbng_workspace* ws, const void* x, const pbng_solve_opts* o, pbn
     };
     reload();
     Events ev;
-    const bool accel = o->accel != PBNG_ACCEL_NONE;
-    const bool safe = safe_effective(ws, o);
-    const SweepArgs<R, PR> a = sweep_args<R, PR>(ws, 1.0, 1.0, o->max_halvings);
+    pbng_solve_opts q = *o;
+    q.lanes = 0;
+    // Lanes per colour: each candidate is timed inside whole sweeps (the
+    // other colours at their current choice), so that the caches see the
+    // solve's mix of phases; the valence heuristic stays unless a candidate
+    // beats it by more than timing noise.
+    auto time_sweeps = [&]() {
+        float t = 1e30f;
+        for (int trial = 0; trial < 3; ++trial) {
+            hipchk(hipEventRecord(ev.a, s), "record");
+            for (int k = 0; k < 16; ++k) launch_sweep<R, PR>(ws, &q, 1.0, 1.0, s);
+            hipchk(hipEventRecord(ev.b, s), "record");
+            t = std::min(t, ev.ms());
+        }
+        return t;
+    };
     for (int c = 0; c < ws->ncol; ++c) {
         const int vb = ws->col_ptr[c], ve = ws->col_ptr[c + 1];
         if (ve <= vb) continue;
         const double mv = double(ws->phase_visits[c]) / double(ve - vb);
-        int best = ws->phase_lanes[c];
-        float best_t = 1e30f;
+        const int heur = ws->phase_lanes[c];
+        int best = heur;
+        float best_t = time_sweeps();
         for (int L = 1; L <= 64; L *= 2) {
-            if (L > 2 * mv + 1 || 16 * L < mv) continue;
-            float t = 1e30f;
-            for (int trial = 0; trial < 3; ++trial) {
-                hipchk(hipEventRecord(ev.a, s), "record");
-                for (int r = 0; r < 8; ++r)
-                    hipchk(launch_phase<R, PR>(a, ws->kmodel, L, accel, safe, ws->general(), vb, ve, s), "phase");
-                hipchk(hipEventRecord(ev.b, s), "record");
-                t = std::min(t, ev.ms());
-            }
-            if (t < best_t) {
+            if (L == heur || L > 2 * mv + 1 || 16 * L < mv) continue;
+            ws->phase_lanes[c] = L;
+            const float t = time_sweeps();
+            if (t < 0.98f * best_t) {
                 best_t = t;
                 best = L;
             }
@@ -1508,8 +1516,6 @@ void autotune_t(pbng_workspace* ws, const void* x, const pbng_solve_opts* o, pbn
     }
     ws->lanes_version++;
     // sweeps per graph: plain launches against replayed graphs
-    pbng_solve_opts q = *o;
-    q.lanes = 0;
     const int n_sw = 64;
     int best_S = 0;
     float best_t = 1e30f;
