@@ -349,7 +349,11 @@ void build2(pbng2d_workspace* ws, const pbng2d_problem* p, const int32_t* colors
     for (int i = 0; i < p->n_verts; ++i)
         if (col[i] >= 0) ws->cptr[col[i] + 1]++;
     for (int c = 0; c < ws->ncol; ++c) ws->cptr[c + 1] += ws->cptr[c];
-    if (int64_t(3) * ws->nt * int64_t(sizeof(double4)) >= (int64_t(1) << 32))
+    // kernels address the visit streams and positions through 32-bit byte
+    // offsets: the largest stream (FP64 shape gradients, 32 B per visit, at
+    // most three visits per triangle) and the FP64 positions must stay below 4 GiB
+    if (int64_t(3) * ws->nt * int64_t(sizeof(double4)) >= (int64_t(1) << 32) ||
+        ws->nv * int64_t(sizeof(double2)) >= (int64_t(1) << 32))
         fail(PBNG_EUNSUPPORTED, "mesh too large for 32-bit stream offsets");
     if (real == PBNG_F64) pack<double>(ws, p, I, int_of);
     else pack<float>(ws, p, I, int_of);
