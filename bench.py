@@ -374,7 +374,9 @@ def differentiable_report(pbng, S, torch, stream, n_inst):
     ta = time.perf_counter() - t0
     fw_upd = sum(s["vertex_updates"] for s in st)
     ad_upd = sum(s["vertex_updates"] for s in sta)
+    others = {m: _adjoint_model(pbng, S, torch, stream, m, so, ao) for m in ("corotated", "snh")}
     return {"instances": len(scs), "vertices": int(x0.shape[0]), "real": "mixed",
+            "other_models_8_instances": others,
             "forward": {"rel_tol": 1e-5, "wall_s": round(tf, 3),
                         "converged": int(sum(s["converged"] for s in st)),
                         "max_sweeps_used": int(max(s["sweeps"] for s in st)),
@@ -385,6 +387,39 @@ def differentiable_report(pbng, S, torch, stream, n_inst):
                         "max_sweeps_used": int(max(s["sweeps"] for s in sta)),
                         "max_rel_residual": max(s["rel_residual"] for s in sta),
                         "vertex_updates_per_s": round(ad_upd / ta, 1)}}
+
+
+def _adjoint_model(pbng, S, torch, stream, model, so, ao, n_inst=8):
+    """Forward and adjoint solves to 1e-5 for the first n_inst differentiable
+    cubes with another model (the adjoint's diagonal blocks are then the
+    modified matrices A_ii)."""
+    scs = S.config_differentiable(n_inst)
+    for sc in scs:
+        sc.model = model
+    ws = pbng.Workspace([pbng.problem_from_scenario(s) for s in scs], real="mixed")
+    x = torch.tensor(pbng.concat_positions([s.initial_iterate() for s in scs]), dtype=torch.float64,
+                     device="cuda")
+    T = torch.tensor(pbng.concat_positions([s.loss_target for s in scs]), dtype=torch.float64, device="cuda")
+    free = np.ones((x.shape[0], 1))
+    off = 0
+    for s in scs:
+        free[off + s.dirichlet_idx] = 0.0
+        off += s.n_verts
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = ws.solve(x, so, stream=stream)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t0
+    g = (2.0 * (x - T) * torch.tensor(free, dtype=torch.float64, device="cuda")).contiguous()
+    t0 = time.perf_counter()
+    _, _, sta = ws.adjoint(x, g, ao, stream=stream, want=("xd", "mu", "lam"))
+    torch.cuda.synchronize()
+    ta = time.perf_counter() - t0
+    return {"forward_wall_s": round(tf, 3), "forward_converged": int(sum(s["converged"] for s in st)),
+            "forward_max_sweeps": int(max(s["sweeps"] for s in st)),
+            "adjoint_wall_s": round(ta, 3), "adjoint_converged": int(sum(s["converged"] for s in sta)),
+            "adjoint_max_sweeps": int(max(s["sweeps"] for s in sta)),
+            "adjoint_max_rel_residual": max(s["rel_residual"] for s in sta)}
 
 
 def muscles_report(pbng, S, torch, stream):
@@ -584,7 +619,21 @@ def planar_report(torch, stream, n=1025, sweeps=200, roof_sweeps=20):
     per_sweep = sum(ws.phase_bytes(c)[0] for c in range(ws.n_colors))
     gbs = per_sweep / ws.n_colors / avg / 1e9
     tr, tr_note = traffic_per_launch(PLANAR_COUNTERS, "k2_phase")
+    # the corotated model on the same square (rotation of each 2x2 F per visit)
+    scc = S.stretched_square(n, "corotated", 1.5)
+    wsc = pbng2d.Workspace2D(pbng2d.problem_from_scenario(scc), real="f32")
+    xc = x0.clone()
+    wsc.solve(xc, max_sweeps=20, check_every=20, stream=stream, **kw)                 # warm-up
+    xc.copy_(x0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, stc = wsc.solve(xc, max_sweeps=sweeps, check_every=sweeps, stream=stream, **kw)
+    torch.cuda.synchronize()
+    elc = time.perf_counter() - t0
     return {"workload": "stretched_square_%dx%d_neohookean" % (n, n), "vertices": ws.n_verts,
+            "corotated": {"ms_per_sweep": round(1e3 * elc / sweeps, 4),
+                          "vertex_updates_per_s": round(stc["vertex_updates"] / elc, 1),
+                          "rel_residual_after": stc["rel_residual"]},
             "triangles": ws.n_tris, "free_vertices": ws.n_free, "colours": ws.n_colors,
             "sweeps": st["sweeps"], "ms_per_sweep": round(1e3 * el / sweeps, 4),
             "vertex_updates_per_s": round(st["vertex_updates"] / el, 1),
