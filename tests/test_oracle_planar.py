@@ -253,3 +253,25 @@ def test_blends_that_reduce_to_the_plain_iteration(kw):
     assert np.abs(a - b).max() <= 1e-13
     c, _ = P.solve(op, col, sc.initial_iterate(), max_sweeps=25, accel="sor", omega=1.5)
     assert np.abs(a - c).max() > 1e-6
+
+
+def test_modified_density_is_spd_for_every_F():
+    """Eq. (mod_hess_dens) with d = 2 as a 4 x 4 matrix on vec(dF): SPD for
+    regular, inverted, rank-one and zero F (mu, lambda > 0)."""
+    mats = [rand_F2(1), rand_F2(-1), np.outer(RNG.normal(size=2), RNG.normal(size=2)), np.zeros((2, 2))]
+    for F in mats:
+        C = P.mod_hess_density(2.0, 7.0, F).reshape(4, 4)
+        assert np.abs(C - C.T).max() <= 1e-14 * np.abs(C).max()
+        assert np.linalg.eigvalsh(C).min() >= 2 * 2.0 * (1 - 1e-12)   # >= 2 mu
+
+
+def test_energies_at_rotations():
+    """The corotated energy vanishes on rotations; the Neo-Hookean one is its
+    constant rest value 1/2 mu d + 1/2 lhat (mu / lhat)^2 there."""
+    mu, lam = 1.7, 3.1
+    lh = mu + lam
+    for _ in range(5):
+        t = RNG.uniform(-np.pi, np.pi)
+        Q = np.array([[np.cos(t), -np.sin(t)], [np.sin(t), np.cos(t)]])
+        assert abs(P.psi(P.COROTATED, mu, lam, Q)) <= 1e-14
+        assert abs(P.psi(P.NEOHOOKEAN, mu, lam, Q) - (mu + 0.5 * lh * (mu / lh) ** 2)) <= 1e-13
