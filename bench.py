@@ -291,6 +291,25 @@ def batched_report(pbng, S, torch, stream, subset):
                 "vertex_updates_per_s": round(sum(s["vertex_updates"] for s in st) / t, 1),
                 "not_converged_rel_residual": [round(s["rel_residual"], 8) for s in st
                                                if not s["converged"]]})
+    # the batched sweep's roofline: back-to-back sweeps (all instances in
+    # every colour phase) timed with HIP events on the launch stream, over
+    # the algorithmic bytes of the phases plus the blend
+    ws.load(x0, stream=stream)
+    ws.sweeps(3, opts, stream=stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    n_sw = 10
+    ev0.record(stream)
+    ws.sweeps(n_sw, opts, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    sweep_s = ev0.elapsed_time(ev1) * 1e-3 / n_sw
+    per_sweep = sum(ws.phase_bytes(c)[0] + 48 * ws.phase_bytes(c)[1] for c in range(ws.n_colors))
+    out["sweep"] = {"ms": round(sweep_s * 1e3, 4), "colours": ws.n_colors,
+                    "algorithmic_bytes": int(per_sweep),
+                    "achieved_GBs": round(per_sweep / sweep_s / 1e9, 1),
+                    "frac_of_hbm_peak": round(per_sweep / sweep_s / 1e9 / HBM_PEAK_GBS, 4),
+                    "bound": "valu (corotated polar decomposition per visit)"}
     # subset: batched vs one instance at a time
     rng = np.random.default_rng(44)
     idx = sorted(rng.choice(len(scs), size=min(subset, len(scs)), replace=False).tolist())
