@@ -391,6 +391,34 @@ def test_muscle_standin_full_sampled_phase():
     assert np.abs(upd - xg[pick]).max() <= tol
 
 
+def test_batched_full_size_sampled_instances():
+    """The batched configuration at full size (256 corotated cubes of 4^3 to
+    32^3 vertices, 2.6M vertices, 11.5M tets) in the benchmark's launch
+    configuration (PBNG_MIXED, one launch per colour over all instances,
+    Chebyshev blend): one GPU sweep over everything, then 8 instances (the
+    largest among them) each against one oracle sweep of that instance alone.
+    Without the safeguard, whose accept/halve choice is discrete."""
+    scs = S.config_batched()
+    announce("batched full size, 256 instances, one sweep mixed")
+    ws = workspace(scs, "mixed")
+    x0 = pbng.concat_positions([s.initial_iterate() for s in scs])
+    x = dev_x(x0, "mixed")
+    kw = dict(accel="chebyshev", rho=0.95, gamma=1.7, safeguard="none")
+    ws.solve(x, max_sweeps=1, rel_tol=0.0, check_every=1, **kw)
+    xg = host(x)
+    off = np.cumsum([0] + [s.n_verts for s in scs])
+    rng = np.random.default_rng(7)
+    pick = set(rng.choice(len(scs), 7, replace=False).tolist())
+    pick.add(int(np.argmax([s.n_verts for s in scs])))
+    for q in sorted(pick):
+        op = O.make_problem(scs[q])
+        col, _ = O.color(op)
+        xo, _ = O.solve(op, col, scs[q].initial_iterate(), max_sweeps=1, n_threads=4, **kw)
+        e = rel_err(xg[off[q]:off[q + 1]], xo)
+        print("instance", q, scs[q].n_verts, "vertices, rel err", e)
+        assert e <= 1e-5, q
+
+
 def test_material_update_reenables_safeguard():
     """A Neo-Hookean workspace built with lambda >= mu in every tet skips the
     safeguard (the step is then a descent step); after a material update to
