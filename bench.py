@@ -116,7 +116,7 @@ def main():
     if args.max_sweeps > 0:
         sopts["max_sweeps"] = args.max_sweeps
     cfg = {"workload": "beam_128x32x32_neohookean_gravity", "vertices": sc.n_verts,
-           "tets": sc.n_tets, "free_vertices": sc.n_free, "model": "neo-hookean",
+           "tets": sc.n_tets, "free_vertices": sc.n_free, "constitutive_model": "neo-hookean",
            "E": 1e5, "nu": 0.45, "density": 1000.0, "accel": "sor omega=1.6",
            "safeguard": "backtrack", "rel_tol": 1e-5, "max_sweeps": sopts["max_sweeps"],
            "positions": "f32", "sweep_arithmetic": "f32", "residual": "f64"}
