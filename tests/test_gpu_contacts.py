@@ -119,3 +119,21 @@ def test_backward_euler_steps_with_detection():
         assert rel_err(host(xg), xo) <= 1e-10, step
         x_prev, x_n = x_n, xo
     assert max(n_contacts) > 0
+
+
+def test_detection_overflow_is_reported_and_recoverable():
+    """More pairs than max_pairs: the call fails with PBNG_EINVAL (nothing is
+    written past max_pairs), and a following call with room, which grows the
+    scratch, returns the full sorted set."""
+    from paper_2306_09021_amd import pbng
+    sc, x = near_blocks()
+    op = O.make_problem(sc)
+    ref_p, _ = brute_contacts(x, sc.tets, op.is_dir, 0.05)
+    assert ref_p.shape[0] > 8
+    announce("contact detection overflow then growth")
+    ws = workspace([sc], "f64")
+    with pytest.raises(pbng.PBNGError) as e:
+        ws.detect_contacts(dev_x(x, "f64"), 0.05, max_pairs=4)
+    assert e.value.code == -1
+    pairs, _ = ws.detect_contacts(dev_x(x, "f64"), 0.05, max_pairs=8192)
+    assert np.array_equal(host(pairs).astype(np.int64), ref_p.astype(np.int64))
