@@ -244,6 +244,48 @@ def test_sampled_vertex_updates_full_beam():
     assert d <= 1e-5 * np.abs(upd - before[pick]).max() + 1e-6
 
 
+def test_paper_block_128_full_sampled_phase():
+    """The paper's largest stretching block (128^3 vertices, 10.2M tets,
+    corotated, frame-1 targets, interior jittered by 1e-3 of the spacing) in
+    the benchmark's launch configuration (FP32, single-instance kernel): all
+    colour phases but the last on the GPU, then the last one, and 64 sampled
+    vertices of it recomputed one by one by the oracle from the GPU's own
+    positions before that phase.
+    Without the safeguard (the corotated step never needs it; the oracle's
+    energy comparison can still halve a rounding-level step)."""
+    sc, _ = S.paper_box_frames(128, "corotated", n_frames=60)
+    announce("paper block 128^3 corotated sampled phase")
+    ws = workspace([sc], "f32")
+    rng = np.random.default_rng(5)
+    x0 = sc.initial_iterate() + 1e-3 * rng.normal(size=(sc.n_verts, 3)) / 127.0
+    x0[sc.dirichlet_idx] = sc.dirichlet_x
+    x0 = x0.astype(np.float32).astype(np.float64)
+    x = dev_x(x0, "f32")
+    ws.load(x)
+    last = ws.n_colors - 1
+    for c in range(last):
+        ws.phase(c, safeguard="none")
+    xs = dev_x(np.zeros_like(x0), "f32")
+    ws.store(xs)
+    torch.cuda.synchronize()
+    before = host(xs)
+    ws.phase(last, safeguard="none")
+    ws.store(xs)
+    torch.cuda.synchronize()
+    xg = host(xs)
+    op = O.make_problem(sc)
+    col, _ = O.color(op)
+    verts = np.nonzero(col == last)[0]
+    pick = rng.choice(verts, 64, replace=False)
+    upd = O.update_vertices(op, before, pick, safeguard="none")
+    step = np.abs(upd - before[pick]).max()
+    tol = 1e-4 * step + 4 * np.finfo(np.float32).eps * np.abs(before[pick]).max()
+    assert np.abs(upd - xg[pick]).max() <= tol
+    # vertices of the other colours are untouched by the last phase
+    other = np.nonzero(col != last)[0]
+    assert np.array_equal(xg[other], before[other])
+
+
 @pytest.mark.parametrize("model", ["nh", "corotated"])
 def test_mixed_parity(model):
     """FP32 arithmetic on an FP64 master copy of the positions."""
