@@ -137,3 +137,42 @@ def test_detection_overflow_is_reported_and_recoverable():
     assert e.value.code == -1
     pairs, _ = ws.detect_contacts(dev_x(x, "f64"), 0.05, max_pairs=8192)
     assert np.array_equal(host(pairs).astype(np.int64), ref_p.astype(np.int64))
+
+
+def test_colliding_blocks_full_size_substep():
+    """The benchmark's collision workload at its size (two 16^3 corotated
+    blocks, 8192 vertices, 33,750 tets, PBNG_MIXED): with the right block
+    pushed into contact range, detection against brute force, the
+    recolouring against the oracle's, then one substep (dt = 1/510 s,
+    k_n = 1e8, 8 Chebyshev iterations, no safeguard) against the oracle run
+    with the same contacts, colouring and inertia."""
+    sc = S.two_blocks(16, gap=0.02, model="corotated", drive=0.0)
+    x = sc.initial_iterate()
+    half = sc.n_verts // 2
+    x[half:, 0] -= 0.03
+    x[sc.dirichlet_idx] = sc.dirichlet_x
+    op = O.make_problem(sc)
+    radius, kn, dt = 0.03, 1e8, 1.0 / 30.0 / 17.0
+    ref_p, ref_n = brute_contacts(x, sc.tets, op.is_dir, radius)
+    assert ref_p.shape[0] > 50
+    announce("colliding blocks 2 x 16^3 one substep mixed")
+    ws = workspace([sc], "mixed")
+    xg = dev_x(x, "mixed")
+    pairs, normals = ws.detect_contacts(xg, radius, max_pairs=1 << 16)
+    assert np.array_equal(host(pairs).astype(np.int64), ref_p.astype(np.int64))
+    assert np.abs(host(normals) - ref_n).max() <= 1e-12
+    col0 = ws.colors()
+    ws.set_contacts(pairs, normals, kn)
+    op2 = O.make_problem(add_contacts(sc, ref_p, ref_n, kn))
+    nodes = np.unique(ref_p.reshape(-1))
+    nodes = nodes[op2.is_dir[nodes] == 0]
+    ref_col, _ = O.recolor(op2, col0, nodes)
+    assert np.array_equal(ws.colors(), ref_col)
+    x_prev = x - 1e-4
+    x_prev[sc.dirichlet_idx] = sc.dirichlet_x
+    ws.set_inertia(dt, torch.tensor(x, device="cuda"), torch.tensor(x_prev, device="cuda"))
+    kw = dict(accel="chebyshev", rho=0.95, gamma=1.2, safeguard="none")
+    ws.solve(xg, max_sweeps=8, rel_tol=0.0, check_every=8, **kw)
+    op2.set_inertia(dt, x, x_prev)
+    xo, _ = O.solve(op2, ws.colors(), x, max_sweeps=8, **kw)
+    assert rel_err(host(xg), xo) <= 1e-5

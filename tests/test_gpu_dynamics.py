@@ -197,3 +197,28 @@ def test_graph_replay_with_inertia():
         outs.append(res)
     for a, b in zip(*outs):
         assert torch.equal(a, b)
+
+
+def test_full_beam_backward_euler_sweep():
+    """The benchmark's backward-Euler workload at full size (128x32x32 beam,
+    dt = 1/30 s, FP32, the benchmark's launch configuration): one sweep with
+    inertia on the GPU against one oracle sweep over every vertex."""
+    sc = S.config_beam_f32()
+    rng = np.random.default_rng(12)
+    x_n = sc.initial_iterate() + 1e-3 * rng.normal(size=(sc.n_verts, 3))
+    x_n[sc.dirichlet_idx] = sc.dirichlet_x
+    x_n = x_n.astype(np.float32).astype(np.float64)
+    x_prev = x_n - 1e-4 * rng.normal(size=x_n.shape)
+    dt = 1.0 / 30.0
+    announce("full beam backward Euler one sweep f32")
+    ws = workspace([sc], "f32")
+    ws.set_inertia(dt, t64(x_n), t64(x_prev))
+    x = dev_x(x_n, "f32")
+    ws.solve(x, max_sweeps=1, rel_tol=0.0, check_every=1, accel="chebyshev", rho=0.95, gamma=1.7,
+             safeguard="backtrack")
+    op = O.make_problem(sc)
+    op.set_inertia(dt, x_n, x_prev)
+    col, _ = O.color(op)
+    xo, _ = O.solve(op, col, x_n, max_sweeps=1, accel="chebyshev", rho=0.95, gamma=1.7,
+                    safeguard="backtrack", n_threads=4)
+    assert rel_err(host(x), xo) <= 1e-6
