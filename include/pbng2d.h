@@ -131,7 +131,10 @@ int32_t pbng2d_residual(pbng2d_workspace* ws, const void* x, double* res_norm, d
  * FP32 form -- 32 bytes per visit record (two int32 vertex indices, four
  * float shape-function gradients, V0 mu and V0 lambda), per updated vertex
  * 28 bytes (position read and written, external force, CSR offset), 8
- * bytes per distinct neighbour position read; doubled floats in FP64.
+ * bytes per distinct neighbour position read; doubled floats in FP64.  A
+ * workspace whose triangles share one (mu, lambda) streams 24 of the 32
+ * record bytes (the rest area follows from the gradients); the figure
+ * stays defined on the full record.
  */
 int32_t pbng2d_load(pbng2d_workspace* ws, const void* x, void* hip_stream);
 int32_t pbng2d_store(pbng2d_workspace* ws, void* x, void* hip_stream);

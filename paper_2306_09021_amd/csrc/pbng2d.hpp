@@ -13,7 +13,10 @@
 //                             that F = (x_j - x_i) dN_j^T + (x_k - x_i) dN_k^T
 //                             and dN_i = -(dN_j + dN_k)
 //   vw[k] = {A0 mu, A0 lambda}
-// 8 + 16 + 8 = 32 bytes per visit in float.
+// 8 + 16 + 8 = 32 bytes per visit in float.  When every triangle has the
+// same (mu, lambda) the workspace omits vw (24 bytes per visit): the rest
+// area follows from the stored gradients, det[dN_j; dN_k] = 1 / (2 A0) for
+// the cyclic pair (j, k) after i, and mu, lambda are kernel arguments.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -44,8 +47,9 @@ struct Sweep2Args {
     const int* vptr;        // [n_free + 1]
     const int2* jk;         // [n_visits]
     const R4* gm;
-    const R2* vw;
+    const R2* vw;           // null with uniform materials
     const R2* fext;         // [n_free] lumped external force
+    R mu_u, lam_u;          // the uniform (mu, lambda) when vw is null
     int* rejected;          // [1]
     R omega, gamma;
     int max_halvings;
@@ -69,9 +73,10 @@ struct Res2Args {
     int n_free, n_verts, n_tris, model;
 };
 
+// uniform: the 24-byte record form (a.vw null, a.mu_u / a.lam_u set)
 template <class R>
-hipError_t launch_phase2(const Sweep2Args<R>& a, int model, int lanes, bool accel, bool safe, int vbeg,
-                         int vend, hipStream_t s);
+hipError_t launch_phase2(const Sweep2Args<R>& a, int model, int lanes, bool accel, bool safe, bool uniform,
+                         int vbeg, int vend, hipStream_t s);
 template <class R>
 hipError_t launch_residual2(const Res2Args<R>& a, double* r_out, hipStream_t s);
 template <class R>

@@ -22,6 +22,8 @@ struct pbng2d_workspace {
     int model = 0;
     int64_t nv = 0, nt = 0, nfree = 0, nvis = 0;
     int ncol = 0;
+    bool uniform = false;           // one (mu, lambda): 24-byte records, no vw stream
+    double mu_u = 0.0, lam_u = 0.0;
     std::vector<int> cptr;          // [ncol + 1] colour ranges, internal order
     std::vector<int> orig_h;        // internal -> caller
     std::vector<int> colors_h;      // caller order, -1 on Dirichlet vertices
@@ -278,7 +280,12 @@ void pack(pbng2d_workspace* ws, const pbng2d_problem* p, const Inc& I, const std
     ws->vptr.upload(vptr);
     ws->jk.upload(jk);
     ws->gm.upload(gm);
-    ws->vw.upload(vw);
+    ws->uniform = true;
+    for (int64_t e = 1; e < nt && ws->uniform; ++e)
+        ws->uniform = geo[e].mu == geo[0].mu && geo[e].lam == geo[0].lam;
+    ws->mu_u = geo[0].mu;
+    ws->lam_u = geo[0].lam;
+    if (!ws->uniform) ws->vw.upload(vw);
     ws->fext.upload(fr);
     ws->rvptr.upload(vptr);
     ws->rv.upload(rv);
@@ -287,7 +294,8 @@ void pack(pbng2d_workspace* ws, const pbng2d_problem* p, const Inc& I, const std
     ws->fext64.upload(f64);
     ws->xd_int.upload(xd);
     ws->orig_of.upload(ws->orig_h);
-    // algorithmic bytes per colour phase (FP32 form; doubled floats in FP64)
+    // algorithmic bytes per colour phase, defined on the full 32-byte record
+    // (FP32 form; doubled floats in FP64) whether or not vw is streamed
     const int64_t fb = ws->real == PBNG_F64 ? 2 : 1;
     ws->ph_bytes.assign(ws->ncol, 0);
     ws->ph_verts.assign(ws->ncol, 0);
@@ -441,7 +449,9 @@ void sweep2(pbng2d_workspace* ws, const pbng_solve_opts* o, double omega, double
     a.vptr = ws->vptr.as<int>();
     a.jk = ws->jk.as<int2>();
     a.gm = ws->gm.as<R4>();
-    a.vw = ws->vw.as<R2>();
+    a.vw = ws->uniform ? nullptr : ws->vw.as<R2>();
+    a.mu_u = R(ws->mu_u);
+    a.lam_u = R(ws->lam_u);
     a.fext = ws->fext.as<R2>();
     a.rejected = ws->rejected.as<int>();
     a.omega = R(omega);
@@ -450,7 +460,8 @@ void sweep2(pbng2d_workspace* ws, const pbng_solve_opts* o, double omega, double
     const int lanes = o->lanes == 0 ? 4 : o->lanes;
     const bool safe = o->safeguard == PBNG_SAFEGUARD_BACKTRACK;
     for (int c = 0; c < ws->ncol; ++c)
-        hipchk(launch_phase2<R>(a, ws->model, lanes, accel, safe, ws->cptr[c], ws->cptr[c + 1], s), "phase launch");
+        hipchk(launch_phase2<R>(a, ws->model, lanes, accel, safe, ws->uniform, ws->cptr[c], ws->cptr[c + 1], s),
+               "phase launch");
     if (accel) std::swap(ws->W.p, ws->N.p);
 }
 

@@ -40,7 +40,7 @@ __device__ __forceinline__ void rot2(R f00, R f01, R f10, R f11, R& c, R& s)
     }
 }
 
-template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE>
+template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool UNI>
 __global__ __launch_bounds__(kBlk) void k2_phase(Sweep2Args<R> a, int vbeg, int vend)
 {
     using R2 = typename R2t<R>::T;
@@ -55,7 +55,14 @@ __global__ __launch_bounds__(kBlk) void k2_phase(Sweep2Args<R> a, int vbeg, int 
     for (int k = kb + lane; k < ke; k += LANES) {
         const int2 jk = at(a.jk, k);
         const auto g = at(a.gm, k);   // dN_j = (g.x, g.y), dN_k = (g.z, g.w)
-        const R2 w = at(a.vw, k);     // (A0 mu, A0 lambda)
+        R2 w;                         // (A0 mu, A0 lambda)
+        if constexpr (UNI) {
+            const R A0 = R(0.5) / abs_(g.x * g.w - g.y * g.z);
+            w.x = a.mu_u * A0;
+            w.y = a.lam_u * A0;
+        } else {
+            w = at(a.vw, k);
+        }
         const R2 xj = at(a.W, jk.x), xk = at(a.W, jk.y);
         const R e1x = xj.x - xi.x, e1y = xj.y - xi.y;
         const R e2x = xk.x - xi.x, e2y = xk.y - xi.y;
@@ -155,37 +162,37 @@ __global__ __launch_bounds__(kBlk) void k2_phase(Sweep2Args<R> a, int vbeg, int 
     }
 }
 
-template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE>
+template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool UNI>
 hipError_t phase_t(const Sweep2Args<R>& a, int vb, int ve, hipStream_t s)
 {
     const int64_t threads = int64_t(ve - vb) * LANES;
     if (threads <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k2_phase<R, MODEL, LANES, ACCEL, SAFE>), dim3(nblocks(threads)), dim3(kBlk), 0, s, a,
-                       vb, ve);
+    hipLaunchKernelGGL((k2_phase<R, MODEL, LANES, ACCEL, SAFE, UNI>), dim3(nblocks(threads)), dim3(kBlk), 0, s,
+                       a, vb, ve);
     return hipGetLastError();
 }
 
-template <class R, int MODEL, int LANES>
+template <class R, int MODEL, int LANES, bool UNI>
 hipError_t phase_flags(const Sweep2Args<R>& a, bool accel, bool safe, int vb, int ve, hipStream_t s)
 {
     // the corotated full step never raises the local energy: no safeguard
     if (MODEL == kPlanarCor) safe = false;
     if (accel)
-        return safe ? phase_t<R, MODEL, LANES, true, true>(a, vb, ve, s)
-                    : phase_t<R, MODEL, LANES, true, false>(a, vb, ve, s);
-    return safe ? phase_t<R, MODEL, LANES, false, true>(a, vb, ve, s)
-                : phase_t<R, MODEL, LANES, false, false>(a, vb, ve, s);
+        return safe ? phase_t<R, MODEL, LANES, true, true, UNI>(a, vb, ve, s)
+                    : phase_t<R, MODEL, LANES, true, false, UNI>(a, vb, ve, s);
+    return safe ? phase_t<R, MODEL, LANES, false, true, UNI>(a, vb, ve, s)
+                : phase_t<R, MODEL, LANES, false, false, UNI>(a, vb, ve, s);
 }
 
-template <class R, int MODEL>
+template <class R, int MODEL, bool UNI>
 hipError_t phase_lanes(const Sweep2Args<R>& a, int lanes, bool accel, bool safe, int vb, int ve, hipStream_t s)
 {
     switch (lanes) {
-    case 1: return phase_flags<R, MODEL, 1>(a, accel, safe, vb, ve, s);
-    case 2: return phase_flags<R, MODEL, 2>(a, accel, safe, vb, ve, s);
-    case 4: return phase_flags<R, MODEL, 4>(a, accel, safe, vb, ve, s);
-    case 8: return phase_flags<R, MODEL, 8>(a, accel, safe, vb, ve, s);
-    case 16: return phase_flags<R, MODEL, 16>(a, accel, safe, vb, ve, s);
+    case 1: return phase_flags<R, MODEL, 1, UNI>(a, accel, safe, vb, ve, s);
+    case 2: return phase_flags<R, MODEL, 2, UNI>(a, accel, safe, vb, ve, s);
+    case 4: return phase_flags<R, MODEL, 4, UNI>(a, accel, safe, vb, ve, s);
+    case 8: return phase_flags<R, MODEL, 8, UNI>(a, accel, safe, vb, ve, s);
+    case 16: return phase_flags<R, MODEL, 16, UNI>(a, accel, safe, vb, ve, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -307,11 +314,15 @@ __global__ __launch_bounds__(kBlk) void k2_store(const typename R2t<R>::T* src, 
 }  // namespace
 
 template <class R>
-hipError_t launch_phase2(const Sweep2Args<R>& a, int model, int lanes, bool accel, bool safe, int vbeg, int vend,
-                         hipStream_t s)
+hipError_t launch_phase2(const Sweep2Args<R>& a, int model, int lanes, bool accel, bool safe, bool uniform,
+                         int vbeg, int vend, hipStream_t s)
 {
-    if (model == kPlanarNeo) return phase_lanes<R, kPlanarNeo>(a, lanes, accel, safe, vbeg, vend, s);
-    return phase_lanes<R, kPlanarCor>(a, lanes, accel, safe, vbeg, vend, s);
+    if (uniform) {
+        if (model == kPlanarNeo) return phase_lanes<R, kPlanarNeo, true>(a, lanes, accel, safe, vbeg, vend, s);
+        return phase_lanes<R, kPlanarCor, true>(a, lanes, accel, safe, vbeg, vend, s);
+    }
+    if (model == kPlanarNeo) return phase_lanes<R, kPlanarNeo, false>(a, lanes, accel, safe, vbeg, vend, s);
+    return phase_lanes<R, kPlanarCor, false>(a, lanes, accel, safe, vbeg, vend, s);
 }
 
 template <class R>
@@ -350,7 +361,8 @@ hipError_t launch_store2(const typename R2t<R>::T* src, const int* orig_of, R* x
 }
 
 #define PBNG2D_INSTANTIATE(R)                                                                                  \
-    template hipError_t launch_phase2<R>(const Sweep2Args<R>&, int, int, bool, bool, int, int, hipStream_t);  \
+    template hipError_t launch_phase2<R>(const Sweep2Args<R>&, int, int, bool, bool, bool, int, int,          \
+                                         hipStream_t);                                                        \
     template hipError_t launch_residual2<R>(const Res2Args<R>&, double*, hipStream_t);                       \
     template hipError_t launch_load2<R>(const R*, const int*, const R2t<R>::T*, R2t<R>::T*, R2t<R>::T*,       \
                                         R2t<R>::T*, int, int, hipStream_t);                                   \
