@@ -441,6 +441,27 @@ def _adjoint_model(pbng, S, torch, stream, model, so, ao, n_inst=8):
             "adjoint_max_rel_residual": max(s["rel_residual"] for s in sta)}
 
 
+def sweep_roofline(ws, x, opts, torch, stream, n_sweeps=10):
+    """HBM roofline of a workspace's colour-phase sweeps in its current state
+    (inertia, contacts and recolouring included): back-to-back sweeps from x
+    timed with HIP events on the launch stream, against the algorithmic
+    bytes of the phases (pbng_phase_bytes) plus the blend's 48 bytes per
+    vertex.  Leaves the workspace's internal iterate changed."""
+    ws.load(x, stream=stream)
+    ws.sweeps(2, opts, stream=stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    ws.sweeps(n_sweeps, opts, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t = ev0.elapsed_time(ev1) * 1e-3 / n_sweeps
+    blend = 48 if opts.accel != 0 else 0
+    b = sum(ws.phase_bytes(c)[0] + blend * ws.phase_bytes(c)[1] for c in range(ws.n_colors))
+    return {"sweep_us": round(t * 1e6, 2), "algorithmic_bytes_per_sweep": int(b),
+            "achieved_GBs": round(b / t / 1e9, 1), "frac_of_hbm_peak": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}
+
+
 def muscles_report(pbng, S, torch, stream):
     """Muscle stand-in (8 ellipsoids, 320k vertices, per-tet E, binding
     springs, ground contact): 1000 Chebyshev sweeps in FP32 and MIXED."""
@@ -465,7 +486,8 @@ def muscles_report(pbng, S, torch, stream):
         out[real] = {"colors": st[0]["n_colors"], "wall_s": round(t, 4),
                      "vertex_updates_per_s": round(st[0]["vertex_updates"] / t, 1),
                      "rel_residual_fp64": st[0]["rel_residual"],
-                     "safeguard_rejections": st[0]["rejected"]}
+                     "safeguard_rejections": st[0]["rejected"],
+                     "sweep_roofline": sweep_roofline(ws, x0, so, torch, stream)}
     return out
 
 
@@ -500,7 +522,8 @@ def paper_boxes_report(pbng, S, torch, stream):
             sts.append(st[0])
         torch.cuda.synchronize()
         t = (time.perf_counter() - t0) / len(xds[1:])
-        out.append({"block": "%d^3" % n, "vertices": sc.n_verts, "tets": sc.n_tets,
+        roof = sweep_roofline(ws, x, so, torch, stream)
+        out.append({"block": "%d^3" % n, "vertices": sc.n_verts, "tets": sc.n_tets, "sweep_roofline": roof,
                     "model": model, "iterations_per_frame": iters,
                     "ms_per_frame": round(t * 1e3, 3),
                     "vertex_updates_per_s": round(sc.n_free * iters / t, 1),
@@ -535,11 +558,12 @@ def dynamics_report(pbng, S, torch, stream, frames=8):
         x_prev, x_n = x_n, x.double()
     tip = float(x_n[:, 1].min() - x_prev.new_tensor(sc.initial_iterate())[:, 1].min())
     t = sum(times[1:]) / (frames - 1)
+    roof = sweep_roofline(ws, x, so, torch, stream)
     return {"workload": "beam 128x32x32 Neo-Hookean, gravity, dt = 1/30 s", "frames": frames,
             "iterations_per_frame": iters, "ms_per_frame": round(t * 1e3, 3),
             "vertex_updates_per_s": round(sc.n_free * iters / t, 1),
             "frame_rel_residual_fp64": [round(r, 6) for r in rels],
-            "lowest_point_drop_m": round(-tip, 6)}
+            "lowest_point_drop_m": round(-tip, 6), "sweep_roofline_with_inertia": roof}
 
 
 def collision_report(pbng, S, torch, stream, frames=8):
@@ -581,7 +605,9 @@ def collision_report(pbng, S, torch, stream, frames=8):
         n_contacts.append(int(pairs.shape[0]))
         n_colors.append(int(st[0]["n_colors"]))
     tm = sum(times[1:]) / (frames - 1)
+    roof = sweep_roofline(ws, x, so, torch, stream)
     return {"workload": "two blocks 2 x 16^3 vertices, corotated, backward Euler with contacts",
+            "sweep_roofline_with_contacts": roof,
             "vertices": sc.n_verts, "tets": sc.n_tets, "substeps_per_frame": sub,
             "iterations_per_frame": sub * iters, "ms_per_frame": round(tm * 1e3, 3),
             "contacts_per_frame_end": n_contacts, "colours": n_colors,

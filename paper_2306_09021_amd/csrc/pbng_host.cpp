@@ -263,7 +263,11 @@ struct pbng_workspace {
     // A and do not change either argument.
     bool safeguard_inactive = false;
     // general sweep kernel: batched instances, weak constraints or planes
-    bool general() const { return any_wc || n_inst > 1 || inertia; }
+    // phase-kernel variant: 1 general (batched, weak constraints, planes,
+    // recoloured vertices, whose phases need the list / colour checks even
+    // after the contacts that moved them are removed), 2 one instance with
+    // inertia only, 0 plain
+    int kernel_mode() const { return (any_wc || n_inst > 1 || moved_any) ? 1 : (inertia ? 2 : 0); }
     int device = 0;
     std::vector<int> col_ptr;              // internal free-vertex range of each colour
     std::vector<int64_t> v_off, t_off;     // per instance
@@ -1099,7 +1103,7 @@ void launch_sweep(pbng_workspace* ws, const pbng_solve_opts* o, double omega, do
         a.pcol = (!ph.list && ws->moved_any) ? ws->pcol.as<int>() : nullptr;
         a.pcolor = ph.color;
         hipchk(launch_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, ph.color), accel,
-                                   safe_effective(ws, o), ws->general(), ph.vb, ph.ve, s),
+                                   safe_effective(ws, o), ws->kernel_mode(), ph.vb, ph.ve, s),
                "sweep launch");
     }
     if (accel) std::swap(ws->W.p, ws->N.p);
@@ -1372,7 +1376,7 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
             a.pcol = (!ph.list && ws->moved_any) ? ws->pcol.as<int>() : nullptr;
             a.pcolor = ph.color;
             hipchk(launch_adjoint_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, ph.color), accel,
-                                               ws->any_wc || ws->inertia, ph.vb, ph.ve, s),
+                                               ws->any_wc || ws->inertia || ws->moved_any, ph.vb, ph.ve, s),
                    "adjoint launch");
         }
         if (accel) std::swap(ws->L.p, ws->LN.p);
@@ -1459,7 +1463,7 @@ void phase_t(pbng_workspace* ws, const pbng_solve_opts* o, int color, hipStream_
         a.pcol = (!ph.list && ws->moved_any) ? ws->pcol.as<int>() : nullptr;
         a.pcolor = ph.color;
         hipchk(launch_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, color), o->accel != PBNG_ACCEL_NONE,
-                                   safe_effective(ws, o), ws->general(), ph.vb, ph.ve, s),
+                                   safe_effective(ws, o), ws->kernel_mode(), ph.vb, ph.ve, s),
                "phase");
     }
 }

@@ -149,10 +149,12 @@ struct SegPlan {
 // ---- launchers (pbng_kernels.hip) -------------------------------------
 // launch_load: free vertices from the caller array, Dirichlet vertices from
 // xd_int (or, when xd_int is null, also from the caller array).
-// gen: the general variant (batched instances, weak constraints, planes)
+// mode: 0 the single-instance kernel, 1 the general variant (batched
+// instances, weak constraints, planes, recoloured vertices, inertia), 2 the
+// single-instance kernel with the backward-Euler inertia term
 template <class R, class PR>
 hipError_t launch_phase(const SweepArgs<R, PR>& a, int model, int lanes, bool accel, bool safe,
-                        bool gen, int vbeg, int vend, hipStream_t s);
+                        int mode, int vbeg, int vend, hipStream_t s);
 template <class R>
 hipError_t launch_load(const R* x_user, const int* orig_of, const typename R4t<R>::T* xd_int,
                        typename R4t<R>::T* d0, typename R4t<R>::T* d1, typename R4t<R>::T* d2,

@@ -419,19 +419,20 @@ __device__ __forceinline__ void lane_visits(const A& a, Acc<R>& q, int kb, int k
     }
 }
 
-// GEN = false: one instance without weak constraints or planes (no
-// per-vertex instance lookup); GEN = true: batched instances with per-
-// instance activity flags, weak constraints and contact planes.
-template <class R, class PR, int MODEL, int LANES, bool ACCEL, bool SAFE, bool GEN>
+// GEN = 0: one instance without weak constraints, planes or inertia (no
+// per-vertex instance lookup); GEN = 1: batched instances with per-instance
+// activity flags, weak constraints, contact planes, recoloured vertices and
+// inertia; GEN = 2: one instance whose only extra term is the inertia.
+template <class R, class PR, int MODEL, int LANES, bool ACCEL, bool SAFE, int GEN>
 __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, int vend)
 {
     using P4 = typename R4t<PR>::T;
-    constexpr bool WC = GEN;
+    constexpr bool WC = GEN == 1;
     const int gid = xcd_block() * kBlock + threadIdx.x;
     int v = vbeg + gid / LANES;
     const int lane = gid & (LANES - 1);
     if (v >= vend) return;
-    if (GEN) {
+    if (GEN == 1) {
         // vertices recoloured after new weak constraints (whole lane groups
         // return together)
         if (a.vlist) v = at(a.vlist, v);
@@ -440,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
     const int kb = at(a.vptr, v), ke = at(a.vptr, v + 1);
     const P4 xw = at(a.W, v);
     int inst = 0;
-    if (GEN) {
+    if (GEN == 1) {
         inst = at(a.vinst, v);
         if (!at(a.active, inst)) {
             if (ACCEL && lane == 0) *ptr_at(a.N, v) = xw;
@@ -504,7 +505,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
             }
         }
     }
-    if (GEN && a.inert) {
+    if (GEN != 0 && a.inert) {
         // backward-Euler inertia: 1/2 c |y_i - xhat_i|^2, c = m_ii / dt^2,
         // exactly quadratic (so it also joins the safeguard's exact part)
         const R c = at(a.inert, v);
@@ -662,7 +663,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
     }
 }
 
-template <class R, class PR, int MODEL, int LANES, bool ACCEL, bool SAFE, bool GEN>
+template <class R, class PR, int MODEL, int LANES, bool ACCEL, bool SAFE, int GEN>
 static hipError_t launch_phase_t(const SweepArgs<R, PR>& a, int vbeg, int vend, hipStream_t s)
 {
     const int64_t threads = int64_t(vend - vbeg) * LANES;
@@ -673,47 +674,54 @@ static hipError_t launch_phase_t(const SweepArgs<R, PR>& a, int vbeg, int vend, 
     return hipGetLastError();
 }
 
+template <class R, class PR, int MODEL, int LANES, int GEN>
+static hipError_t dispatch_as(const SweepArgs<R, PR>& a, bool accel, bool safe, int vb, int ve, hipStream_t s)
+{
+    const int code = (accel ? 2 : 0) | (safe ? 1 : 0);
+    switch (code) {
+    case 0: return launch_phase_t<R, PR, MODEL, LANES, false, false, GEN>(a, vb, ve, s);
+    case 1: return launch_phase_t<R, PR, MODEL, LANES, false, true, GEN>(a, vb, ve, s);
+    case 2: return launch_phase_t<R, PR, MODEL, LANES, true, false, GEN>(a, vb, ve, s);
+    default: return launch_phase_t<R, PR, MODEL, LANES, true, true, GEN>(a, vb, ve, s);
+    }
+}
+
 template <class R, class PR, int MODEL, int LANES>
-static hipError_t dispatch_flags(const SweepArgs<R, PR>& a, bool accel, bool safe, bool wc, int vb,
+static hipError_t dispatch_flags(const SweepArgs<R, PR>& a, bool accel, bool safe, int mode, int vb,
                                  int ve, hipStream_t s)
 {
-    const int code = (accel ? 4 : 0) | (safe ? 2 : 0) | (wc ? 1 : 0);
-    switch (code) {
-    case 0: return launch_phase_t<R, PR, MODEL, LANES, false, false, false>(a, vb, ve, s);
-    case 1: return launch_phase_t<R, PR, MODEL, LANES, false, false, true>(a, vb, ve, s);
-    case 2: return launch_phase_t<R, PR, MODEL, LANES, false, true, false>(a, vb, ve, s);
-    case 3: return launch_phase_t<R, PR, MODEL, LANES, false, true, true>(a, vb, ve, s);
-    case 4: return launch_phase_t<R, PR, MODEL, LANES, true, false, false>(a, vb, ve, s);
-    case 5: return launch_phase_t<R, PR, MODEL, LANES, true, false, true>(a, vb, ve, s);
-    case 6: return launch_phase_t<R, PR, MODEL, LANES, true, true, false>(a, vb, ve, s);
-    default: return launch_phase_t<R, PR, MODEL, LANES, true, true, true>(a, vb, ve, s);
+    switch (mode) {
+    case 0: return dispatch_as<R, PR, MODEL, LANES, 0>(a, accel, safe, vb, ve, s);
+    case 1: return dispatch_as<R, PR, MODEL, LANES, 1>(a, accel, safe, vb, ve, s);
+    case 2: return dispatch_as<R, PR, MODEL, LANES, 2>(a, accel, safe, vb, ve, s);
+    default: return hipErrorInvalidValue;
     }
 }
 
 template <class R, class PR, int MODEL>
 static hipError_t dispatch_lanes(const SweepArgs<R, PR>& a, int lanes, bool accel, bool safe,
-                                 bool wc, int vb, int ve, hipStream_t s)
+                                 int mode, int vb, int ve, hipStream_t s)
 {
     switch (lanes) {
-    case 1: return dispatch_flags<R, PR, MODEL, 1>(a, accel, safe, wc, vb, ve, s);
-    case 2: return dispatch_flags<R, PR, MODEL, 2>(a, accel, safe, wc, vb, ve, s);
-    case 4: return dispatch_flags<R, PR, MODEL, 4>(a, accel, safe, wc, vb, ve, s);
-    case 8: return dispatch_flags<R, PR, MODEL, 8>(a, accel, safe, wc, vb, ve, s);
-    case 16: return dispatch_flags<R, PR, MODEL, 16>(a, accel, safe, wc, vb, ve, s);
-    case 32: return dispatch_flags<R, PR, MODEL, 32>(a, accel, safe, wc, vb, ve, s);
-    case 64: return dispatch_flags<R, PR, MODEL, 64>(a, accel, safe, wc, vb, ve, s);
+    case 1: return dispatch_flags<R, PR, MODEL, 1>(a, accel, safe, mode, vb, ve, s);
+    case 2: return dispatch_flags<R, PR, MODEL, 2>(a, accel, safe, mode, vb, ve, s);
+    case 4: return dispatch_flags<R, PR, MODEL, 4>(a, accel, safe, mode, vb, ve, s);
+    case 8: return dispatch_flags<R, PR, MODEL, 8>(a, accel, safe, mode, vb, ve, s);
+    case 16: return dispatch_flags<R, PR, MODEL, 16>(a, accel, safe, mode, vb, ve, s);
+    case 32: return dispatch_flags<R, PR, MODEL, 32>(a, accel, safe, mode, vb, ve, s);
+    case 64: return dispatch_flags<R, PR, MODEL, 64>(a, accel, safe, mode, vb, ve, s);
     default: return hipErrorInvalidValue;
     }
 }
 
 template <class R, class PR>
 hipError_t launch_phase(const SweepArgs<R, PR>& a, int model, int lanes, bool accel, bool safe,
-                        bool wc, int vbeg, int vend, hipStream_t s)
+                        int mode, int vbeg, int vend, hipStream_t s)
 {
-    if (model == kNeo) return dispatch_lanes<R, PR, kNeo>(a, lanes, accel, safe, wc, vbeg, vend, s);
-    if (model == kNeoU) return dispatch_lanes<R, PR, kNeoU>(a, lanes, accel, safe, wc, vbeg, vend, s);
-    if (model == kSnh) return dispatch_lanes<R, PR, kSnh>(a, lanes, accel, safe, wc, vbeg, vend, s);
-    return dispatch_lanes<R, PR, kCor>(a, lanes, accel, safe, wc, vbeg, vend, s);
+    if (model == kNeo) return dispatch_lanes<R, PR, kNeo>(a, lanes, accel, safe, mode, vbeg, vend, s);
+    if (model == kNeoU) return dispatch_lanes<R, PR, kNeoU>(a, lanes, accel, safe, mode, vbeg, vend, s);
+    if (model == kSnh) return dispatch_lanes<R, PR, kSnh>(a, lanes, accel, safe, mode, vbeg, vend, s);
+    return dispatch_lanes<R, PR, kCor>(a, lanes, accel, safe, mode, vbeg, vend, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1556,7 +1564,7 @@ hipError_t launch_set_inertia(const double* x_n, const double* x_prev, const int
                                                    const R4t<R>::T*, double*, double*, double*,   \
                                                    double*, const int*, hipStream_t);
 #define PBNG_INST_SWEEP(R, PR)                                                                    \
-    template hipError_t launch_phase<R, PR>(const SweepArgs<R, PR>&, int, int, bool, bool, bool,  \
+    template hipError_t launch_phase<R, PR>(const SweepArgs<R, PR>&, int, int, bool, bool, int,   \
                                             int, int, hipStream_t);                               \
     template hipError_t launch_adjoint_phase<R, PR>(const AdjArgs<R, PR>&, int, int, bool, bool,  \
                                                     int, int, hipStream_t);                            \

@@ -176,3 +176,39 @@ def test_colliding_blocks_full_size_substep():
     op2.set_inertia(dt, x, x_prev)
     xo, _ = O.solve(op2, ws.colors(), x, max_sweeps=8, **kw)
     assert rel_err(host(xg), xo) <= 1e-5
+
+
+def test_removing_contacts_keeps_recoloured_phases():
+    """Contacts installed (some vertices recoloured) and then removed: the
+    recoloured vertices keep their new colours, so every later solve and
+    adjoint still runs their phases from the vertex lists, also with no
+    other weak constraint, plane, inertia or second instance.  FP64 against
+    the oracle with the workspace's colouring and no contacts."""
+    from oracle import dense as D
+    from paper_2306_09021_amd import pbng
+    sc, x = near_blocks(model="nh")
+    op = O.make_problem(sc)
+    pairs, normals = brute_contacts(x, sc.tets, op.is_dir, 0.05)
+    announce("contacts installed then removed, solve and adjoint f64")
+    ws = workspace([sc], "f64")
+    col0 = ws.colors()
+    ws.set_contacts(torch.tensor(pairs, dtype=torch.int32, device="cuda"),
+                    torch.tensor(normals, dtype=torch.float64, device="cuda"), 1e3)
+    ws.set_contacts(None, None, 1e3)
+    col = ws.colors()
+    assert np.any(col != col0)
+    check_valid_coloring(op, col)
+    kw = dict(accel="chebyshev", rho=0.9, gamma=1.3, safeguard="backtrack")
+    xo, _ = O.solve(op, col, x, max_sweeps=40, **kw)
+    xg = dev_x(x, "f64")
+    ws.solve(xg, max_sweeps=40, rel_tol=0.0, check_every=40, **kw)
+    assert rel_err(host(xg), xo) <= 1e-10
+    # adjoint at an equilibrium, against a dense solve
+    xe, _ = O.solve(op, col, x, max_sweeps=20000, rel_tol=1e-13, check_every=50, **kw)
+    g = 2.0 * (xe - sc.rest_pos) * (op.is_dir == 0)[:, None]
+    lam_d = D.adjoint_dense(op, xe, g)
+    o = pbng.adjoint_opts(rel_tol=1e-12, max_sweeps=20000, check_every=20, accel="chebyshev", rho=0.9,
+                          gamma=1.0)
+    rc, out, st = ws.adjoint(dev_x(xe, "f64"), dev_x(g, "f64"), o, want=("lam_vec",))
+    lv = host(out["lam_vec"])
+    assert np.linalg.norm(lv - lam_d) / np.linalg.norm(lam_d) <= 1e-8
