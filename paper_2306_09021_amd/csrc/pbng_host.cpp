@@ -1702,7 +1702,10 @@ int32_t pbng_workspace_set_materials(pbng_workspace* ws, const double* mu_dev, c
             int h[2] = {0, 0};
             hipchk(hipMemcpyAsync(h, ws->flag.p, 2 * sizeof(int), hipMemcpyDeviceToHost, s), "material check");
             hipchk(hipStreamSynchronize(s), "material check");
+            const bool was_inactive = ws->safeguard_inactive;
             ws->safeguard_inactive = ws->n_planes == 0 && h[0] != 0;
+            // the safeguard decides the kernel variant a captured graph holds
+            if (was_inactive != ws->safeguard_inactive) ws->drop_graph();
             const int km = h[1] ? 3 : PBNG_NEOHOOKEAN;
             if (km != ws->kmodel) {
                 // the record form changes: new streams, new kernel variant

@@ -483,6 +483,34 @@ def test_material_update_reenables_safeguard():
         assert rel_err(host(x), xo) <= tol
 
 
+def test_graph_replay_follows_material_updates():
+    """A graph captured while the Neo-Hookean safeguard is skipped
+    (lambda >= mu) is not replayed after a material update to lambda < mu:
+    the next solve captures the safeguarded kernel and matches the oracle's
+    safeguarded solve with the new materials (FP64)."""
+    soft = S.twist_box(6, "nh", 1e4, 0.05, 90.0, 2.0, 0.01, seed=6)
+    stiff = S.twist_box(6, "nh", 1e4, 0.45, 90.0, 2.0, 0.01, seed=6)
+    hp = pbng.problem_from_scenario(soft)
+    nt = soft.tets.shape[0]
+    xo, sto, _ = oracle_solve(soft, 40, safeguard="backtrack")
+    assert sto["halvings"] > 0
+    announce("graph replay across a material update that re-enables the safeguard")
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        ws = workspace([stiff], "f64")
+        kw = dict(max_sweeps=40, rel_tol=0.0, check_every=40, safeguard="backtrack", sweeps_per_graph=4,
+                  stream=stream)
+        x = dev_x(stiff.initial_iterate(), "f64")
+        ws.solve(x, **kw)
+        mu = torch.full((nt,), hp.mu, dtype=torch.float64, device="cuda")
+        lam = torch.full((nt,), hp.lam, dtype=torch.float64, device="cuda")
+        ws.set_materials(mu, lam, stream=stream)
+        x = dev_x(soft.initial_iterate(), "f64")
+        ws.solve(x, **kw)
+        stream.synchronize()
+    assert rel_err(host(x), xo) <= 1e-10
+
+
 def test_record_form_follows_material_updates():
     """A Neo-Hookean workspace with one (mu, lambda) per instance streams the
     40-byte records; a material update to per-tet values switches it to the
