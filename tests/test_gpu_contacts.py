@@ -212,3 +212,73 @@ def test_removing_contacts_keeps_recoloured_phases():
     rc, out, st = ws.adjoint(dev_x(xe, "f64"), dev_x(g, "f64"), o, want=("lam_vec",))
     lv = host(out["lam_vec"])
     assert np.linalg.norm(lv - lam_d) / np.linalg.norm(lam_d) <= 1e-8
+
+
+def test_state_changes_in_sequence_with_graph_replay():
+    """One workspace through every state change, with graph replay on
+    (sweeps_per_graph = 4 on a non-null stream): quasistatic solve, inertia
+    on, contacts in (recolouring), new materials, contacts out, inertia off,
+    new Dirichlet targets.  After each change a 24-sweep solve in FP64
+    against the oracle set up in the same state (1e-10)."""
+    import copy
+    sc = S.two_blocks(5, gap=0.02, model="corotated", drive=0.0)
+    half = sc.n_verts // 2
+    x = sc.initial_iterate()
+    x[half:, 0] -= 0.04
+    x[sc.dirichlet_idx] = sc.dirichlet_x
+    radius, kn, dt = 0.05, 1e4, 0.01
+    kw = dict(accel="chebyshev", rho=0.9, gamma=1.2, safeguard="backtrack")
+    stream = torch.cuda.Stream()
+    announce("state changes in sequence with graph replay f64")
+    with torch.cuda.stream(stream):
+        ws = workspace([sc], "f64")
+        state = dict(sc=copy.copy(sc), contacts=None, inertia=None, mu=None, lam=None)
+
+        def check(tag, x_start):
+            xg = dev_x(x_start, "f64")
+            ws.solve(xg, max_sweeps=24, rel_tol=0.0, check_every=24, sweeps_per_graph=4, stream=stream, **kw)
+            stream.synchronize()
+            s = state["sc"] if state["contacts"] is None else add_contacts(state["sc"], *state["contacts"], kn)
+            op = O.make_problem(s, mu=state["mu"], lam=state["lam"])
+            if state["inertia"] is not None:
+                op.set_inertia(dt, *state["inertia"])
+            xo, _ = O.solve(op, ws.colors(), x_start, max_sweeps=24, **kw)
+            e = rel_err(host(xg), xo)
+            print(tag, "rel err", e)
+            assert e <= 1e-10, tag
+            return host(xg)
+
+        x1 = check("quasistatic", x)
+        x_prev = x - 1e-3
+        x_prev[sc.dirichlet_idx] = sc.dirichlet_x
+        ws.set_inertia(dt, torch.tensor(x, device="cuda"), torch.tensor(x_prev, device="cuda"), stream=stream)
+        state["inertia"] = (x, x_prev)
+        check("inertia on", x)
+        pairs, normals = ws.detect_contacts(dev_x(x, "f64"), radius, max_pairs=4096, stream=stream)
+        assert pairs.shape[0] > 0
+        ws.set_contacts(pairs, normals, kn, stream=stream)
+        state["contacts"] = (host(pairs).astype(np.int64), host(normals))
+        check("contacts in", x)
+        from paper_2306_09021_amd import pbng
+        mu0, lam0 = pbng.lame(sc.E, sc.nu)
+        nt = sc.n_tets
+        mu = np.full(nt, float(mu0)) * np.linspace(0.5, 1.5, nt)
+        lam = np.full(nt, float(lam0)) * np.linspace(1.5, 0.5, nt)
+        ws.set_materials(torch.tensor(mu, device="cuda"), torch.tensor(lam, device="cuda"), stream=stream)
+        state["mu"], state["lam"] = mu, lam
+        check("new materials", x)
+        ws.set_contacts(None, None, kn, stream=stream)
+        state["contacts"] = None
+        check("contacts out", x)
+        ws.set_inertia(0.0, stream=stream)
+        state["inertia"] = None
+        check("inertia off", x1)
+        xd = sc.dirichlet_x.copy()
+        xd[:, 1] += 0.05
+        ws.set_dirichlet(torch.tensor(xd, device="cuda"), stream=stream)
+        s2 = copy.copy(sc)
+        s2.dirichlet_x = xd
+        state["sc"] = s2
+        x2 = x1.copy()
+        x2[sc.dirichlet_idx] = xd
+        check("new Dirichlet targets", x2)
