@@ -282,3 +282,44 @@ def test_state_changes_in_sequence_with_graph_replay():
         x2 = x1.copy()
         x2[sc.dirichlet_idx] = xd
         check("new Dirichlet targets", x2)
+
+
+def test_batched_instances_with_contacts():
+    """Two instances (two-block scenes pushed together by different amounts)
+    in one workspace: detection keeps pairs inside each instance, contacts
+    and recolouring act per instance, and each instance's solve equals its
+    own oracle solve with its contacts and the workspace's colouring (FP64)."""
+    scs, xs = [], []
+    for k, shift in enumerate((0.035, 0.045)):
+        sc = S.two_blocks(5, gap=0.02, model="nh", drive=0.0)
+        x = sc.initial_iterate()
+        x[sc.n_verts // 2:, 0] -= shift
+        x[sc.dirichlet_idx] = sc.dirichlet_x
+        scs.append(sc)
+        xs.append(x)
+    off = np.cumsum([0] + [s.n_verts for s in scs])
+    xall = np.concatenate(xs)
+    announce("batched instances with contacts f64")
+    ws = workspace(scs, "f64")
+    radius, kn = 0.05, 1e4
+    pairs, normals = ws.detect_contacts(dev_x(xall, "f64"), radius, max_pairs=8192)
+    p_h, n_h = host(pairs).astype(np.int64), host(normals)
+    ws.set_contacts(pairs, normals, kn)
+    kw = dict(accel="chebyshev", rho=0.9, gamma=1.2, safeguard="backtrack")
+    xg = dev_x(xall, "f64")
+    ws.solve(xg, max_sweeps=30, rel_tol=0.0, check_every=30, **kw)
+    xg, col = host(xg), ws.colors()
+    counts = []
+    for q, sc in enumerate(scs):
+        inq = (p_h[:, 0] >= off[q]) & (p_h[:, 0] < off[q + 1])
+        assert np.all((p_h[inq, 1] >= off[q]) & (p_h[inq, 1] < off[q + 1]))
+        op = O.make_problem(sc)
+        ref_p, ref_n = brute_contacts(xs[q], sc.tets, op.is_dir, radius)
+        assert np.array_equal(p_h[inq] - off[q], ref_p.astype(np.int64))
+        counts.append(int(inq.sum()))
+        op2 = O.make_problem(add_contacts(sc, ref_p, ref_n, kn))
+        cq = col[off[q]:off[q + 1]]
+        check_valid_coloring(op2, cq)
+        xo, _ = O.solve(op2, cq, xs[q], max_sweeps=30, **kw)
+        assert rel_err(xg[off[q]:off[q + 1]], xo) <= 1e-10, q
+    assert counts[0] > 0 and counts[1] > 0
