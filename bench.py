@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--planar-only", action="store_true",
                     help="run only the planar (triangle-mesh) report and print it (profiling)")
     ap.add_argument("--planar-sweeps", type=int, default=200)
+    ap.add_argument("--only", default="",
+                    help="run only this sub-report (batched, backward_euler, ...) and print it (profiling)")
     return ap.parse_args()
 
 
@@ -107,6 +109,15 @@ def main():
         del src, dst
     if args.planar_only:
         print(json.dumps({"planar": planar_report(torch, stream, sweeps=args.planar_sweeps)}))
+        return
+    if args.only:
+        from paper_2306_09021_amd import pbng
+        from paper_2306_09021_amd import scenarios as S
+        fn = sub_reports(args, pbng, S, torch, stream).get(args.only)
+        if fn is None:
+            print("unknown sub-report %r" % args.only, file=sys.stderr)
+            sys.exit(2)
+        print(json.dumps({args.only: fn()}))
         return
 
     sc = S.config_beam_f32()
@@ -185,16 +196,7 @@ def main():
         progress("cpu baseline: %.3e vertex updates/s" % cpu["value"])
     extras = {}
     if not args.no_extras:
-        reports = [("beam_to_tol", lambda: beam_to_tol_report(pbng, S, torch, stream)),
-                   ("batched", lambda: batched_report(pbng, S, torch, stream, args.batched_subset)),
-                   ("differentiable",
-                    lambda: differentiable_report(pbng, S, torch, stream, args.diff_instances)),
-                   ("muscles", lambda: muscles_report(pbng, S, torch, stream)),
-                   ("paper_blocks", lambda: paper_boxes_report(pbng, S, torch, stream)),
-                   ("backward_euler", lambda: dynamics_report(pbng, S, torch, stream)),
-                   ("collisions", lambda: collision_report(pbng, S, torch, stream)),
-                   ("planar", lambda: planar_report(torch, stream, sweeps=args.planar_sweeps))]
-        for name, fn in reports:
+        for name, fn in sub_reports(args, pbng, S, torch, stream).items():
             # a failing sub-report is recorded, not fatal to the headline line
             try:
                 extras[name] = fn()
@@ -259,6 +261,18 @@ def beam_to_tol_report(pbng, S, torch, stream, max_sweeps=40000):
             "time_to_tol_ms": (round(s0["time_to_tol_ms"], 2) if s0["converged"] else None),
             "wall_s": round(el, 4), "vertex_updates_per_s": round(s0["vertex_updates"] / el, 1),
             "lanes_per_colour": [int(v) for v in lanes], "sweeps_per_graph": int(opts.sweeps_per_graph)}
+
+
+def sub_reports(args, pbng, S, torch, stream):
+    """The sub-reports of the bench line, in order, by name."""
+    return {"beam_to_tol": lambda: beam_to_tol_report(pbng, S, torch, stream),
+            "batched": lambda: batched_report(pbng, S, torch, stream, args.batched_subset),
+            "differentiable": lambda: differentiable_report(pbng, S, torch, stream, args.diff_instances),
+            "muscles": lambda: muscles_report(pbng, S, torch, stream),
+            "paper_blocks": lambda: paper_boxes_report(pbng, S, torch, stream),
+            "backward_euler": lambda: dynamics_report(pbng, S, torch, stream),
+            "collisions": lambda: collision_report(pbng, S, torch, stream),
+            "planar": lambda: planar_report(torch, stream, sweeps=args.planar_sweeps)}
 
 
 def batched_report(pbng, S, torch, stream, subset):
