@@ -121,3 +121,26 @@ def test_stable_neohookean_safeguard_active_parity():
     print("halvings", sto["halvings"])
     assert sto["halvings"] > 0
     assert rel_err(xg, xo) <= 1e-10
+
+
+@pytest.mark.parametrize("real,tol,safeguard", [("f64", 1e-10, "backtrack"), ("f32", 1e-5, "none")])
+def test_stable_neohookean_paper_block_full_size(real, tol, safeguard):
+    """The paper's 32^3 stretching block with the stable Neo-Hookean model at
+    its full size, frame-1 targets, interior jittered: 4 sweeps with the
+    benchmark's Chebyshev blend against 4 oracle sweeps over every vertex
+    (FP32 without the safeguard, whose accept / halve choice FP32 and FP64
+    can take differently at ties)."""
+    sc, _ = S.paper_box_frames(32, "snh", n_frames=60)
+    rng = np.random.default_rng(21)
+    x0 = sc.initial_iterate() + 1e-3 / 31.0 * rng.normal(size=(sc.n_verts, 3))
+    x0[sc.dirichlet_idx] = sc.dirichlet_x
+    if real == "f32":
+        x0 = x0.astype(np.float32).astype(np.float64)
+    kw = dict(accel="chebyshev", rho=0.95, gamma=1.7, safeguard=safeguard)
+    announce("stable Neo-Hookean 32^3 block full size %s" % real)
+    ws = workspace([sc], real)
+    x = dev_x(x0, real)
+    ws.solve(x, max_sweeps=4, rel_tol=0.0, check_every=4, **kw)
+    op = O.make_problem(sc)
+    xo, _ = O.solve(op, ws.colors(), x0, max_sweeps=4, n_threads=4, **kw)
+    assert rel_err(host(x), xo) <= tol
