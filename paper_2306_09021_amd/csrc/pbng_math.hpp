@@ -327,6 +327,7 @@ __device__ __forceinline__ bool polar_newton(const Cols<R>& F, Cols<R>& X)
     const R tiny = dbl ? R(1e-200) : R(1e-30);
     X = F;
     bool act = true, ok = false;
+    R dprev = R(1);
     for (int it = 0; it < iters; ++it) {
         if (!__any(act)) break;
         if (act) {
@@ -335,8 +336,15 @@ __device__ __forceinline__ bool polar_newton(const Cols<R>& F, Cols<R>& X)
             if (!(det > tiny)) {
                 act = false;
             } else {
-                const R q = sqrt_(frob2(C) * rcp(frob2(X)));   // |X^{-1}|_F det / |X|_F
-                const R zeta = sqrt_(q * rcp(det));
+                // Frobenius scaling speeds up the first steps; once a step
+                // changed X by less than 1e-2 the unscaled iteration is
+                // already in its quadratic regime (Higham 1986), and the
+                // scale factor's norms and roots are skipped.
+                R zeta = R(1);
+                if (dprev > R(1e-4)) {
+                    const R q = sqrt_(frob2(C) * rcp(frob2(X)));   // |X^{-1}|_F det / |X|_F
+                    zeta = sqrt_(q * rcp(det));
+                }
                 const R a = R(0.5) * zeta, b = R(0.5) * rcp(zeta * det);
                 Cols<R> Y;
                 Y.c0 = a * X.c0 + b * C.c0;
@@ -344,6 +352,7 @@ __device__ __forceinline__ bool polar_newton(const Cols<R>& F, Cols<R>& X)
                 Y.c2 = a * X.c2 + b * C.c2;
                 const V3<R> d0 = Y.c0 - X.c0, d1 = Y.c1 - X.c1, d2 = Y.c2 - X.c2;
                 const R d = dot(d0, d0) + dot(d1, d1) + dot(d2, d2);
+                dprev = d;
                 X = Y;
                 if (d <= tol) {
                     act = false;
