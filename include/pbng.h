@@ -225,8 +225,12 @@ int32_t pbng_default_adjoint_opts(pbng_adjoint_opts* o);
  * colour absent from the used-colour sets S_c of its incident tets and
  * weak constraints, then registers it in each of them.  Dirichlet vertices
  * get -1.  colors_out [p->n_verts]; *n_colors_out = number of colours.
- * Errors: PBNG_EINVAL, PBNG_EMESH (index out of range), PBNG_ECOLOR (more
- * than 64 colours would be needed).
+ * Reads n_verts, n_tets, tets, the Dirichlet list and the weak-constraint
+ * CSR (wc_ptr, wc_vert), which are checked first as in
+ * pbng_workspace_create.  Errors: PBNG_EINVAL (bad sizes, n_tets >= 2^29,
+ * a null array, a repeated or out-of-range Dirichlet index, a malformed
+ * wc_ptr), PBNG_EMESH (tet or constraint vertex out of range, a repeated
+ * vertex), PBNG_ECOLOR (more than 64 colours would be needed).
  */
 int32_t pbng_color(const pbng_problem* p, int32_t* colors_out, int32_t* n_colors_out);
 

@@ -72,7 +72,9 @@ typedef struct pbng2d_workspace pbng2d_workspace;
  * vertices in ascending index each take the least colour used by no
  * already coloured vertex of an incident triangle; Dirichlet vertices get
  * -1.  colors_out [n_verts]; *n_colors_out the number of colours.
- * Errors: PBNG_EINVAL, PBNG_EMESH, PBNG_ECOLOR (more than 64 colours).
+ * Errors: PBNG_EINVAL, PBNG_EMESH, PBNG_ECOLOR (more than 64 colours),
+ * PBNG_EUNSUPPORTED (n_tris above INT32_MAX / 3, checked before tris is
+ * read).
  */
 int32_t pbng2d_color(const pbng2d_problem* p, int32_t* colors_out, int32_t* n_colors_out);
 
@@ -82,8 +84,8 @@ int32_t pbng2d_color(const pbng2d_problem* p, int32_t* colors_out, int32_t* n_co
  * pbng2d_color; a supplied colouring is checked.  real = PBNG_F32 or
  * PBNG_F64 (positions and sweep arithmetic; PBNG_MIXED is not offered).
  * Errors: PBNG_EINVAL, PBNG_EMESH, PBNG_EMATERIAL, PBNG_ECOLOR, PBNG_ENAN,
- * PBNG_EUNSUPPORTED (a model other than the two above), PBNG_EHIP,
- * PBNG_ENOMEM.
+ * PBNG_EUNSUPPORTED (a model other than the two above, or a mesh too large
+ * for the 32-bit indices and stream offsets), PBNG_EHIP, PBNG_ENOMEM.
  */
 int32_t pbng2d_workspace_create(const pbng2d_problem* p, const int32_t* colors, int32_t real,
                                 pbng2d_workspace** ws_out);

@@ -7,6 +7,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <numeric>
@@ -71,6 +72,8 @@ void validate2(const pbng2d_problem* p)
 {
     if (!p) fail(PBNG_EINVAL, "problem is null");
     if (p->n_verts < 1 || p->n_tris < 1) fail(PBNG_EINVAL, "need at least one vertex and one triangle");
+    // the vertex -> triangle incidence holds 3 n_tris int32 entries
+    if (p->n_tris > INT32_MAX / 3) fail(PBNG_EUNSUPPORTED, "too many triangles for 32-bit indices");
     if (!p->rest_pos || !p->tris) fail(PBNG_EINVAL, "rest_pos and tris are required");
     if (p->model != PBNG_NEOHOOKEAN && p->model != PBNG_COROTATED) {
         if (p->model == PBNG_STABLE_NEOHOOKEAN)

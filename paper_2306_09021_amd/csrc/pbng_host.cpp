@@ -59,15 +59,14 @@ bool tet_rest(const double* X, const int32_t* t, double* dminv, double* V0)
     return true;
 }
 
-void validate_problem(const pbng_problem* p, int q)
+// What the colouring reads: sizes (the vertex -> tet incidence holds
+// 4 n_tets int32 entries), tet and weak-constraint vertex indices, the
+// constraint CSR and the Dirichlet list.
+void validate_topology(const pbng_problem* p, int q)
 {
-    if (!p) fail(PBNG_EINVAL, "problem %d: null", q);
     if (p->n_verts <= 0 || p->n_tets < 0) fail(PBNG_EINVAL, "problem %d: bad sizes", q);
-    if (!p->rest_pos) fail(PBNG_EINVAL, "problem %d: rest_pos is null", q);
+    if (p->n_tets >= (int64_t(1) << 29)) fail(PBNG_EINVAL, "problem %d: too many tets for 32-bit indices", q);
     if (p->n_tets > 0 && !p->tets) fail(PBNG_EINVAL, "problem %d: tets is null", q);
-    if (p->model != PBNG_NEOHOOKEAN && p->model != PBNG_COROTATED && p->model != PBNG_STABLE_NEOHOOKEAN)
-        fail(PBNG_EINVAL, "problem %d: unknown model %d", q, p->model);
-    if (!finite_arr(p->rest_pos, 3ll * p->n_verts)) fail(PBNG_ENAN, "problem %d: non-finite rest_pos", q);
     for (int64_t e = 0; e < p->n_tets; ++e) {
         const int32_t* t = p->tets + 4 * e;
         for (int j = 0; j < 4; ++j) {
@@ -77,6 +76,41 @@ void validate_problem(const pbng_problem* p, int q)
                 if (t[k] == t[j]) fail(PBNG_EMESH, "problem %d: tet %lld repeats a vertex", q, (long long)e);
         }
     }
+    if (p->n_dirichlet < 0 || p->n_dirichlet > p->n_verts) fail(PBNG_EINVAL, "problem %d: bad n_dirichlet", q);
+    if (p->n_dirichlet > 0) {
+        if (!p->dirichlet_idx) fail(PBNG_EINVAL, "problem %d: dirichlet_idx is null", q);
+        std::vector<char> seen(p->n_verts, 0);
+        for (int k = 0; k < p->n_dirichlet; ++k) {
+            const int v = p->dirichlet_idx[k];
+            if (v < 0 || v >= p->n_verts) fail(PBNG_EINVAL, "problem %d: Dirichlet index %d out of range", q, v);
+            if (seen[v]) fail(PBNG_EINVAL, "problem %d: Dirichlet index %d repeated", q, v);
+            seen[v] = 1;
+        }
+    }
+    if (p->n_wc < 0) fail(PBNG_EINVAL, "problem %d: bad n_wc", q);
+    if (p->n_wc > 0) {
+        if (!p->wc_ptr || !p->wc_vert) fail(PBNG_EINVAL, "problem %d: weak-constraint arrays are null", q);
+        if (p->wc_ptr[0] != 0) fail(PBNG_EINVAL, "problem %d: wc_ptr[0] must be 0", q);
+        for (int c = 0; c < p->n_wc; ++c)
+            if (p->wc_ptr[c + 1] < p->wc_ptr[c]) fail(PBNG_EINVAL, "problem %d: wc_ptr not monotone", q);
+        const int nnz = p->wc_ptr[p->n_wc];
+        for (int k = 0; k < nnz; ++k)
+            if (p->wc_vert[k] < 0 || p->wc_vert[k] >= p->n_verts) fail(PBNG_EMESH, "problem %d: weak-constraint vertex out of range", q);
+        for (int c = 0; c < p->n_wc; ++c)
+            for (int k = p->wc_ptr[c]; k < p->wc_ptr[c + 1]; ++k)
+                for (int j = p->wc_ptr[c]; j < k; ++j)
+                    if (p->wc_vert[j] == p->wc_vert[k]) fail(PBNG_EMESH, "problem %d: weak constraint %d repeats a vertex", q, c);
+    }
+}
+
+void validate_problem(const pbng_problem* p, int q)
+{
+    if (!p) fail(PBNG_EINVAL, "problem %d: null", q);
+    validate_topology(p, q);
+    if (!p->rest_pos) fail(PBNG_EINVAL, "problem %d: rest_pos is null", q);
+    if (p->model != PBNG_NEOHOOKEAN && p->model != PBNG_COROTATED && p->model != PBNG_STABLE_NEOHOOKEAN)
+        fail(PBNG_EINVAL, "problem %d: unknown model %d", q, p->model);
+    if (!finite_arr(p->rest_pos, 3ll * p->n_verts)) fail(PBNG_ENAN, "problem %d: non-finite rest_pos", q);
     const bool pt = p->mu_tet != nullptr || p->lambda_tet != nullptr;
     if (pt && (!p->mu_tet || !p->lambda_tet))
         fail(PBNG_EINVAL, "problem %d: mu_tet and lambda_tet must be given together", q);
@@ -97,31 +131,13 @@ void validate_problem(const pbng_problem* p, int q)
         fail(PBNG_ENAN, "problem %d: non-finite body force", q);
     if (p->nodal_force && !finite_arr(p->nodal_force, 3ll * p->n_verts))
         fail(PBNG_ENAN, "problem %d: non-finite nodal_force", q);
-    if (p->n_dirichlet < 0 || p->n_dirichlet > p->n_verts) fail(PBNG_EINVAL, "problem %d: bad n_dirichlet", q);
     if (p->n_dirichlet > 0) {
-        if (!p->dirichlet_idx || !p->dirichlet_x) fail(PBNG_EINVAL, "problem %d: Dirichlet arrays are null", q);
-        std::vector<char> seen(p->n_verts, 0);
-        for (int k = 0; k < p->n_dirichlet; ++k) {
-            const int v = p->dirichlet_idx[k];
-            if (v < 0 || v >= p->n_verts) fail(PBNG_EINVAL, "problem %d: Dirichlet index %d out of range", q, v);
-            if (seen[v]) fail(PBNG_EINVAL, "problem %d: Dirichlet index %d repeated", q, v);
-            seen[v] = 1;
-        }
+        if (!p->dirichlet_x) fail(PBNG_EINVAL, "problem %d: dirichlet_x is null", q);
         if (!finite_arr(p->dirichlet_x, 3ll * p->n_dirichlet)) fail(PBNG_ENAN, "problem %d: non-finite Dirichlet target", q);
     }
-    if (p->n_wc < 0) fail(PBNG_EINVAL, "problem %d: bad n_wc", q);
     if (p->n_wc > 0) {
-        if (!p->wc_ptr || !p->wc_vert || !p->wc_w || !p->wc_K) fail(PBNG_EINVAL, "problem %d: weak-constraint arrays are null", q);
-        if (p->wc_ptr[0] != 0) fail(PBNG_EINVAL, "problem %d: wc_ptr[0] must be 0", q);
-        for (int c = 0; c < p->n_wc; ++c)
-            if (p->wc_ptr[c + 1] < p->wc_ptr[c]) fail(PBNG_EINVAL, "problem %d: wc_ptr not monotone", q);
+        if (!p->wc_w || !p->wc_K) fail(PBNG_EINVAL, "problem %d: weak-constraint arrays are null", q);
         const int nnz = p->wc_ptr[p->n_wc];
-        for (int k = 0; k < nnz; ++k)
-            if (p->wc_vert[k] < 0 || p->wc_vert[k] >= p->n_verts) fail(PBNG_EMESH, "problem %d: weak-constraint vertex out of range", q);
-        for (int c = 0; c < p->n_wc; ++c)
-            for (int k = p->wc_ptr[c]; k < p->wc_ptr[c + 1]; ++k)
-                for (int j = p->wc_ptr[c]; j < k; ++j)
-                    if (p->wc_vert[j] == p->wc_vert[k]) fail(PBNG_EMESH, "problem %d: weak constraint %d repeats a vertex", q, c);
         if (!finite_arr(p->wc_w, nnz) || !finite_arr(p->wc_K, 6ll * p->n_wc)) fail(PBNG_ENAN, "problem %d: non-finite weak constraint", q);
     }
     if (p->n_planes < 0) fail(PBNG_EINVAL, "problem %d: bad n_planes", q);
@@ -1619,17 +1635,7 @@ int32_t pbng_color(const pbng_problem* p, int32_t* colors_out, int32_t* n_colors
 {
     return guard([&] {
         if (!p || !colors_out || !n_colors_out) fail(PBNG_EINVAL, "null argument");
-        if (p->n_verts <= 0 || p->n_tets < 0) fail(PBNG_EINVAL, "bad sizes");
-        if (p->n_tets > 0 && !p->tets) fail(PBNG_EINVAL, "tets is null");
-        for (int64_t e = 0; e < 4ll * p->n_tets; ++e)
-            if (p->tets[e] < 0 || p->tets[e] >= p->n_verts) fail(PBNG_EMESH, "tet vertex out of range");
-        for (int k = 0; k < p->n_dirichlet; ++k)
-            if (p->dirichlet_idx[k] < 0 || p->dirichlet_idx[k] >= p->n_verts) fail(PBNG_EINVAL, "Dirichlet index out of range");
-        if (p->n_wc > 0) {
-            if (!p->wc_ptr || !p->wc_vert) fail(PBNG_EINVAL, "weak-constraint arrays are null");
-            for (int k = 0; k < p->wc_ptr[p->n_wc]; ++k)
-                if (p->wc_vert[k] < 0 || p->wc_vert[k] >= p->n_verts) fail(PBNG_EMESH, "weak-constraint vertex out of range");
-        }
+        validate_topology(p, 0);
         *n_colors_out = color_instance(p, colors_out);
         return PBNG_OK;
     });

@@ -126,3 +126,35 @@ def torch_has_gpu():
         return torch.cuda.is_available()
     except Exception:
         return False
+
+
+def _raw_color(s, n_verts):
+    out = np.zeros(n_verts, np.int32)
+    n = ctypes.c_int32()
+    return pbng.lib().pbng_color(ctypes.byref(s), out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                 ctypes.byref(n))
+
+
+def test_color_rejects_malformed_structure_before_reading_it():
+    from tests.test_oracle_solve import with_extras, small_twist
+    hp = pbng.problem_from_scenario(with_extras(small_twist(4)))
+    assert hp.struct().n_wc > 0 and hp.struct().n_dirichlet > 0
+    s = hp.struct()
+    assert _raw_color(s, hp.n_verts) == 0
+    s = hp.struct()
+    s.dirichlet_idx = None                                     # Dirichlet list missing
+    assert _raw_color(s, hp.n_verts) == -1
+    s = hp.struct()
+    s.n_dirichlet = hp.n_verts + 1                             # more prescribed vertices than vertices
+    assert _raw_color(s, hp.n_verts) == -1
+    s = hp.struct()
+    bad_ptr = np.array(np.ctypeslib.as_array(s.wc_ptr, (s.n_wc + 1,)), np.int32)
+    bad_ptr[1], bad_ptr[0] = 0, 1                              # constraint CSR not starting at 0
+    s.wc_ptr = bad_ptr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    assert _raw_color(s, hp.n_verts) == -1
+    s = hp.struct()
+    s.wc_vert = None
+    assert _raw_color(s, hp.n_verts) == -1
+    s = hp.struct()
+    s.n_tets = 1 << 29                                         # incidence would overflow int32
+    assert _raw_color(s, hp.n_verts) == -1

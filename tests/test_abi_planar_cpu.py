@@ -76,6 +76,13 @@ def test_planar_workspace_rejects_invalid_problems_before_device_work():
     assert _create_err(hp, colors=col) == -4
     hp = fresh()
     s = hp.struct()
+    s.n_tris = 2 ** 31 // 3 + 1                      # incidence would overflow int32; tris not read
+    h = ctypes.c_void_p()
+    assert pbng2d.lib().pbng2d_workspace_create(ctypes.byref(s), None, pbng.REAL["f32"],
+                                                ctypes.byref(h)) == -8
+    assert not h.value
+    hp = fresh()
+    s = hp.struct()
     h = ctypes.c_void_p()
     assert pbng2d.lib().pbng2d_workspace_create(ctypes.byref(s), None, pbng.REAL["mixed"],
                                                 ctypes.byref(h)) == -1
