@@ -58,7 +58,8 @@ def parse():
                     help="run only the planar (triangle-mesh) report and print it (profiling)")
     ap.add_argument("--planar-sweeps", type=int, default=200)
     ap.add_argument("--only", default="",
-                    help="run only this sub-report (batched, backward_euler, ...) and print it (profiling)")
+                    help="run only these sub-reports (comma-separated: batched, backward_euler, ...) "
+                         "and print them (profiling)")
     return ap.parse_args()
 
 
@@ -113,11 +114,13 @@ def main():
     if args.only:
         from paper_2306_09021_amd import pbng
         from paper_2306_09021_amd import scenarios as S
-        fn = sub_reports(args, pbng, S, torch, stream).get(args.only)
-        if fn is None:
-            print("unknown sub-report %r" % args.only, file=sys.stderr)
+        reports = sub_reports(args, pbng, S, torch, stream)
+        names = args.only.split(",")
+        unknown = [n for n in names if n not in reports]
+        if unknown:
+            print("unknown sub-report(s) %r" % unknown, file=sys.stderr)
             sys.exit(2)
-        print(json.dumps({args.only: fn()}))
+        print(json.dumps({n: reports[n]() for n in names}))
         return
 
     sc = S.config_beam_f32()

@@ -988,7 +988,9 @@ SweepArgs<R, PR> sweep_args(pbng_workspace* ws, double omega, double gamma, int 
     a.imu = ws->imu.as<R>();
     a.ilam = ws->ilam.as<R>();
     a.fext = ws->fext.as<R4>();
-    a.vinst = ws->vinst.as<int>();
+    // one instance: no per-vertex instance lookup (the solve loops run
+    // sweeps only while that instance is active)
+    a.vinst = ws->n_inst > 1 ? ws->vinst.as<int>() : nullptr;
     a.active = ws->active.as<int>();
     a.wvptr = ws->wvptr.as<int>();
     a.wv_c = ws->wv_c.as<int>();

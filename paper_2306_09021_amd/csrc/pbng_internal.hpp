@@ -76,7 +76,8 @@ struct SweepArgs {
     const R* imu;          // [n_inst] mu, lambda of each instance (40-byte
     const R* ilam;         //          Neo-Hookean records only)
     const R4* fext;        // [n_free] lumped external force
-    const int* vinst;      // [n_free] instance of each free vertex
+    const int* vinst;      // [n_free] instance of each free vertex; null with one
+                           // instance (instance 0, active whenever sweeps run)
     const int* active;     // [n_inst] 1 while the instance iterates
     const int* wvptr;      // [n_verts + 1] weak constraints per vertex
     const int* wv_c;

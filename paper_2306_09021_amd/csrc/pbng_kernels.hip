@@ -441,7 +441,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
     const int kb = at(a.vptr, v), ke = at(a.vptr, v + 1);
     const P4 xw = at(a.W, v);
     int inst = 0;
-    if (GEN == 1) {
+    if (GEN == 1 && a.vinst) {
         inst = at(a.vinst, v);
         if (!at(a.active, inst)) {
             if (ACCEL && lane == 0) *ptr_at(a.N, v) = xw;
