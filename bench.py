@@ -410,8 +410,12 @@ def differentiable_report(pbng, S, torch, stream, n_inst):
     ta = time.perf_counter() - t0
     fw_upd = sum(s["vertex_updates"] for s in st)
     ad_upd = sum(s["vertex_updates"] for s in sta)
+    # roofline of the forward sweep (algorithmic bytes in the FP32 form of
+    # the definition: 60 B per visit without the 8 B of per-tet Lame)
+    roof = sweep_roofline(ws, x0, so, torch, stream)
     others = {m: _adjoint_model(pbng, S, torch, stream, m, so, ao) for m in ("corotated", "snh")}
     return {"instances": len(scs), "vertices": int(x0.shape[0]), "real": "mixed",
+            "forward_sweep_roofline": roof,
             "other_models_8_instances": others,
             "forward": {"rel_tol": 1e-5, "wall_s": round(tf, 3),
                         "converged": int(sum(s["converged"] for s in st)),
