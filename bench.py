@@ -185,13 +185,19 @@ def main():
     avg_bytes = total_bytes / n_launch
     achieved = avg_bytes / avg_dur / 1e9
     tr, tr_note = traffic_per_launch()
+    copy_big = copy_bandwidth(torch, stream, 1 << 30, 10)
+    copy_same = copy_bandwidth(torch, stream, int(avg_bytes), n_launch)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": (int(tr) if tr is not None else None),
                 "traffic_note": tr_note,
                 "kernel": "k_phase (colour-phase vertex update)",
                 "avg_launch_us": round(avg_dur * 1e6, 2),
-                "avg_algorithmic_bytes": int(avg_bytes), "launches_timed": n_launch}
+                "avg_algorithmic_bytes": int(avg_bytes), "launches_timed": n_launch,
+                "copy_GBs_1GiB": round(copy_big, 1),
+                "frac_of_copy_1GiB": round(achieved / copy_big, 4),
+                "copy_GBs_same_bytes_per_launch": round(copy_same, 1),
+                "frac_of_copy_same_bytes": round(achieved / copy_same, 4)}
 
     progress("beam: %.3e vertex updates/s, k_phase %.2f us per launch" % (value, avg_dur * 1e6))
     cpu = None if args.no_cpu_baseline else cpu_baseline(sc, args.cpu_sweeps)
@@ -460,6 +466,28 @@ def _adjoint_model(pbng, S, torch, stream, model, so, ao, n_inst=8):
             "adjoint_wall_s": round(ta, 3), "adjoint_converged": int(sum(s["converged"] for s in sta)),
             "adjoint_max_sweeps": int(max(s["sweeps"] for s in sta)),
             "adjoint_max_rel_residual": max(s["rel_residual"] for s in sta)}
+
+
+def copy_bandwidth(torch, stream, moved_bytes, reps):
+    """Device-to-device copy bandwidth (bytes read + bytes written per second)
+    of back-to-back copies that each move moved_bytes in total, timed with
+    HIP events on the launch stream: the measured ceiling that the phase
+    kernels are compared with, once at 1 GiB and once at their own bytes
+    per launch."""
+    n = max(1, moved_bytes // 8)
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t = ev0.elapsed_time(ev1) * 1e-3 / reps
+    return 8.0 * n / t / 1e9
 
 
 def sweep_roofline(ws, x, opts, torch, stream, n_sweeps=10):
