@@ -633,7 +633,7 @@ def collision_report(pbng, S, torch, stream, frames=8):
     so = pbng.solve_opts(max_sweeps=iters, rel_tol=0.0, check_every=iters, accel="chebyshev",
                          rho=0.95, gamma=1.2, safeguard="backtrack")
     half = sc.n_verts // 2
-    right = sc.dirichlet_idx >= half
+    right = torch.tensor(np.nonzero(sc.dirichlet_idx >= half)[0], device="cuda")
     xd0 = torch.tensor(sc.dirichlet_x, dtype=torch.float64, device="cuda")
     x_prev = torch.tensor(sc.initial_iterate(), dtype=torch.float64, device="cuda")
     x_n = x_prev.clone()
@@ -645,7 +645,7 @@ def collision_report(pbng, S, torch, stream, frames=8):
         for _ in range(sub):
             t += dt
             xd = xd0.clone()
-            xd[torch.tensor(right, device="cuda"), 0] -= vel * t
+            xd[right, 0] -= vel * t
             ws.set_dirichlet(xd, stream=stream)
             pairs, normals = ws.detect_contacts(x, radius, max_pairs=1 << 16, stream=stream)
             ws.set_contacts(pairs, normals, kn, stream=stream)

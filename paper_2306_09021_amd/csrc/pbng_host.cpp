@@ -317,14 +317,17 @@ struct pbng_workspace {
     // the list of vertices recoloured into it
     std::vector<int> h_color, h_rvptr, h_rv, h_vinst;
     std::vector<int4> h_tet;
+    // one launch per colour: home range [hb, he) of internal free
+    // vertices, then the slice [lb, le) of xlist (vertices recoloured into
+    // the colour)
     struct PhaseSpec {
-        int color, vb, ve;
-        bool list;
+        int color, hb, he, lb, le;
     };
     std::vector<PhaseSpec> phases;
     bool moved_any = false;
     int ncol_dyn = 0;
     Dev pcol, xlist;
+    Pinned stage;                          // staging of batched uploads
     // proximity detection: candidate surface vertices (built on first use)
     // and scratch sized for n_cand candidates and det_cap pairs
     int n_cand = -1;
@@ -397,7 +400,14 @@ void upload_real(Dev& d, const std::vector<double>& v)
     d.upload(t);
 }
 
-SegPlan make_plan(const std::vector<int64_t>& seg, Dev& cb, Dev& ce, Dev& qp, Dev& part)
+template <class R>
+void stage_real(Uploader& up, Dev& d, const std::vector<double>& v)
+{
+    std::vector<R> t(v.begin(), v.end());
+    up.add(d, t);
+}
+
+SegPlan make_plan(const std::vector<int64_t>& seg, Dev& cb, Dev& ce, Dev& qp, Dev& part, Uploader& up)
 {
     const int64_t chunk = 4096;
     std::vector<int64_t> b, e;
@@ -410,10 +420,10 @@ SegPlan make_plan(const std::vector<int64_t>& seg, Dev& cb, Dev& ce, Dev& qp, De
         }
     }
     q.back() = int(b.size());
-    cb.upload(b);
-    ce.upload(e);
-    qp.upload(q);
-    part.alloc(std::max<size_t>(1, b.size()) * sizeof(double));
+    up.add(cb, b);
+    up.add(ce, e);
+    up.add(qp, q);
+    part.reserve(std::max<size_t>(1, b.size()) * sizeof(double));
     SegPlan P;
     P.cbeg = cb.as<int64_t>();
     P.cend = ce.as<int64_t>();
@@ -472,7 +482,7 @@ hipError_t build_visits(pbng_workspace* ws, const double* mu, const double* lam,
 // Launch plan of a sweep from the current colouring: colour c runs its home
 // range [col_ptr[c], col_ptr[c+1]) (vertices recoloured away are skipped on
 // the device) and then, if any, the list of vertices recoloured into c.
-void rebuild_phases(pbng_workspace* ws)
+void rebuild_phases(pbng_workspace* ws, Uploader& up)
 {
     const int nf = int(ws->nfree);
     int ncol = ws->ncol;
@@ -491,18 +501,21 @@ void rebuild_phases(pbng_workspace* ws)
     ws->phases.clear();
     std::vector<int> list;
     for (int c = 0; c < ncol; ++c) {
-        if (c < ws->ncol && ws->col_ptr[c + 1] > ws->col_ptr[c])
-            ws->phases.push_back({c, ws->col_ptr[c], ws->col_ptr[c + 1], false});
-        if (c < int(moved_in.size()) && !moved_in[c].empty()) {
-            const int b = int(list.size());
-            list.insert(list.end(), moved_in[c].begin(), moved_in[c].end());
-            ws->phases.push_back({c, b, int(list.size()), true});
+        pbng_workspace::PhaseSpec ph{c, 0, 0, int(list.size()), int(list.size())};
+        if (c < ws->ncol) {
+            ph.hb = ws->col_ptr[c];
+            ph.he = ws->col_ptr[c + 1];
         }
+        if (c < int(moved_in.size())) {
+            list.insert(list.end(), moved_in[c].begin(), moved_in[c].end());
+            ph.le = int(list.size());
+        }
+        if (ph.he > ph.hb || ph.le > ph.lb) ws->phases.push_back(ph);
     }
     if (ws->moved_any) {
         std::vector<int> pc(ws->h_color.begin(), ws->h_color.begin() + nf);
-        ws->pcol.upload(pc);
-        ws->xlist.upload(list);
+        up.add(ws->pcol, pc);
+        up.add(ws->xlist, list);
     }
 }
 
@@ -561,7 +574,7 @@ void recolor_contacts(pbng_workspace* ws)
 // instance: the global constraint list, the per-vertex CSR (constraint,
 // weight), and the instance-major energy slots (tets, vertices,
 // constraints of each instance) with their segmented-sum plan.
-void install_constraints(pbng_workspace* ws)
+void install_constraints(pbng_workspace* ws, Uploader& up)
 {
     const int n = ws->n_inst;
     const int64_t nv = ws->nv, nt = ws->nt;
@@ -616,24 +629,24 @@ void install_constraints(pbng_workspace* ws)
     ws->n_wc = int(wc_ptr.size()) - 1;
     ws->any_wc = ws->n_wc > 0 || ws->n_planes > 0;
     auto upR = [&](Dev& d, const std::vector<double>& v) {
-        if (ws->math64()) upload_real<double>(d, v);
-        else upload_real<float>(d, v);
+        if (ws->math64()) stage_real<double>(up, d, v);
+        else stage_real<float>(up, d, v);
     };
-    ws->wvptr.upload(wvptr);
-    ws->wv_c.upload(wv_c);
+    up.add(ws->wvptr, wvptr);
+    up.add(ws->wv_c, wv_c);
     upR(ws->wv_s, wv_s);
-    ws->wc_ptr.upload(wc_ptr);
-    ws->wc_vert.upload(wc_vert);
+    up.add(ws->wc_ptr, wc_ptr);
+    up.add(ws->wc_vert, wc_vert);
     upR(ws->wc_w, wc_w);
     upR(ws->wc_K, wc_K);
-    ws->wv_s64.upload(wv_s);
-    ws->wc_w64.upload(wc_w);
-    ws->wc_K64.upload(wc_K);
-    ws->wc_eidx.upload(wc_eidx);
-    ws->tet_eidx.upload(tet_eidx);
-    ws->vert_eidx.upload(vert_eidx);
-    ws->ebuf.alloc(std::max<int64_t>(1, eo) * sizeof(double));
-    ws->plan_e = make_plan(seg_e, ws->seg_e_cb, ws->seg_e_ce, ws->seg_e_q, ws->seg_e_part);
+    up.add(ws->wv_s64, wv_s);
+    up.add(ws->wc_w64, wc_w);
+    up.add(ws->wc_K64, wc_K);
+    up.add(ws->wc_eidx, wc_eidx);
+    up.add(ws->tet_eidx, tet_eidx);
+    up.add(ws->vert_eidx, vert_eidx);
+    ws->ebuf.reserve(std::max<int64_t>(1, eo) * sizeof(double));
+    ws->plan_e = make_plan(seg_e, ws->seg_e_cb, ws->seg_e_ce, ws->seg_e_q, ws->seg_e_part, up);
 }
 
 void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const int32_t* colors_in)
@@ -952,8 +965,10 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     upP(ws->xd_int, xd_int);
     ws->dir_internal.upload(dir_internal);
     ws->dir_pos.upload(dir_pos);
-    ws->plan_r = make_plan(seg_r, ws->seg_r_cb, ws->seg_r_ce, ws->seg_r_q, ws->seg_r_part);
-    install_constraints(ws);
+    Uploader up;
+    ws->plan_r = make_plan(seg_r, ws->seg_r_cb, ws->seg_r_ce, ws->seg_r_q, ws->seg_r_part, up);
+    install_constraints(ws, up);
+    up.flush(ws->stage, nullptr);
     ws->out_r.alloc(n * sizeof(double));
     ws->out_e.alloc(n * sizeof(double));
     ws->W.alloc(nv * ws->r4());
@@ -966,7 +981,8 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     ws->h_color.assign(nv, -1);
     for (int c = 0; c < ws->ncol; ++c)
         for (int k = ws->col_ptr[c]; k < ws->col_ptr[c + 1]; ++k) ws->h_color[k] = c;
-    rebuild_phases(ws);
+    rebuild_phases(ws, up);
+    up.flush(ws->stage, nullptr);
 }
 
 template <class R, class PR>
@@ -1007,6 +1023,8 @@ SweepArgs<R, PR> sweep_args(pbng_workspace* ws, double omega, double gamma, int 
     a.vlist = nullptr;
     a.pcol = nullptr;
     a.pcolor = 0;
+    a.list_from = 0;
+    a.list_beg = 0;
     a.omega = PR(omega);
     a.gamma = PR(gamma);
     a.max_halvings = max_halvings;
@@ -1111,17 +1129,29 @@ void ensure_ring(pbng_workspace* ws)
     if (!ws->N.p) ws->N.alloc(ws->nv * ws->r4());
 }
 
+// Launch slots of one colour's phase (home range, then recoloured list)
+// into the kernel arguments; returns the slot range [vb, ve).
+template <class Args>
+std::pair<int, int> phase_slots(const pbng_workspace* ws, const pbng_workspace::PhaseSpec& ph, Args& a)
+{
+    const bool has_list = ph.le > ph.lb;
+    a.vlist = has_list ? ws->xlist.as<int>() : nullptr;
+    a.pcol = ws->moved_any ? ws->pcol.as<int>() : nullptr;
+    a.pcolor = ph.color;
+    a.list_from = ph.he;
+    a.list_beg = ph.lb;
+    return {ph.hb, ph.he + (ph.le - ph.lb)};
+}
+
 template <class R, class PR>
 void launch_sweep(pbng_workspace* ws, const pbng_solve_opts* o, double omega, double gamma, hipStream_t s)
 {
     const bool accel = o->accel != PBNG_ACCEL_NONE;
     SweepArgs<R, PR> a = sweep_args<R, PR>(ws, omega, gamma, o->max_halvings);
     for (const auto& ph : ws->phases) {
-        a.vlist = ph.list ? ws->xlist.as<int>() : nullptr;
-        a.pcol = (!ph.list && ws->moved_any) ? ws->pcol.as<int>() : nullptr;
-        a.pcolor = ph.color;
+        const auto [vb, ve] = phase_slots(ws, ph, a);
         hipchk(launch_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, ph.color), accel,
-                                   safe_effective(ws, o), ws->kernel_mode(), ph.vb, ph.ve, s),
+                                   safe_effective(ws, o), ws->kernel_mode(), vb, ve, s),
                "sweep launch");
     }
     if (accel) std::swap(ws->W.p, ws->N.p);
@@ -1325,6 +1355,8 @@ AdjArgs<R, PR> adj_args(pbng_workspace* ws, double omega, double gamma)
     a.vlist = nullptr;
     a.pcol = nullptr;
     a.pcolor = 0;
+    a.list_from = 0;
+    a.list_beg = 0;
     a.omega = PR(omega);
     a.gamma = PR(gamma);
     return a;
@@ -1390,11 +1422,9 @@ int32_t adjoint_t(pbng_workspace* ws, const void* x_eq, const void* dLdx, double
         omega_prev = omega;
         AdjArgs<R, PR> a = adj_args<R, PR>(ws, omega, accel ? o->gamma : 1.0);
         for (const auto& ph : ws->phases) {
-            a.vlist = ph.list ? ws->xlist.as<int>() : nullptr;
-            a.pcol = (!ph.list && ws->moved_any) ? ws->pcol.as<int>() : nullptr;
-            a.pcolor = ph.color;
+            const auto [vb, ve] = phase_slots(ws, ph, a);
             hipchk(launch_adjoint_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, ph.color), accel,
-                                               ws->any_wc || ws->inertia || ws->moved_any, ph.vb, ph.ve, s),
+                                               ws->any_wc || ws->inertia || ws->moved_any, vb, ve, s),
                    "adjoint launch");
         }
         if (accel) std::swap(ws->L.p, ws->LN.p);
@@ -1467,9 +1497,7 @@ struct Events {
     }
 };
 
-// Measured choice of the lanes per vertex of every colour (the tile of the
-// colour-phase kernel) and of the sweeps per captured graph.
-// The launches of one colour (its home range and the list of vertices
+// The launch of one colour (its home range and the list of vertices
 // recoloured into it), with the blend weights 1.
 template <class R, class PR>
 void phase_t(pbng_workspace* ws, const pbng_solve_opts* o, int color, hipStream_t s)
@@ -1477,15 +1505,15 @@ void phase_t(pbng_workspace* ws, const pbng_solve_opts* o, int color, hipStream_
     SweepArgs<R, PR> a = sweep_args<R, PR>(ws, 1.0, 1.0, o->max_halvings);
     for (const auto& ph : ws->phases) {
         if (ph.color != color) continue;
-        a.vlist = ph.list ? ws->xlist.as<int>() : nullptr;
-        a.pcol = (!ph.list && ws->moved_any) ? ws->pcol.as<int>() : nullptr;
-        a.pcolor = ph.color;
+        const auto [vb, ve] = phase_slots(ws, ph, a);
         hipchk(launch_phase<R, PR>(a, ws->kmodel, pick_lanes(ws, o->lanes, color), o->accel != PBNG_ACCEL_NONE,
-                                   safe_effective(ws, o), ws->kernel_mode(), ph.vb, ph.ve, s),
+                                   safe_effective(ws, o), ws->kernel_mode(), vb, ve, s),
                "phase");
     }
 }
 
+// Measured choice of the lanes per vertex of every colour (the tile of the
+// colour-phase kernel) and of the sweeps per captured graph.
 template <class R, class PR>
 void autotune_t(pbng_workspace* ws, const void* x, const pbng_solve_opts* o, pbng_solve_opts* tuned,
                 hipStream_t s)
@@ -1824,14 +1852,17 @@ int32_t pbng_workspace_set_contacts(pbng_workspace* ws, int32_t n, const int32_t
             const double K[6] = {k_n * nx * nx, k_n * nx * ny, k_n * nx * nz, k_n * ny * ny, k_n * ny * nz, k_n * nz * nz};
             for (int j = 0; j < 6; ++j) cts[k].K[j] = K[j];
         }
-        hipchk(hipStreamSynchronize(s), "sync");
+        // the constraint arrays keep their allocations (Dev::reserve): no
+        // queued work may still read them
+        hipchk(hipDeviceSynchronize(), "contacts");
         ws->contacts = std::move(cts);
-        install_constraints(ws);
+        Uploader up;
+        install_constraints(ws, up);
         recolor_contacts(ws);
-        rebuild_phases(ws);
+        rebuild_phases(ws, up);
+        up.flush(ws->stage, s);
         ws->drop_graph();
         ws->ring_valid = false;
-        hipchk(hipDeviceSynchronize(), "contacts");
         return PBNG_OK;
     });
 }

@@ -91,12 +91,15 @@ struct SweepArgs {
     int* rejected;         // [n_inst]
     const R* inert;        // [n_free] m_ii / dt^2 (backward Euler), or null
     const P4* xhat;        // [n_free] 2 x^n - x^{n-1}
-    // recoloured vertices (general kernel only): a list launch takes its
-    // vertices from vlist[vbeg, vend); a range launch skips vertices whose
-    // current colour pcol[v] is not pcolor (pcol null: none moved)
+    // recoloured vertices (general kernel only): the launch slots
+    // [vbeg, list_from) are the colour's home range, whose vertices v are
+    // skipped when their current colour pcol[v] is not pcolor (pcol null:
+    // none moved); slots v >= list_from (vlist non-null) take the vertex
+    // vlist[v - list_from + list_beg] recoloured into pcolor
     const int* vlist;
     const int* pcol;
     int pcolor;
+    int list_from, list_beg;
     PR omega, gamma;
     int max_halvings;
 };
@@ -288,6 +291,7 @@ struct AdjArgs {
     const int* vlist;      // as in SweepArgs
     const int* pcol;
     int pcolor;
+    int list_from, list_beg;
     PR omega, gamma;
 };
 template <class R, class PR>

@@ -435,7 +435,7 @@ __global__ __launch_bounds__(kBlock) void k_phase(SweepArgs<R, PR> a, int vbeg, 
     if (GEN == 1) {
         // vertices recoloured after new weak constraints (whole lane groups
         // return together)
-        if (a.vlist) v = at(a.vlist, v);
+        if (a.vlist && v >= a.list_from) v = at(a.vlist, v - a.list_from + a.list_beg);
         else if (a.pcol && at(a.pcol, v) != a.pcolor) return;
     }
     const int kb = at(a.vptr, v), ke = at(a.vptr, v + 1);
@@ -749,7 +749,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_phase(AdjArgs<R, PR> a, int vbeg
     const int lane = gid & (LANES - 1);
     if (v >= vend) return;
     if (WC) {
-        if (a.vlist) v = at(a.vlist, v);
+        if (a.vlist && v >= a.list_from) v = at(a.vlist, v - a.list_from + a.list_beg);
         else if (a.pcol && at(a.pcol, v) != a.pcolor) return;
     }
     const V3<PR> xi = xyz(at(a.X, v));
