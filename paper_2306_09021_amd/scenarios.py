@@ -233,6 +233,79 @@ def two_blocks(n: int = 8, gap: float = 0.02, model: str = COROTATED, E: float =
                     dirichlet_idx=didx, dirichlet_x=dx, x0=X.copy(), density=density)
 
 
+def icosphere(subdiv: int):
+    """Unit icosphere: vertices [n, 3] on the sphere and outward-oriented
+    (counter-clockwise seen from outside) triangles [m, 3]; each
+    subdivision splits every triangle into four at the normalised edge
+    midpoints (12 vertices and 20 faces, then 42 / 80, 162 / 320, ...)."""
+    t = (1.0 + 5.0 ** 0.5) / 2.0
+    V = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0), (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    V = [np.array(v, float) / np.linalg.norm(v) for v in V]
+    F = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11), (1, 5, 9), (5, 11, 4), (11, 10, 2),
+         (10, 7, 6), (7, 1, 8), (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9), (4, 9, 5),
+         (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(subdiv):
+        mid = {}
+
+        def m(a, b):
+            k = (min(a, b), max(a, b))
+            if k not in mid:
+                v = V[a] + V[b]
+                V.append(v / np.linalg.norm(v))
+                mid[k] = len(V) - 1
+            return mid[k]
+        F = [f for (a, b, c) in F for f in ((a, m(a, b), m(c, a)), (b, m(b, c), m(a, b)),
+                                            (c, m(c, a), m(b, c)), (m(a, b), m(b, c), m(c, a)))]
+    return np.array(V), np.array(F, np.int32)
+
+
+def hedgehog(subdiv: int = 2, model: str = NEOHOOKEAN, E: float = 1e4, nu: float = 0.3,
+             seed: int = 11, squeeze: float = 0.8, jitter: float = 0.02) -> Scenario:
+    """One free vertex of high valence: vertex 0 at the centre of a unit
+    icosphere, one tet per sphere triangle (20 * 4^subdiv tets, all
+    incident to vertex 0).  The lower half of the sphere is prescribed,
+    squeezed along y by `squeeze`; the rest starts jittered (seeded)."""
+    V, F = icosphere(subdiv)
+    X = np.vstack([np.zeros((1, 3)), V])
+    # (centre, a, b, c) with (a, b, c) counter-clockwise seen from outside
+    # has det[Xa - X0, Xb - X0, Xc - X0] > 0: positive rest volume
+    tets = np.concatenate([np.zeros((F.shape[0], 1), np.int32), F + 1], axis=1).astype(np.int32)
+    rng = np.random.default_rng(seed)
+    low = np.nonzero(X[:, 1] < -0.2)[0].astype(np.int32)
+    xd = X[low] * np.array([1.0, squeeze, 1.0])
+    x0 = X + jitter * rng.uniform(-1.0, 1.0, X.shape)
+    x0[low] = xd
+    return Scenario(name="hedgehog_%d" % subdiv, rest_pos=X, tets=tets, model=model, E=np.asarray(E),
+                    nu=np.asarray(nu), dirichlet_idx=low, dirichlet_x=xd, x0=x0)
+
+
+def clique_chain(n: int = 64, seed: int = 12) -> Scenario:
+    """n free vertices on a line and a Dirichlet anchor (vertex n), no tets:
+    one weak constraint binds all n + 1 (weights 1 and -n, K = I), so the
+    free vertices take n different colours; springs (K = 10 I, weights
+    +1 / -1) join consecutive vertices and vertex 0 to the anchor; seeded
+    normal nodal forces and a jittered start."""
+    rng = np.random.default_rng(seed)
+    X = np.zeros((n + 1, 3))
+    X[:, 0] = np.arange(n + 1, dtype=float)
+    w = np.ones(n + 1)
+    w[n] = -float(n)
+    ptr, vert, wts, K = [0, n + 1], list(range(n + 1)), list(w), [[1.0, 0, 0, 1.0, 0, 1.0]]
+    for a, b in [(j, j + 1) for j in range(n - 1)] + [(0, n)]:
+        vert += [a, b]
+        wts += [1.0, -1.0]
+        ptr.append(len(vert))
+        K.append([10.0, 0, 0, 10.0, 0, 10.0])
+    x0 = X + 0.1 * rng.uniform(-1.0, 1.0, X.shape)
+    x0[n] = X[n]
+    return Scenario(name="clique_chain_%d" % n, rest_pos=X, tets=np.zeros((0, 4), np.int32), model=NEOHOOKEAN,
+                    E=np.asarray(1e4), nu=np.asarray(0.3), dirichlet_idx=np.array([n], np.int32),
+                    dirichlet_x=X[n:].copy(), x0=x0, nodal_force=rng.normal(size=X.shape),
+                    wc_ptr=np.array(ptr, np.int32), wc_vert=np.array(vert, np.int32),
+                    wc_w=np.array(wts), wc_K=np.array(K))
+
+
 def config_plain_f64() -> Scenario:
     """Plain PBNG in FP64: 10^3-vertex unit cube (3,645 tets), fixed-corotated,
     E = 1e4, nu = 0.3, bottom pinned, top stretched 1.3x and twisted 90 deg,

@@ -158,3 +158,30 @@ def test_color_rejects_malformed_structure_before_reading_it():
     s = hp.struct()
     s.n_tets = 1 << 29                                         # incidence would overflow int32
     assert _raw_color(s, hp.n_verts) == -1
+
+
+def _clique(n):
+    """n free vertices bound by one weak constraint (so all n colours
+    differ) plus one Dirichlet anchor in the same constraint."""
+    a = np.zeros((n + 1, 3))
+    a[:, 0] = np.arange(n + 1)
+    w = np.ones(n + 1)
+    w[n] = -float(n)
+    return S.Scenario(name="clique%d" % n, rest_pos=a, tets=np.zeros((0, 4), np.int32), model="nh",
+                      E=np.asarray(1e4), nu=np.asarray(0.3), dirichlet_idx=np.array([n], np.int32),
+                      dirichlet_x=a[n:], x0=a, wc_ptr=np.array([0, n + 1], np.int32),
+                      wc_vert=np.arange(n + 1, dtype=np.int32), wc_w=w,
+                      wc_K=np.array([[1.0, 0, 0, 1.0, 0, 1.0]]))
+
+
+def test_color_limit_is_64_colours():
+    """The library's colour sets are 64-bit masks: 64 mutually constrained
+    free vertices take colours 0..63 exactly as the oracle gives them, and
+    a 65th is rejected with PBNG_ECOLOR (the oracle, unbounded, gives 65)."""
+    c1, n1, c2, n2 = _colors_both(_clique(64))
+    assert n1 == n2 == 64 and np.array_equal(c1, c2)
+    assert sorted(c1[:64]) == list(range(64)) and c1[64] == -1
+    with pytest.raises(pbng.PBNGError) as e:
+        pbng.color(pbng.problem_from_scenario(_clique(65)))
+    assert e.value.code == -4
+    assert O.color(O.make_problem(_clique(65)))[1] == 65

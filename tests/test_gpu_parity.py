@@ -537,3 +537,34 @@ def test_record_form_follows_material_updates():
             xo, _ = O.solve(op, col, sc.initial_iterate(), max_sweeps=30, accel="chebyshev", rho=0.9,
                             gamma=1.3, safeguard="backtrack")
             assert rel_err(host(x), xo) <= tol, (k, real)
+
+
+@pytest.mark.parametrize("model", ["nh", "corotated", "snh"])
+@pytest.mark.parametrize("real,tol", [("f64", 1e-10), ("f32", 1e-5)])
+@pytest.mark.parametrize("lanes", [0, 1, 64])
+def test_high_valence_vertex_parity(model, real, tol, lanes):
+    """A free vertex with 1280 incident tets (the centre of a three times
+    subdivided icosphere): one lane takes all 1280 visits, 64 lanes take 20
+    each (ten passes of the two-visit loop)."""
+    sc = S.hedgehog(3, model)
+    announce("hedgehog 1280 tets %s %s lanes=%d" % (model, real, lanes))
+    xg, stg, _ = _run_gpu(sc, real, 20, safeguard="backtrack", lanes=lanes)
+    xo, sto, op = oracle_solve(sc, 20, safeguard="backtrack")
+    e = rel_err(xg, xo)
+    print("rel err", e, "disp err", disp_err(xg, xo, sc.rest_pos))
+    assert stg["n_colors"] == O.color(op)[1] == 7
+    assert e <= tol
+
+
+@pytest.mark.parametrize("real,tol", [("f64", 1e-10), ("f32", 1e-5)])
+def test_sixty_four_colours_parity(real, tol):
+    """The colour limit: 64 free vertices bound by one weak constraint take
+    64 colours, so a sweep is 64 one-vertex phases."""
+    sc = S.clique_chain(64)
+    announce("clique chain 64 colours %s" % real)
+    xg, stg, _ = _run_gpu(sc, real, 30, safeguard="backtrack")
+    xo, sto, _ = oracle_solve(sc, 30, safeguard="backtrack")
+    assert stg["n_colors"] == 64
+    e = rel_err(xg, xo)
+    print("rel err", e)
+    assert e <= tol
