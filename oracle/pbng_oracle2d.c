@@ -5,7 +5,9 @@
  * (Sec. "Discretization"), 2x2 deformation gradients, the constitutive
  * models of Eq. (cor) and Eq. (nh) with d = 2, the modified Hessian of
  * Eq. (mod_hess_dens) / (mod_hess) with the 2x2 cofactor matrix, and 2x2
- * local systems in the update of Eq. (pbgn_update) / (pbgn_dx).
+ * local systems in the update of Eq. (pbgn_update) / (pbgn_dx), with the
+ * weak constraints of Sec. "Weak Constraints", contact half-planes and the
+ * backward-Euler inertia of Eq. (fem_be) in their d = 2 form.
  *
  * TEST INFRASTRUCTURE ONLY.  Built into oracle/liboracle.so next to the
  * 3-D oracle and loaded by tests/, __graft_entry__.smoke() and the
@@ -33,7 +35,14 @@
 #define OR2_SAFEGUARD_BACKTRACK 1
 
 /* A planar problem; arrays owned by the caller.  Matrices are row-major
- * 2x2, M[2 * r + c]. */
+ * 2x2, M[2 * r + c].  The energy is the sum of A0 Psi(F) over triangles,
+ * -y . fhat, the weak constraints of Sec. "Weak Constraints" with d = 2
+ * (1/2 C_c^T K_c C_c, C_c = sum_j w_j y_{v_j}, K_c symmetric 2x2 stored as
+ * (xx, xy, yy)), for every vertex and contact half-plane (n_x, n_y, d, k)
+ * the penalty 1/2 k min(0, n . y - d)^2, and, with minert non-null, the
+ * backward-Euler inertia of Eq. (fem_be) written as the incremental
+ * potential: sum_i 1/2 minert_i |y_i - xhat_i|^2, minert_i = m_ii / dt^2
+ * (zero on Dirichlet vertices), xhat = 2 x^n - x^{n-1}. */
 typedef struct {
     int32_t nv, nt, model;
     const double* X;        /* [nv][2] rest positions                    */
@@ -42,6 +51,15 @@ typedef struct {
     const double* lam;      /* [nt] Lame lambda                          */
     const double* fext;     /* [nv][2] lumped external force             */
     const uint8_t* is_dir;  /* [nv] 1 = Dirichlet                        */
+    int32_t n_wc;
+    const int32_t* wc_ptr;  /* [n_wc + 1]                                */
+    const int32_t* wc_vert; /* [nnz]                                     */
+    const double* wc_w;     /* [nnz] w0 - w1                             */
+    const double* wc_K;     /* [n_wc][3] (xx, xy, yy)                    */
+    int32_t n_planes;
+    const double* planes;   /* [n_planes][4] (n_x, n_y, d, k)            */
+    const double* minert;   /* [nv] or NULL                              */
+    const double* xhat;     /* [nv][2]                                   */
 } or2_problem;
 
 /* Same field layout as the 3-D oracle's options and statistics. */
@@ -184,6 +202,17 @@ int or2_prep(int32_t nv, int32_t nt, const double* X, const int32_t* tris, doubl
     return 0;
 }
 
+/* Lumped mass of Eq. (fem_be) with d = 2: m_ii = int R0 N_i dX, i.e.
+ * R0 A0_e / 3 from every incident triangle (unit thickness).  Accumulates
+ * into m[nv]. */
+void or2_lumped_mass(int32_t nv, int32_t nt, const int32_t* tris, const double* A0, double density,
+                     double* m)
+{
+    (void)nv;
+    for (int e = 0; e < nt; ++e)
+        for (int j = 0; j < 3; ++j) m[tris[3 * e + j]] += density * A0[e] / 3.0;
+}
+
 /* Lumped body force: a linear basis function integrates to A0 / 3 over a
  * triangle, so fhat_i += R0 g A0_e / 3 from every incident triangle. */
 void or2_body_force(int32_t nv, int32_t nt, const int32_t* tris, const double* A0, double density,
@@ -205,15 +234,18 @@ static void deformation_gradient(const double* y, const int32_t* t, const double
         }
 }
 
-/* vertex -> incident triangles (with local slot) */
+/* vertex -> incident triangles (with local slot); vertex -> incident weak
+ * constraints (with the position of the vertex in the constraint) */
 typedef struct {
     int32_t *tptr, *tlist, *tslot;
+    int32_t *cptr, *clist, *cpos;
     double *dN, *A0;
 } or2_adj;
 
 static void adj_free(or2_adj* A)
 {
     free(A->tptr); free(A->tlist); free(A->tslot); free(A->dN); free(A->A0);
+    free(A->cptr); free(A->clist); free(A->cpos);
     memset(A, 0, sizeof *A);
 }
 
@@ -239,17 +271,53 @@ static int adj_build(const or2_problem* p, or2_adj* A)
             A->tlist[k] = e;
             A->tslot[k] = j;
         }
+    int nnz = p->n_wc > 0 ? p->wc_ptr[p->n_wc] : 0;
+    A->cptr = (int32_t*)calloc((size_t)nv + 1, sizeof(int32_t));
+    for (int k = 0; k < nnz; ++k) {
+        int v = p->wc_vert[k];
+        if (v < 0 || v >= nv) { free(fill); adj_free(A); return -2; }
+        A->cptr[v + 1]++;
+    }
+    for (int i = 0; i < nv; ++i) A->cptr[i + 1] += A->cptr[i];
+    A->clist = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz + 1));
+    A->cpos = (int32_t*)malloc(sizeof(int32_t) * (size_t)(nnz + 1));
+    memset(fill, 0, sizeof(int32_t) * ((size_t)nv + 1));
+    for (int c = 0; c < p->n_wc; ++c)
+        for (int k = p->wc_ptr[c]; k < p->wc_ptr[c + 1]; ++k) {
+            int v = p->wc_vert[k];
+            int q = A->cptr[v] + fill[v]++;
+            A->clist[q] = c;
+            A->cpos[q] = k;
+        }
     free(fill);
     return 0;
 }
+
+/* K_c entry (a, b) from the stored (xx, xy, yy). */
+static double symK(const double* K, int a, int b) { return (a == b) ? K[2 * a] : K[1]; }
+
+/* C_c = sum_j w_j y_{v_j}, with y_i replaced by yi when yi is non-null. */
+static void constraint_value(const or2_problem* p, int c, const double* y, int i, const double* yi, double* C)
+{
+    C[0] = C[1] = 0.0;
+    for (int s = p->wc_ptr[c]; s < p->wc_ptr[c + 1]; ++s) {
+        int v = p->wc_vert[s];
+        const double* yv = (yi && v == i) ? yi : y + 2 * v;
+        C[0] += p->wc_w[s] * yv[0];
+        C[1] += p->wc_w[s] * yv[1];
+    }
+}
+
+/* phi = n . y - d of half-plane q at position y. */
+static double plane_phi(const double* pl, const double* y) { return pl[0] * y[0] + pl[1] * y[1] - pl[2]; }
 
 /* ------------------------------------------------------------------ */
 /* Node colouring, Sec. "Coloring and Parallelism"                       */
 /* ------------------------------------------------------------------ */
 /* Free vertices in ascending index each take the least colour used by no
- * already coloured vertex of an incident triangle (the union of the sets
- * S_c of those triangles).  Dirichlet vertices get -1.  Returns the number
- * of colours or < 0 on error. */
+ * already coloured vertex of an incident triangle or weak constraint (the
+ * union of the sets S_c of those elements).  Dirichlet vertices get -1.
+ * Returns the number of colours or < 0 on error. */
 int32_t or2_color(const or2_problem* p, int32_t* colors)
 {
     or2_adj A;
@@ -266,6 +334,11 @@ int32_t or2_color(const or2_problem* p, int32_t* colors)
             for (int j = 0; j < 3; ++j)
                 if (colors[t[j]] >= 0) used[colors[t[j]]] = 1;
         }
+        for (int k = A.cptr[i]; k < A.cptr[i + 1]; ++k) {
+            int c = A.clist[k];
+            for (int s = p->wc_ptr[c]; s < p->wc_ptr[c + 1]; ++s)
+                if (colors[p->wc_vert[s]] >= 0) used[colors[p->wc_vert[s]]] = 1;
+        }
         int col = 0;
         while (used[col]) ++col;
         if (col >= 255) { adj_free(&A); return -4; }
@@ -280,7 +353,8 @@ int32_t or2_color(const or2_problem* p, int32_t* colors)
 /* Local energy, local system and the update                            */
 /* ------------------------------------------------------------------ */
 /* Energy of the terms involving vertex i with y_i replaced by yi: incident
- * triangles A0 Psi(F) and -yi . fext_i; magnitudes added to *absum. */
+ * triangles A0 Psi(F), incident weak constraints, the half-plane penalties,
+ * the inertia and -yi . fext_i; magnitudes added to *absum. */
 static double local_energy(const or2_problem* p, const or2_adj* A, const double* y, int i,
                            const double* yi, double* absum)
 {
@@ -303,6 +377,30 @@ static double local_energy(const or2_problem* p, const or2_adj* A, const double*
         E += w;
         ab += fabs(w);
     }
+    for (int k = A->cptr[i]; k < A->cptr[i + 1]; ++k) {
+        int c = A->clist[k];
+        double C[2];
+        constraint_value(p, c, y, i, yi, C);
+        const double* K = p->wc_K + 3 * c;
+        double w = 0.5 * (K[0] * C[0] * C[0] + 2.0 * K[1] * C[0] * C[1] + K[2] * C[1] * C[1]);
+        E += w;
+        ab += fabs(w);
+    }
+    for (int q = 0; q < p->n_planes; ++q) {
+        const double* pl = p->planes + 4 * q;
+        double phi = plane_phi(pl, yi);
+        if (phi < 0.0) {
+            double w = 0.5 * pl[3] * phi * phi;
+            E += w;
+            ab += fabs(w);
+        }
+    }
+    if (p->minert) {
+        double d0 = yi[0] - p->xhat[2 * i], d1 = yi[1] - p->xhat[2 * i + 1];
+        double w = 0.5 * p->minert[i] * (d0 * d0 + d1 * d1);
+        E += w;
+        ab += fabs(w);
+    }
     double w = -(yi[0] * p->fext[2 * i] + yi[1] * p->fext[2 * i + 1]);
     E += w;
     ab += fabs(w);
@@ -311,7 +409,10 @@ static double local_energy(const or2_problem* p, const or2_adj* A, const double*
 }
 
 /* g_i = dE/dy_i and the modified nodal Hessian of Eq. (mod_hess), the
- * density of Eq. (mod_hess_dens) contracted with dN_i dN_i^T. */
+ * density of Eq. (mod_hess_dens) contracted with dN_i dN_i^T, plus the
+ * exact second derivatives of the other terms: s_ci^2 K_c for a weak
+ * constraint in which vertex i has weight s_ci, k n n^T for an active
+ * half-plane, minert_i I for the inertia. */
 static void local_system(const or2_problem* p, const or2_adj* A, const double* y, int i, double* gi,
                          double* Ai)
 {
@@ -337,6 +438,31 @@ static void local_system(const or2_problem* p, const or2_adj* A, const double* y
                 Ai[2 * al + be] += V * s;
             }
     }
+    for (int k = A->cptr[i]; k < A->cptr[i + 1]; ++k) {
+        int c = A->clist[k];
+        double sci = p->wc_w[A->cpos[k]], C[2];
+        constraint_value(p, c, y, i, NULL, C);
+        const double* K = p->wc_K + 3 * c;
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                gi[a] += sci * symK(K, a, b) * C[b];
+                Ai[2 * a + b] += sci * sci * symK(K, a, b);
+            }
+    }
+    for (int q = 0; q < p->n_planes; ++q) {
+        const double* pl = p->planes + 4 * q;
+        double phi = plane_phi(pl, y + 2 * i);
+        if (phi < 0.0)
+            for (int a = 0; a < 2; ++a) {
+                gi[a] += pl[3] * phi * pl[a];
+                for (int b = 0; b < 2; ++b) Ai[2 * a + b] += pl[3] * pl[a] * pl[b];
+            }
+    }
+    if (p->minert)
+        for (int a = 0; a < 2; ++a) {
+            gi[a] += p->minert[i] * (y[2 * i + a] - p->xhat[2 * i + a]);
+            Ai[2 * a + a] += p->minert[i];
+        }
 }
 
 static double to_f32(double v) { return (double)(float)v; }
@@ -380,9 +506,11 @@ static int update_vertex(const or2_problem* p, const or2_adj* A, double* y, int 
     return halvings;
 }
 
-/* r_i = f_i(y) + fhat_i over free vertices (Eq. fem_qs) by scattering the
- * element forces -A0 P dN_j; total energy sum A0 Psi - y . fhat.  Returns
- * ||r||_2, or -1 on a mesh error. */
+/* r_i = f_i(y) + fhat_i over free vertices (Eq. fem_qs, with the inertia
+ * the force of the incremental potential) by scattering the element forces
+ * -A0 P dN_j, the constraint forces -w_j K_c C_c, the half-plane forces
+ * -k phi n and -minert_i (y_i - xhat_i); total energy of every term.
+ * Returns ||r||_2, or -1 on a mesh error. */
 double or2_residual(const or2_problem* p, const double* y, double* r_out /* nullable [nv][2] */,
                     double* energy_out)
 {
@@ -399,6 +527,31 @@ double or2_residual(const or2_problem* p, const double* y, double* r_out /* null
         E += A.A0[e] * or2_psi(p->model, p->mu[e], p->lam[e], F);
         for (int j = 0; j < 3; ++j)
             for (int r = 0; r < 2; ++r) f[2 * t[j] + r] -= A.A0[e] * (P[2 * r] * g[2 * j] + P[2 * r + 1] * g[2 * j + 1]);
+    }
+    for (int c = 0; c < p->n_wc; ++c) {
+        double C[2];
+        constraint_value(p, c, y, -1, NULL, C);
+        const double* K = p->wc_K + 3 * c;
+        double KC[2] = {K[0] * C[0] + K[1] * C[1], K[1] * C[0] + K[2] * C[1]};
+        E += 0.5 * (C[0] * KC[0] + C[1] * KC[1]);
+        for (int s = p->wc_ptr[c]; s < p->wc_ptr[c + 1]; ++s)
+            for (int a = 0; a < 2; ++a) f[2 * p->wc_vert[s] + a] -= p->wc_w[s] * KC[a];
+    }
+    for (int i = 0; i < p->nv; ++i) {
+        for (int q = 0; q < p->n_planes; ++q) {
+            const double* pl = p->planes + 4 * q;
+            double phi = plane_phi(pl, y + 2 * i);
+            if (phi < 0.0) {
+                E += 0.5 * pl[3] * phi * phi;
+                for (int a = 0; a < 2; ++a) f[2 * i + a] -= pl[3] * phi * pl[a];
+            }
+        }
+        if (p->minert) {
+            double d0 = y[2 * i] - p->xhat[2 * i], d1 = y[2 * i + 1] - p->xhat[2 * i + 1];
+            E += 0.5 * p->minert[i] * (d0 * d0 + d1 * d1);
+            f[2 * i] -= p->minert[i] * d0;
+            f[2 * i + 1] -= p->minert[i] * d1;
+        }
     }
     double n2 = 0.0;
     for (int i = 0; i < p->nv; ++i) {

@@ -24,7 +24,9 @@ _up = C.POINTER(C.c_uint8)
 
 class _Problem2(C.Structure):
     _fields_ = [("nv", C.c_int32), ("nt", C.c_int32), ("model", C.c_int32), ("X", _dp),
-                ("tris", _ip), ("mu", _dp), ("lam", _dp), ("fext", _dp), ("is_dir", _up)]
+                ("tris", _ip), ("mu", _dp), ("lam", _dp), ("fext", _dp), ("is_dir", _up),
+                ("n_wc", C.c_int32), ("wc_ptr", _ip), ("wc_vert", _ip), ("wc_w", _dp), ("wc_K", _dp),
+                ("n_planes", C.c_int32), ("planes", _dp), ("minert", _dp), ("xhat", _dp)]
 
 
 _ready = False
@@ -42,6 +44,7 @@ def lib():
         L.or2_prep.argtypes = [C.c_int32, C.c_int32, _dp, _ip, _dp, _dp]
         L.or2_prep.restype = C.c_int
         L.or2_body_force.argtypes = [C.c_int32, C.c_int32, _ip, _dp, C.c_double, _dp, _dp]
+        L.or2_lumped_mass.argtypes = [C.c_int32, C.c_int32, _ip, _dp, C.c_double, _dp]
         L.or2_color.argtypes = [C.POINTER(_Problem2), _ip]
         L.or2_color.restype = C.c_int32
         L.or2_residual.argtypes = [C.POINTER(_Problem2), _dp, _dp, _dp]
@@ -94,6 +97,25 @@ class PlanarProblem:
     dN: np.ndarray
     dirichlet_idx: np.ndarray
     dirichlet_x: np.ndarray
+    wc_ptr: np.ndarray = None
+    wc_vert: np.ndarray = None
+    wc_w: np.ndarray = None
+    wc_K: np.ndarray = None          # [n_wc, 3] (xx, xy, yy)
+    planes: np.ndarray = None        # [n_planes, 4] (nx, ny, d, k)
+    mass: np.ndarray = None          # lumped m_ii = R0 sum A0 / 3 (Eq. fem_be, d = 2)
+    minert: np.ndarray = None        # m_ii / dt^2 on free vertices, or None
+    xhat: np.ndarray = None          # 2 x^n - x^{n-1}
+
+    def set_inertia(self, dt, x_n=None, x_prev=None):
+        """Backward-Euler inertia with time step dt and xhat = 2 x^n - x^{n-1};
+        dt <= 0 removes it."""
+        if dt is None or dt <= 0:
+            self.minert = self.xhat = None
+            return
+        m = self.mass / (dt * dt)
+        m[self.is_dir != 0] = 0.0
+        self.minert = np.ascontiguousarray(m)
+        self.xhat = np.ascontiguousarray(2.0 * _f64(x_n, (-1, 2)) - _f64(x_prev, (-1, 2)))
 
     def struct(self) -> _Problem2:
         s = _Problem2()
@@ -101,6 +123,13 @@ class PlanarProblem:
         s.X, s.tris, s.mu, s.lam, s.fext = (_d(self.X), _i(self.tris), _d(self.mu), _d(self.lam),
                                             _d(self.fext))
         s.is_dir = self.is_dir.ctypes.data_as(_up)
+        s.n_wc = self.wc_ptr.size - 1
+        s.wc_ptr, s.wc_vert, s.wc_w, s.wc_K = (_i(self.wc_ptr), _i(self.wc_vert), _d(self.wc_w),
+                                                _d(self.wc_K))
+        s.n_planes = self.planes.shape[0]
+        s.planes = _d(self.planes)
+        if self.minert is not None:
+            s.minert, s.xhat = _d(self.minert), _d(self.xhat)
         return s
 
 
@@ -130,10 +159,19 @@ def make_problem(sc, mu=None, lam=None) -> PlanarProblem:
         fext += np.asarray(sc.nodal_force, np.float64).reshape(nv, 2)
     is_dir = np.zeros(nv, np.uint8)
     is_dir[np.asarray(sc.dirichlet_idx, np.int64)] = 1
+    mass = np.zeros(nv)
+    if nt > 0:
+        L.or2_lumped_mass(nv, nt, _i(T), _d(A0), float(sc.density), _d(mass))
     return PlanarProblem(nv=nv, nt=nt, model=MODEL[sc.model], X=X, tris=T, mu=mu, lam=lam,
                          fext=np.ascontiguousarray(fext), is_dir=is_dir, A0=A0[:nt], dN=dN[:nt],
                          dirichlet_idx=np.asarray(sc.dirichlet_idx, np.int32),
-                         dirichlet_x=np.asarray(sc.dirichlet_x, np.float64))
+                         dirichlet_x=np.asarray(sc.dirichlet_x, np.float64),
+                         wc_ptr=np.ascontiguousarray(sc.wc_ptr, np.int32),
+                         wc_vert=np.ascontiguousarray(sc.wc_vert, np.int32),
+                         wc_w=np.ascontiguousarray(sc.wc_w, np.float64),
+                         wc_K=np.ascontiguousarray(np.asarray(sc.wc_K, np.float64).reshape(-1, 3)),
+                         planes=np.ascontiguousarray(np.asarray(sc.planes, np.float64).reshape(-1, 4)),
+                         mass=mass)
 
 
 def color(op: PlanarProblem):

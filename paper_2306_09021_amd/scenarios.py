@@ -550,7 +550,7 @@ def square_mesh(nx: int, ny: int, h=1.0, diagonal: str = "uniform"):
 
 @dataclass
 class Scenario2D:
-    """One planar quasistatic problem (inputs only); positions are [n, 2]."""
+    """One planar problem (inputs only); positions are [n, 2]."""
     name: str
     rest_pos: np.ndarray                       # float64 [n, 2]
     tris: np.ndarray                           # int32 [m, 3], counter-clockwise
@@ -563,6 +563,11 @@ class Scenario2D:
     density: float = 0.0
     gravity: tuple = (0.0, 0.0)
     nodal_force: Optional[np.ndarray] = None   # float64 [n, 2]
+    wc_ptr: np.ndarray = field(default_factory=lambda: np.zeros(1, np.int32))
+    wc_vert: np.ndarray = field(default_factory=lambda: np.zeros(0, np.int32))
+    wc_w: np.ndarray = field(default_factory=lambda: np.zeros(0, np.float64))
+    wc_K: np.ndarray = field(default_factory=lambda: np.zeros((0, 3), np.float64))   # (xx, xy, yy)
+    planes: np.ndarray = field(default_factory=lambda: np.zeros((0, 4), np.float64))  # (nx, ny, d, k)
 
     @property
     def n_verts(self) -> int:
