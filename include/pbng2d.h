@@ -12,13 +12,15 @@
  * / (pbgn_dx) solves a 2x2 SPD system.  The planar experiment of Sec.
  * "PBNG vs. PBD and Limited Newton" is of this kind.
  *
+ * Weak constraints (Sec. "Weak Constraints"), contact half-planes and the
+ * backward-Euler inertia of Eq. (fem_be) enter as in pbng.h with d = 2.
+ *
  * Conventions are those of pbng.h (status codes, pbng_last_error(), host
  * and device pointers, ownership, streams), with positions as row-major
  * [n][2] arrays in the caller's vertex order.  One problem per workspace.
  * Not supported in the planar family: the stable Neo-Hookean model (its
  * printed rest-state constant 3 mu / (4 lambda) makes F = I stress free
- * only for d = 3), weak constraints, contact planes, inertia and the
- * adjoint.
+ * only for d = 3), contact detection with recolouring, and the adjoint.
  */
 #ifndef PBNG2D_H
 #define PBNG2D_H
@@ -46,6 +48,18 @@ extern "C" {
  *  nodal_force [n_verts][2]  optional extra lumped load (may be NULL)
  *  n_dirichlet, dirichlet_idx [n_dirichlet], dirichlet_x [n_dirichlet][2]
  *                        prescribed vertices (distinct) and their targets
+ *  n_wc, wc_ptr [n_wc+1], wc_vert [nnz], wc_w [nnz], wc_K [n_wc][3]
+ *                        weak constraints: C_c = sum_j wc_w[j] y_{wc_vert[j]}
+ *                        over j in [wc_ptr[c], wc_ptr[c+1]) (wc_ptr[0] = 0,
+ *                        non-decreasing, distinct vertices per constraint),
+ *                        energy 1/2 C_c^T K_c C_c with K_c symmetric stored
+ *                        as (xx, xy, yy); arrays may be NULL when n_wc == 0
+ *  n_planes, planes [n_planes][4]
+ *                        contact half-planes (n_x, n_y, d, k), k >= 0: every
+ *                        vertex with phi = n . y - d < 0 carries the penalty
+ *                        1/2 k phi^2
+ * Fields after dirichlet_x were added with the constraints; zero them
+ * (n_wc = n_planes = 0) for a purely elastic problem.
  */
 typedef struct pbng2d_problem {
     int32_t n_verts;
@@ -63,6 +77,13 @@ typedef struct pbng2d_problem {
     int32_t n_dirichlet;
     const int32_t* dirichlet_idx;
     const double* dirichlet_x;
+    int32_t n_wc;
+    const int32_t* wc_ptr;
+    const int32_t* wc_vert;
+    const double* wc_w;
+    const double* wc_K;
+    int32_t n_planes;
+    const double* planes;
 } pbng2d_problem;
 
 typedef struct pbng2d_workspace pbng2d_workspace;
@@ -70,8 +91,8 @@ typedef struct pbng2d_workspace pbng2d_workspace;
 /*
  * Node colouring (Sec. "Coloring and Parallelism"), host only: free
  * vertices in ascending index each take the least colour used by no
- * already coloured vertex of an incident triangle; Dirichlet vertices get
- * -1.  colors_out [n_verts]; *n_colors_out the number of colours.
+ * already coloured vertex of an incident triangle or weak constraint;
+ * Dirichlet vertices get -1.  colors_out [n_verts]; *n_colors_out the number of colours.
  * Errors: PBNG_EINVAL, PBNG_EMESH, PBNG_ECOLOR (more than 64 colours),
  * PBNG_EUNSUPPORTED (n_tris above INT32_MAX / 3, checked before tris is
  * read).
@@ -107,10 +128,12 @@ int32_t pbng2d_workspace_colors(const pbng2d_workspace* ws, int32_t* colors_out)
  * vertex) of o; sweeps_per_graph and resume are ignored.  The backtracking
  * safeguard is exact for the Neo-Hookean model (its local energy is a
  * quadratic along the step, |F|^2 being quadratic and det F affine in
- * x_i); for the corotated model the full step never increases the local
- * energy (mu |F' - R(F')|^2 <= mu |F' - R(F)|^2 majorises it by the
- * quadratic whose Hessian is the modified matrix A_i), so no halving is
- * ever taken there.  stats (host, one entry) may be NULL.  Returns PBNG_OK,
+ * x_i, and so are the weak constraints and the inertia; half-plane
+ * penalties are evaluated exactly); for the corotated model the full step
+ * never increases the local energy (mu |F' - R(F')|^2 <= mu |F' - R(F)|^2
+ * majorises it by the quadratic whose Hessian is the modified matrix A_i)
+ * unless it enters a half-plane, so halvings are only ever tested, on the
+ * exact energy, when that bound fails.  stats (host, one entry) may be NULL.  Returns PBNG_OK,
  * PBNG_NOT_CONVERGED (outputs valid), PBNG_ENAN or another error.
  */
 int32_t pbng2d_solve(pbng2d_workspace* ws, void* x_inout, const pbng_solve_opts* o,
@@ -118,12 +141,27 @@ int32_t pbng2d_solve(pbng2d_workspace* ws, void* x_inout, const pbng_solve_opts*
 
 /*
  * FP64 residual and energy (Eq. fem_qs): *res_norm = ||f(x) + fhat||_2
- * over free vertices, *energy = sum A0 Psi(F) - x . fhat (either may be
- * NULL); r_out: optional device double [n_verts][2] (zero on Dirichlet
+ * over free vertices, *energy = sum A0 Psi(F) - x . fhat plus the weak
+ * constraint, half-plane and inertia terms (either may be NULL); r_out: optional device double [n_verts][2] (zero on Dirichlet
  * rows).  x: device [n_verts][2] of the workspace's real type.
  */
 int32_t pbng2d_residual(pbng2d_workspace* ws, const void* x, double* res_norm, double* energy,
                         double* r_out, void* hip_stream);
+
+/*
+ * Backward-Euler inertia (Eq. fem_be, minimised as the incremental
+ * potential) with d = 2: with dt > 0 every later solve and residual adds
+ * sum over free vertices i of 1/2 m_ii / dt^2 |y_i - xhat_i|^2 to the
+ * energy, xhat = 2 x^n - x^{n-1}, lumped mass m_ii = R0 sum_{e incident to
+ * i} A0_e / 3 (R0 = the problem's density, unit thickness).  x_n_dev,
+ * x_prev_dev: device double arrays [n_verts][2] in the caller's order
+ * (Dirichlet rows ignored), read on hip_stream before the call returns;
+ * the workspace keeps its own xhat.  dt <= 0 switches inertia off (the
+ * pointers may then be NULL).  Errors: PBNG_EINVAL (null arrays with
+ * dt > 0, non-finite dt), PBNG_EHIP.
+ */
+int32_t pbng2d_workspace_set_inertia(pbng2d_workspace* ws, double dt, const double* x_n_dev,
+                                     const double* x_prev_dev, void* hip_stream);
 
 /*
  * Launch-level access for measurement, as in pbng.h: load the internal

@@ -53,10 +53,23 @@ struct Sweep2Args {
     int* rejected;          // [1]
     R omega, gamma;
     int max_halvings;
+    // weak constraints, contact half-planes and inertia (EXTRA kernels)
+    const int* wvptr;       // [n_free + 1] constraints of each free vertex
+    const int* wv_c;        // constraint index
+    const R* wv_s;          // weight of the vertex in that constraint
+    const int* wc_ptr;      // [n_wc + 1]
+    const int* wc_vert;     // internal vertex indices
+    const R* wc_w;
+    const R* wc_K;          // [n_wc][3] (xx, xy, yy)
+    const R* planes;        // [n_planes][4] (n_x, n_y, d, k)
+    int n_planes;
+    const R* inert;         // [n_free] m_ii / dt^2, or null
+    const R2* xhat;         // [n_free] 2 x^n - x^{n-1}
 };
 
-// FP64 residual / energy: per triangle V0 P dN_j (vp) and V0 Psi, per
-// vertex the force balance and -x . fhat.
+// FP64 residual / energy: per triangle A0 P dN_j (vp) and A0 Psi, per
+// vertex the force balance, -x . fhat, the half-plane penalties and the
+// inertia, per weak constraint its energy.
 template <class R>
 struct Res2Args {
     using R2 = typename R2t<R>::T;
@@ -64,25 +77,45 @@ struct Res2Args {
     const int4* tri;        // [n_tris] internal vertex indices (w unused)
     const TriGeo* geo;
     double* vp;             // [n_tris][3][2]
-    double* ebuf;           // [n_tris + n_verts] energy summands
+    double* ebuf;           // [n_tris + n_verts + n_wc] energy summands
     const int* rvptr;       // [n_free + 1] visits of every free vertex
     const int* rv;          // tri * 3 + slot
     const double* fext64;   // [n_verts][2] internal order
     const int* orig_of;     // [n_verts]
     double* rsq;            // [n_verts] squared residual per vertex
     int n_free, n_verts, n_tris, model;
+    // weak constraints (ebuf[n_tris + n_verts + c] takes 1/2 C^T K C),
+    // half-planes (every vertex) and inertia (free vertices, or null)
+    const int* wvptr;       // [n_free + 1]
+    const int* wv_c;
+    const double* wv_s;
+    const int* wc_ptr;      // [n_wc + 1]
+    const int* wc_vert;     // internal
+    const double* wc_w;
+    const double* wc_K;     // [n_wc][3]
+    int n_wc;
+    const double* planes;   // [n_planes][4]
+    int n_planes;
+    const double* inert;    // [n_free] m_ii / dt^2, or null
+    const double* xhat;     // [n_free][2]
 };
 
-// uniform: the 24-byte record form (a.vw null, a.mu_u / a.lam_u set)
+// uniform: the 24-byte record form (a.vw null, a.mu_u / a.lam_u set);
+// extra: weak constraints, half-planes or inertia present
 template <class R>
 hipError_t launch_phase2(const Sweep2Args<R>& a, int model, int lanes, bool accel, bool safe, bool uniform,
-                         int vbeg, int vend, hipStream_t s);
+                         bool extra, int vbeg, int vend, hipStream_t s);
 template <class R>
 hipError_t launch_residual2(const Res2Args<R>& a, double* r_out, hipStream_t s);
 template <class R>
 hipError_t launch_load2(const R* x_user, const int* orig_of, const typename R2t<R>::T* xd_int,
                         typename R2t<R>::T* d0, typename R2t<R>::T* d1, typename R2t<R>::T* d2, int n_free,
                         int n_verts, hipStream_t s);
+// xhat = 2 x^n - x^{n-1} of the free vertices (internal order) from caller
+// order FP64 arrays, in FP64 and in the sweep precision
+template <class R>
+hipError_t launch_xhat2(const double* x_n, const double* x_prev, const int* orig_of, double* xhat64,
+                        typename R2t<R>::T* xhat, int n_free, hipStream_t s);
 template <class R>
 hipError_t launch_store2(const typename R2t<R>::T* src, const int* orig_of, R* x_user, int n_verts,
                          hipStream_t s);

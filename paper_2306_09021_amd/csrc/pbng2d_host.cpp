@@ -37,6 +37,14 @@ struct pbng2d_workspace {
     double* hbuf = nullptr;         // pinned [2]
     int64_t sweep_l = 0;
     double omega_l = 1.0;
+    // weak constraints (internal vertex indices; per free vertex CSR),
+    // half-planes and inertia
+    int n_wc = 0, n_planes = 0;
+    bool inertia = false;
+    std::vector<double> mass_h;     // lumped m_ii, internal order
+    Dev wvptr, wv_c, wv_s, wv_s64, wc_ptr, wc_vert, wc_w, wc_w64, wc_K, wc_K64, planes, planes64;
+    Dev inert, inert64, xhat, xhat64;
+    bool extra() const { return n_wc > 0 || n_planes > 0 || inertia; }
 
     size_t r2() const { return real == PBNG_F64 ? 2 * sizeof(double) : 2 * sizeof(float); }
     ~pbng2d_workspace()
@@ -111,10 +119,34 @@ void validate2(const pbng2d_problem* p)
     }
     if (p->n_dirichlet > 0 && !finite_all(p->dirichlet_x, 2 * int64_t(p->n_dirichlet)))
         fail(PBNG_ENAN, "non-finite Dirichlet target");
+    if (p->n_wc < 0) fail(PBNG_EINVAL, "bad n_wc");
+    if (p->n_wc > 0) {
+        if (!p->wc_ptr || !p->wc_vert || !p->wc_w || !p->wc_K) fail(PBNG_EINVAL, "weak-constraint arrays are null");
+        if (p->wc_ptr[0] != 0) fail(PBNG_EINVAL, "wc_ptr[0] must be 0");
+        for (int c = 0; c < p->n_wc; ++c)
+            if (p->wc_ptr[c + 1] < p->wc_ptr[c]) fail(PBNG_EINVAL, "wc_ptr not monotone");
+        const int nnz = p->wc_ptr[p->n_wc];
+        for (int k = 0; k < nnz; ++k)
+            if (p->wc_vert[k] < 0 || p->wc_vert[k] >= p->n_verts) fail(PBNG_EMESH, "weak-constraint vertex out of range");
+        for (int c = 0; c < p->n_wc; ++c)
+            for (int k = p->wc_ptr[c]; k < p->wc_ptr[c + 1]; ++k)
+                for (int j = p->wc_ptr[c]; j < k; ++j)
+                    if (p->wc_vert[j] == p->wc_vert[k]) fail(PBNG_EMESH, "weak constraint %d repeats a vertex", c);
+        if (!finite_all(p->wc_w, nnz) || !finite_all(p->wc_K, 3 * int64_t(p->n_wc)))
+            fail(PBNG_ENAN, "non-finite weak constraint");
+    }
+    if (p->n_planes < 0) fail(PBNG_EINVAL, "bad n_planes");
+    if (p->n_planes > 0) {
+        if (!p->planes) fail(PBNG_EINVAL, "planes is null");
+        if (!finite_all(p->planes, 4 * int64_t(p->n_planes))) fail(PBNG_ENAN, "non-finite half-plane");
+        for (int q = 0; q < p->n_planes; ++q)
+            if (p->planes[4 * q + 3] < 0.0) fail(PBNG_EINVAL, "half-plane stiffness < 0");
+    }
 }
 
 struct Inc {
     std::vector<int> ptr, tri, slot;
+    std::vector<int> cptr, clist, cpos;   // vertex -> weak constraints
 };
 
 Inc incidence2(const pbng2d_problem* p)
@@ -133,6 +165,20 @@ Inc incidence2(const pbng2d_problem* p)
             const int k = I.ptr[v] + fill[v]++;
             I.tri[k] = e;
             I.slot[k] = j;
+        }
+    const int nnz = p->n_wc > 0 ? p->wc_ptr[p->n_wc] : 0;
+    I.cptr.assign(p->n_verts + 1, 0);
+    for (int k = 0; k < nnz; ++k) I.cptr[p->wc_vert[k] + 1]++;
+    for (int i = 0; i < p->n_verts; ++i) I.cptr[i + 1] += I.cptr[i];
+    I.clist.resize(nnz);
+    I.cpos.resize(nnz);
+    std::vector<int> f2(I.cptr.begin(), I.cptr.end() - 1);
+    for (int c = 0; c < p->n_wc; ++c)
+        for (int k = p->wc_ptr[c]; k < p->wc_ptr[c + 1]; ++k) {
+            const int v = p->wc_vert[k];
+            I.clist[f2[v]] = c;
+            I.cpos[f2[v]] = k;
+            f2[v]++;
         }
     return I;
 }
@@ -156,6 +202,11 @@ int color2(const pbng2d_problem* p, const Inc& I, int32_t* colors)
             const int32_t* t = p->tris + 3 * I.tri[k];
             for (int j = 0; j < 3; ++j)
                 if (colors[t[j]] >= 0) used |= uint64_t(1) << colors[t[j]];
+        }
+        for (int k = I.cptr[i]; k < I.cptr[i + 1]; ++k) {
+            const int c = I.clist[k];
+            for (int m = p->wc_ptr[c]; m < p->wc_ptr[c + 1]; ++m)
+                if (colors[p->wc_vert[m]] >= 0) used |= uint64_t(1) << colors[p->wc_vert[m]];
         }
         if (used == ~uint64_t(0)) fail(PBNG_ECOLOR, "more than 64 colours needed");
         int c = 0;
@@ -182,6 +233,12 @@ int check_colors2(const pbng2d_problem* p, const int32_t* colors)
                 if (colors[t[a]] >= 0 && colors[t[a]] == colors[t[b]])
                     fail(PBNG_ECOLOR, "triangle %d: two vertices share colour %d", e, colors[t[a]]);
     }
+    for (int c = 0; c < p->n_wc; ++c)
+        for (int k = p->wc_ptr[c]; k < p->wc_ptr[c + 1]; ++k)
+            for (int j = p->wc_ptr[c]; j < k; ++j) {
+                const int ca = colors[p->wc_vert[j]], cb = colors[p->wc_vert[k]];
+                if (ca >= 0 && ca == cb) fail(PBNG_ECOLOR, "weak constraint %d: two vertices share colour %d", c, ca);
+            }
     return ncol;
 }
 
@@ -280,6 +337,54 @@ void pack(pbng2d_workspace* ws, const pbng2d_problem* p, const Inc& I, const std
             xd[v - nf] = R2{R(p->dirichlet_x[2 * k]), R(p->dirichlet_x[2 * k + 1])};
         }
     }
+    // weak constraints in internal indices, the per-free-vertex CSR of
+    // (constraint, weight), half-planes and the lumped masses
+    ws->n_wc = p->n_wc;
+    ws->n_planes = p->n_planes;
+    {
+        const int nnz = p->n_wc > 0 ? p->wc_ptr[p->n_wc] : 0;
+        std::vector<int> wcp(p->n_wc + 1, 0), wcv(std::max(1, nnz)), wvp(nf + 1, 0), wvc;
+        std::vector<double> wcw(std::max(1, nnz)), wck(std::max<int64_t>(1, 3 * int64_t(p->n_wc))), wvs;
+        if (p->n_wc > 0) std::copy(p->wc_ptr, p->wc_ptr + p->n_wc + 1, wcp.begin());
+        for (int k = 0; k < nnz; ++k) {
+            wcv[k] = int_of[p->wc_vert[k]];
+            wcw[k] = p->wc_w[k];
+        }
+        for (int64_t k = 0; k < 3 * int64_t(p->n_wc); ++k) wck[k] = p->wc_K[k];
+        for (int64_t v = 0; v < nf; ++v) {
+            const int o = ws->orig_h[v];
+            for (int m = I.cptr[o]; m < I.cptr[o + 1]; ++m) {
+                wvc.push_back(I.clist[m]);
+                wvs.push_back(p->wc_w[I.cpos[m]]);
+            }
+            wvp[v + 1] = int(wvc.size());
+        }
+        if (wvc.empty()) {
+            wvc.push_back(0);
+            wvs.push_back(0.0);
+        }
+        std::vector<double> pl(std::max<int64_t>(1, 4 * int64_t(p->n_planes)), 0.0);
+        for (int64_t k = 0; k < 4 * int64_t(p->n_planes); ++k) pl[k] = p->planes[k];
+        auto conv = [](const std::vector<double>& a) { return std::vector<R>(a.begin(), a.end()); };
+        ws->wc_ptr.upload(wcp);
+        ws->wc_vert.upload(wcv);
+        ws->wc_w.upload(conv(wcw));
+        ws->wc_w64.upload(wcw);
+        ws->wc_K.upload(conv(wck));
+        ws->wc_K64.upload(wck);
+        ws->wvptr.upload(wvp);
+        ws->wv_c.upload(wvc);
+        ws->wv_s.upload(conv(wvs));
+        ws->wv_s64.upload(wvs);
+        ws->planes.upload(conv(pl));
+        ws->planes64.upload(pl);
+        // lumped mass of Eq. (fem_be) with d = 2: R0 A0 / 3 per incident triangle
+        ws->mass_h.assign(nv, 0.0);
+        for (int64_t e = 0; e < nt; ++e) {
+            const int ids[3] = {tri[e].x, tri[e].y, tri[e].z};
+            for (int j = 0; j < 3; ++j) ws->mass_h[ids[j]] += p->density * geo[e].A0 / 3.0;
+        }
+    }
     ws->vptr.upload(vptr);
     ws->jk.upload(jk);
     ws->gm.upload(gm);
@@ -372,11 +477,11 @@ void build2(pbng2d_workspace* ws, const pbng2d_problem* p, const int32_t* colors
     ws->Wres.alloc(ws->nv * ws->r2());
     ws->rejected.alloc(sizeof(int));
     ws->vp.alloc(6 * ws->nt * sizeof(double));
-    ws->ebuf.alloc((ws->nt + ws->nv) * sizeof(double));
+    ws->ebuf.alloc((ws->nt + ws->nv + ws->n_wc) * sizeof(double));
     ws->rsq.alloc(ws->nv * sizeof(double));
     ws->out.alloc(2 * sizeof(double));
     ws->plan_r = plan_range(ws->nv, ws->cb_r, ws->ce_r, ws->qp_r, ws->part_r);
-    ws->plan_e = plan_range(ws->nt + ws->nv, ws->cb_e, ws->ce_e, ws->qp_e, ws->part_e);
+    ws->plan_e = plan_range(ws->nt + ws->nv + ws->n_wc, ws->cb_e, ws->ce_e, ws->qp_e, ws->part_e);
     hipchk(hipHostMalloc(reinterpret_cast<void**>(&ws->hbuf), 2 * sizeof(double), hipHostMallocDefault),
            "pinned alloc");
 }
@@ -399,6 +504,18 @@ void residual2(pbng2d_workspace* ws, const void* X, double* r_out, hipStream_t s
     a.n_verts = int(ws->nv);
     a.n_tris = int(ws->nt);
     a.model = ws->model;
+    a.wvptr = ws->wvptr.as<int>();
+    a.wv_c = ws->wv_c.as<int>();
+    a.wv_s = ws->wv_s64.as<double>();
+    a.wc_ptr = ws->wc_ptr.as<int>();
+    a.wc_vert = ws->wc_vert.as<int>();
+    a.wc_w = ws->wc_w64.as<double>();
+    a.wc_K = ws->wc_K64.as<double>();
+    a.n_wc = ws->n_wc;
+    a.planes = ws->planes64.as<double>();
+    a.n_planes = ws->n_planes;
+    a.inert = ws->inertia ? ws->inert64.as<double>() : nullptr;
+    a.xhat = ws->inertia ? ws->xhat64.as<double>() : nullptr;
     hipchk(launch_residual2<R>(a, r_out, s), "residual");
     double* out = ws->out.as<double>();
     hipchk(launch_segsum(ws->rsq.as<double>(), ws->plan_r, 1, out, s), "residual sum");
@@ -460,10 +577,22 @@ void sweep2(pbng2d_workspace* ws, const pbng_solve_opts* o, double omega, double
     a.omega = R(omega);
     a.gamma = R(gamma);
     a.max_halvings = o->max_halvings;
+    a.wvptr = ws->wvptr.as<int>();
+    a.wv_c = ws->wv_c.as<int>();
+    a.wv_s = ws->wv_s.as<R>();
+    a.wc_ptr = ws->wc_ptr.as<int>();
+    a.wc_vert = ws->wc_vert.as<int>();
+    a.wc_w = ws->wc_w.as<R>();
+    a.wc_K = ws->wc_K.as<R>();
+    a.planes = ws->planes.as<R>();
+    a.n_planes = ws->n_planes;
+    a.inert = ws->inertia ? ws->inert.as<R>() : nullptr;
+    a.xhat = ws->inertia ? ws->xhat.as<R2>() : nullptr;
     const int lanes = o->lanes == 0 ? 4 : o->lanes;
     const bool safe = o->safeguard == PBNG_SAFEGUARD_BACKTRACK;
     for (int c = 0; c < ws->ncol; ++c)
-        hipchk(launch_phase2<R>(a, ws->model, lanes, accel, safe, ws->uniform, ws->cptr[c], ws->cptr[c + 1], s),
+        hipchk(launch_phase2<R>(a, ws->model, lanes, accel, safe, ws->uniform, ws->extra(), ws->cptr[c],
+                                ws->cptr[c + 1], s),
                "phase launch");
     if (accel) std::swap(ws->W.p, ws->N.p);
 }
@@ -647,6 +776,46 @@ int32_t pbng2d_residual(pbng2d_workspace* ws, const void* x, double* res_norm, d
         }
         if (res_norm) *res_norm = ws->hbuf[0];
         if (energy) *energy = ws->hbuf[1];
+        return PBNG_OK;
+    });
+}
+
+int32_t pbng2d_workspace_set_inertia(pbng2d_workspace* ws, double dt, const double* x_n_dev,
+                                     const double* x_prev_dev, void* hip_stream)
+{
+    return guard([&] {
+        check_ws2(ws);
+        if (!std::isfinite(dt)) fail(PBNG_EINVAL, "non-finite dt");
+        if (dt <= 0.0) {
+            ws->inertia = false;
+            return PBNG_OK;
+        }
+        if (!x_n_dev || !x_prev_dev) fail(PBNG_EINVAL, "null x_n or x_prev");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        const int64_t nf = ws->nfree;
+        std::vector<double> c64(std::max<int64_t>(1, nf), 0.0);
+        for (int64_t v = 0; v < nf; ++v) c64[v] = ws->mass_h[v] / (dt * dt);
+        // no queued work reads the old inertia arrays after this sync
+        hipchk(hipStreamSynchronize(s), "sync");
+        ws->inert64.upload(c64);
+        if (ws->real == PBNG_F64) {
+            ws->inert.upload(c64);
+        } else {
+            std::vector<float> c32(c64.begin(), c64.end());
+            ws->inert.upload(c32);
+        }
+        if (!ws->xhat64.p) ws->xhat64.alloc(std::max<int64_t>(1, nf) * 2 * sizeof(double));
+        if (!ws->xhat.p) ws->xhat.alloc(std::max<int64_t>(1, nf) * ws->r2());
+        if (ws->real == PBNG_F64)
+            hipchk(launch_xhat2<double>(x_n_dev, x_prev_dev, ws->orig_of.as<int>(), ws->xhat64.as<double>(),
+                                        ws->xhat.as<double2>(), int(nf), s),
+                   "inertia");
+        else
+            hipchk(launch_xhat2<float>(x_n_dev, x_prev_dev, ws->orig_of.as<int>(), ws->xhat64.as<double>(),
+                                       ws->xhat.as<float2>(), int(nf), s),
+                   "inertia");
+        hipchk(hipStreamSynchronize(s), "inertia");
+        ws->inertia = true;
         return PBNG_OK;
     });
 }

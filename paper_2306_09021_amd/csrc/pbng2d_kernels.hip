@@ -40,10 +40,68 @@ __device__ __forceinline__ void rot2(R f00, R f01, R f10, R f11, R& c, R& s)
     }
 }
 
-template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool UNI>
+// One visit of vertex i at position (xix, xiy): F = (x_j - x_i) dN_j^T +
+// (x_k - x_i) dN_k^T, dN_i = -(dN_j + dN_k) and (A0 mu, A0 lambda).
+template <class R>
+struct Visit2 {
+    R f00, f01, f10, f11, ax, ay, wm, wl;
+};
+
+template <class R, bool UNI>
+__device__ __forceinline__ Visit2<R> visit2(const Sweep2Args<R>& a, int k, R xix, R xiy)
+{
+    using R2 = typename R2t<R>::T;
+    Visit2<R> r;
+    const int2 jk = at(a.jk, k);
+    const auto g = at(a.gm, k);   // dN_j = (g.x, g.y), dN_k = (g.z, g.w)
+    if constexpr (UNI) {
+        const R A0 = R(0.5) / abs_(g.x * g.w - g.y * g.z);
+        r.wm = a.mu_u * A0;
+        r.wl = a.lam_u * A0;
+    } else {
+        const R2 w = at(a.vw, k);
+        r.wm = w.x;
+        r.wl = w.y;
+    }
+    const R2 xj = at(a.W, jk.x), xk = at(a.W, jk.y);
+    const R e1x = xj.x - xix, e1y = xj.y - xiy;
+    const R e2x = xk.x - xix, e2y = xk.y - xiy;
+    r.f00 = e1x * g.x + e2x * g.z;
+    r.f01 = e1x * g.y + e2x * g.w;
+    r.f10 = e1y * g.x + e2y * g.z;
+    r.f11 = e1y * g.y + e2y * g.w;
+    r.ax = -(g.x + g.z);
+    r.ay = -(g.y + g.w);
+    return r;
+}
+
+// A0 Psi of Eq. (cor) with d = 2 for one visit.
+template <class R>
+__device__ __forceinline__ R cor_energy2(const Visit2<R>& q)
+{
+    R c, sn;
+    rot2(q.f00, q.f01, q.f10, q.f11, c, sn);
+    const R d00 = q.f00 - c, d01 = q.f01 + sn, d10 = q.f10 - sn, d11 = q.f11 - c;
+    const R J = q.f00 * q.f11 - q.f01 * q.f10;
+    return q.wm * (d00 * d00 + d01 * d01 + d10 * d10 + d11 * d11) + R(0.5) * q.wl * (J - R(1)) * (J - R(1));
+}
+
+// Penalty 1/2 k min(0, phi)^2 of half-plane q at (x, y).
+template <class R>
+__device__ __forceinline__ R plane_energy2(const Sweep2Args<R>& a, int q, R x, R y)
+{
+    const R phi = at(a.planes, 4 * q) * x + at(a.planes, 4 * q + 1) * y - at(a.planes, 4 * q + 2);
+    return phi < R(0) ? R(0.5) * at(a.planes, 4 * q + 3) * phi * phi : R(0);
+}
+
+// EXTRA: the vertex's weak constraints (spread over the lanes like its
+// visits), the half-planes and the inertia; each is an exact quadratic in
+// x_i except the half-planes, which are evaluated exactly along the step.
+template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool UNI, bool EXTRA>
 __global__ __launch_bounds__(kBlk) void k2_phase(Sweep2Args<R> a, int vbeg, int vend)
 {
     using R2 = typename R2t<R>::T;
+    constexpr bool COR_EXACT = SAFE && EXTRA && MODEL == kPlanarCor;
     const int t = xcd_block() * kBlk + int(threadIdx.x);
     const int v = vbeg + t / LANES;
     const int lane = t & (LANES - 1);
@@ -52,48 +110,61 @@ __global__ __launch_bounds__(kBlk) void k2_phase(Sweep2Args<R> a, int vbeg, int 
     const int kb = at(a.vptr, v), ke = at(a.vptr, v + 1);
     R gx = R(0), gy = R(0), s = R(0), lxx = R(0), lxy = R(0), lyy = R(0);
     R mxx = R(0), mxy = R(0), myy = R(0);
+    R E0 = R(0), E0a = R(0);
     for (int k = kb + lane; k < ke; k += LANES) {
-        const int2 jk = at(a.jk, k);
-        const auto g = at(a.gm, k);   // dN_j = (g.x, g.y), dN_k = (g.z, g.w)
-        R2 w;                         // (A0 mu, A0 lambda)
-        if constexpr (UNI) {
-            const R A0 = R(0.5) / abs_(g.x * g.w - g.y * g.z);
-            w.x = a.mu_u * A0;
-            w.y = a.lam_u * A0;
-        } else {
-            w = at(a.vw, k);
-        }
-        const R2 xj = at(a.W, jk.x), xk = at(a.W, jk.y);
-        const R e1x = xj.x - xi.x, e1y = xj.y - xi.y;
-        const R e2x = xk.x - xi.x, e2y = xk.y - xi.y;
-        const R f00 = e1x * g.x + e2x * g.z, f01 = e1x * g.y + e2x * g.w;
-        const R f10 = e1y * g.x + e2y * g.z, f11 = e1y * g.y + e2y * g.w;
-        const R ax = -(g.x + g.z), ay = -(g.y + g.w);  // dN_i
-        const R J = f00 * f11 - f01 * f10;
+        const Visit2<R> q = visit2<R, UNI>(a, k, xi.x, xi.y);
+        const R J = q.f00 * q.f11 - q.f01 * q.f10;
         // c = cof(F) dN_i with cof(F) = [[f11, -f10], [-f01, f00]]
-        const R cx = f11 * ax - f10 * ay, cy = f00 * ay - f01 * ax;
-        const R fax = f00 * ax + f01 * ay, fay = f10 * ax + f11 * ay;
-        s += w.x * (ax * ax + ay * ay);
-        lxx += w.y * cx * cx;
-        lxy += w.y * cx * cy;
-        lyy += w.y * cy * cy;
+        const R cx = q.f11 * q.ax - q.f10 * q.ay, cy = q.f00 * q.ay - q.f01 * q.ax;
+        const R fax = q.f00 * q.ax + q.f01 * q.ay, fay = q.f10 * q.ax + q.f11 * q.ay;
+        s += q.wm * (q.ax * q.ax + q.ay * q.ay);
+        lxx += q.wl * cx * cx;
+        lxy += q.wl * cx * cy;
+        lyy += q.wl * cy * cy;
         if constexpr (MODEL == kPlanarNeo) {
             // A0 lhat (J - 1 - mu / lhat) = A0 lhat (J - 1) - A0 mu
-            const R q = (w.x + w.y) * (J - R(1)) - w.x;
-            gx += w.x * fax + q * cx;
-            gy += w.x * fay + q * cy;
+            const R qq = (q.wm + q.wl) * (J - R(1)) - q.wm;
+            gx += q.wm * fax + qq * cx;
+            gy += q.wm * fay + qq * cy;
             if (SAFE) {
-                mxx += w.x * cx * cx;
-                mxy += w.x * cx * cy;
-                myy += w.x * cy * cy;
+                mxx += q.wm * cx * cx;
+                mxy += q.wm * cx * cy;
+                myy += q.wm * cy * cy;
             }
         } else {
             R c, sn;
-            rot2(f00, f01, f10, f11, c, sn);
-            const R rax = c * ax - sn * ay, ray = sn * ax + c * ay;  // R dN_i
-            const R q = w.y * (J - R(1));
-            gx += R(2) * w.x * (fax - rax) + q * cx;
-            gy += R(2) * w.x * (fay - ray) + q * cy;
+            rot2(q.f00, q.f01, q.f10, q.f11, c, sn);
+            const R rax = c * q.ax - sn * q.ay, ray = sn * q.ax + c * q.ay;  // R dN_i
+            const R qq = q.wl * (J - R(1));
+            gx += R(2) * q.wm * (fax - rax) + qq * cx;
+            gy += R(2) * q.wm * (fay - ray) + qq * cy;
+            if constexpr (COR_EXACT) {
+                const R e = cor_energy2(q);
+                E0 += e;
+                E0a += abs_(e);
+            }
+        }
+    }
+    // exact quadratic terms other than the elastic ones: gradient (qgx, qgy)
+    // and Hessian (kxx, kxy, kyy)
+    R qgx = R(0), qgy = R(0), kxx = R(0), kxy = R(0), kyy = R(0);
+    if constexpr (EXTRA) {
+        for (int k = at(a.wvptr, v) + lane; k < at(a.wvptr, v + 1); k += LANES) {
+            const int c = at(a.wv_c, k);
+            const R sc = at(a.wv_s, k);
+            R Cx = R(0), Cy = R(0);
+            for (int j = at(a.wc_ptr, c); j < at(a.wc_ptr, c + 1); ++j) {
+                const R w = at(a.wc_w, j);
+                const R2 p = at(a.W, at(a.wc_vert, j));
+                Cx += w * p.x;
+                Cy += w * p.y;
+            }
+            const R K0 = at(a.wc_K, 3 * c), K1 = at(a.wc_K, 3 * c + 1), K2 = at(a.wc_K, 3 * c + 2);
+            qgx += sc * (K0 * Cx + K1 * Cy);
+            qgy += sc * (K1 * Cx + K2 * Cy);
+            kxx += sc * sc * K0;
+            kxy += sc * sc * K1;
+            kyy += sc * sc * K2;
         }
     }
     if (LANES > 1) {
@@ -108,35 +179,131 @@ __global__ __launch_bounds__(kBlk) void k2_phase(Sweep2Args<R> a, int vbeg, int 
             mxy = lsum<LANES>(mxy);
             myy = lsum<LANES>(myy);
         }
+        if (EXTRA) {
+            qgx = lsum<LANES>(qgx);
+            qgy = lsum<LANES>(qgy);
+            kxx = lsum<LANES>(kxx);
+            kxy = lsum<LANES>(kxy);
+            kyy = lsum<LANES>(kyy);
+        }
+        if (COR_EXACT) {
+            E0 = lsum<LANES>(E0);
+            E0a = lsum<LANES>(E0a);
+        }
+    }
+    if (EXTRA && a.inert) {
+        // backward-Euler inertia 1/2 c |x_i - xhat_i|^2, c = m_ii / dt^2
+        const R c = at(a.inert, v);
+        const R2 xh = at(a.xhat, v);
+        qgx += c * (xi.x - xh.x);
+        qgy += c * (xi.y - xh.y);
+        kxx += c;
+        kyy += c;
     }
     const R2 f = at(a.fext, v);
-    const R gtx = gx - f.x, gty = gy - f.y;
-    const R Axx = R(2) * s + lxx, Axy = lxy, Ayy = R(2) * s + lyy;
+    const R gtx = gx + qgx - f.x, gty = gy + qgy - f.y;
+    R Axx = R(2) * s + lxx + kxx, Axy = lxy + kxy, Ayy = R(2) * s + lyy + kyy;
+    R gsx = gtx, gsy = gty;  // with the active half-planes
+    if constexpr (EXTRA) {
+        for (int q = 0; q < a.n_planes; ++q) {
+            const R nx = at(a.planes, 4 * q), ny = at(a.planes, 4 * q + 1), kp = at(a.planes, 4 * q + 3);
+            const R phi = nx * xi.x + ny * xi.y - at(a.planes, 4 * q + 2);
+            if (phi < R(0)) {
+                gsx += kp * phi * nx;
+                gsy += kp * phi * ny;
+                Axx += kp * nx * nx;
+                Axy += kp * nx * ny;
+                Ayy += kp * ny * ny;
+            }
+        }
+    }
     const R det = Axx * Ayy - Axy * Axy;
     bool reject = !(Axx > R(0) && det > R(0));
     R dx = R(0), dy = R(0), alpha = R(1);
     if (!reject) {
         const R id = R(1) / det;
-        dx = -(Ayy * gtx - Axy * gty) * id;
-        dy = -(Axx * gty - Axy * gtx) * id;
-        if constexpr (SAFE && MODEL == kPlanarNeo) {
+        dx = -(Ayy * gsx - Axy * gsy) * id;
+        dy = -(Axx * gsy - Axy * gsx) * id;
+    }
+    if (SAFE && !reject) {
+        const R u = sizeof(R) == 8 ? R(1.1102230246251565e-16) : R(5.9604644775390625e-08);
+        // change of the half-plane penalties when x_i moves by alpha d
+        auto plane_change = [&](R al, R& dE, R& ab) {
+            if constexpr (EXTRA) {
+                for (int q = 0; q < a.n_planes; ++q) {
+                    const R e0 = plane_energy2(a, q, xi.x, xi.y);
+                    const R e1 = plane_energy2(a, q, xi.x + al * dx, xi.y + al * dy);
+                    dE += e1 - e0;
+                    ab += e0 + e1;
+                }
+            }
+        };
+        if constexpr (MODEL == kPlanarNeo) {
             // Along x_i + alpha d the Neo-Hookean local energy is exactly
             // E(0) + alpha g.d + alpha^2 / 2 d^T H d with
-            // H = sum A0 (mu |dN_i|^2 I + lhat c c^T): |F|^2 is quadratic and
-            // det F affine in x_i.
-            const R hxx = s + lxx + mxx, hxy = lxy + mxy, hyy = s + lyy + myy;
+            // H = sum A0 (mu |dN_i|^2 I + lhat c c^T) (|F|^2 is quadratic and
+            // det F affine in x_i) plus the exact quadratic terms; the
+            // half-planes are evaluated exactly.
+            const R hxx = s + lxx + mxx + kxx, hxy = lxy + mxy + kxy, hyy = s + lyy + myy + kyy;
             const R lin = gtx * dx + gty * dy;
             const R quad = dx * (hxx * dx + hxy * dy) + dy * (hxy * dx + hyy * dy);
-            const R u = sizeof(R) == 8 ? R(1.1102230246251565e-16) : R(5.9604644775390625e-08);
             for (int h = 0;; ++h) {
-                const R dE = alpha * lin + R(0.5) * alpha * alpha * quad;
-                const R ab = abs_(alpha * lin) + abs_(R(0.5) * alpha * alpha * quad);
+                R dE = alpha * lin + R(0.5) * alpha * alpha * quad;
+                R ab = abs_(alpha * lin) + abs_(R(0.5) * alpha * alpha * quad);
+                plane_change(alpha, dE, ab);
                 if (dE <= R(8) * u * ab) break;
                 if (h >= a.max_halvings) {
                     reject = true;
                     break;
                 }
                 alpha *= R(0.5);
+            }
+        } else if constexpr (COR_EXACT) {
+            // The corotated local energy is majorised by the quadratic with
+            // gradient g and Hessian A (without the half-planes): mu
+            // |F' - R(F')|^2 <= mu |F' - R(F)|^2.  Only a half-plane that
+            // the step enters can raise the energy beyond it; when the bound
+            // does not show a decrease, the energy is evaluated exactly.
+            const R bl = gtx * dx + gty * dy;
+            const R bxx = R(2) * s + lxx + kxx, bxy = lxy + kxy, byy = R(2) * s + lyy + kyy;
+            const R bq = dx * (bxx * dx + bxy * dy) + dy * (bxy * dx + byy * dy);
+            R dEb = bl + R(0.5) * bq, abb = abs_(bl) + abs_(R(0.5) * bq);
+            for (int q = 0; q < a.n_planes; ++q) {
+                const R nx = at(a.planes, 4 * q), ny = at(a.planes, 4 * q + 1), kp = at(a.planes, 4 * q + 3);
+                const R phi0 = nx * xi.x + ny * xi.y - at(a.planes, 4 * q + 2);
+                const R phi1 = phi0 + nx * dx + ny * dy;
+                const R e0 = phi0 < R(0) ? R(0.5) * kp * phi0 * phi0 : R(0);
+                const R e1 = phi1 < R(0) ? R(0.5) * kp * phi1 * phi1 : R(0);
+                // an active half-plane is inside the quadratic already
+                const R qpl = phi0 < R(0) ? R(0.5) * kp * (phi1 * phi1 - phi0 * phi0) : R(0);
+                dEb += (e1 - e0) - qpl;
+                abb += e0 + e1 + abs_(qpl);
+            }
+            if (!(dEb <= R(8) * u * abb)) {
+                const R qlin = qgx * dx + qgy * dy;
+                const R qquad = dx * (kxx * dx + kxy * dy) + dy * (kxy * dx + kyy * dy);
+                const R flin = f.x * dx + f.y * dy;
+                for (int h = 0;; ++h) {
+                    R E1 = R(0), E1a = R(0);
+                    for (int k = kb + lane; k < ke; k += LANES) {
+                        const R e = cor_energy2(visit2<R, UNI>(a, k, xi.x + alpha * dx, xi.y + alpha * dy));
+                        E1 += e;
+                        E1a += abs_(e);
+                    }
+                    if (LANES > 1) {
+                        E1 = lsum<LANES>(E1);
+                        E1a = lsum<LANES>(E1a);
+                    }
+                    R dE = (E1 - E0) + alpha * (qlin - flin) + R(0.5) * alpha * alpha * qquad;
+                    R ab = E0a + E1a + abs_(alpha * (qlin - flin)) + abs_(R(0.5) * alpha * alpha * qquad);
+                    plane_change(alpha, dE, ab);
+                    if (dE <= R(8) * u * ab) break;
+                    if (h >= a.max_halvings) {
+                        reject = true;
+                        break;
+                    }
+                    alpha *= R(0.5);
+                }
             }
         }
     }
@@ -162,39 +329,48 @@ __global__ __launch_bounds__(kBlk) void k2_phase(Sweep2Args<R> a, int vbeg, int 
     }
 }
 
-template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool UNI>
+template <class R, int MODEL, int LANES, bool ACCEL, bool SAFE, bool UNI, bool EXTRA>
 hipError_t phase_t(const Sweep2Args<R>& a, int vb, int ve, hipStream_t s)
 {
     const int64_t threads = int64_t(ve - vb) * LANES;
     if (threads <= 0) return hipSuccess;
-    hipLaunchKernelGGL((k2_phase<R, MODEL, LANES, ACCEL, SAFE, UNI>), dim3(nblocks(threads)), dim3(kBlk), 0, s,
-                       a, vb, ve);
+    hipLaunchKernelGGL((k2_phase<R, MODEL, LANES, ACCEL, SAFE, UNI, EXTRA>), dim3(nblocks(threads)), dim3(kBlk),
+                       0, s, a, vb, ve);
     return hipGetLastError();
 }
 
-template <class R, int MODEL, int LANES, bool UNI>
+template <class R, int MODEL, int LANES, bool UNI, bool EXTRA>
 hipError_t phase_flags(const Sweep2Args<R>& a, bool accel, bool safe, int vb, int ve, hipStream_t s)
 {
-    // the corotated full step never raises the local energy: no safeguard
-    if (MODEL == kPlanarCor) safe = false;
+    // the corotated full step never raises the local energy unless it
+    // enters a half-plane: no safeguard without them
+    if (MODEL == kPlanarCor && !(EXTRA && a.n_planes > 0)) safe = false;
     if (accel)
-        return safe ? phase_t<R, MODEL, LANES, true, true, UNI>(a, vb, ve, s)
-                    : phase_t<R, MODEL, LANES, true, false, UNI>(a, vb, ve, s);
-    return safe ? phase_t<R, MODEL, LANES, false, true, UNI>(a, vb, ve, s)
-                : phase_t<R, MODEL, LANES, false, false, UNI>(a, vb, ve, s);
+        return safe ? phase_t<R, MODEL, LANES, true, true, UNI, EXTRA>(a, vb, ve, s)
+                    : phase_t<R, MODEL, LANES, true, false, UNI, EXTRA>(a, vb, ve, s);
+    return safe ? phase_t<R, MODEL, LANES, false, true, UNI, EXTRA>(a, vb, ve, s)
+                : phase_t<R, MODEL, LANES, false, false, UNI, EXTRA>(a, vb, ve, s);
 }
 
-template <class R, int MODEL, bool UNI>
+template <class R, int MODEL, bool UNI, bool EXTRA>
 hipError_t phase_lanes(const Sweep2Args<R>& a, int lanes, bool accel, bool safe, int vb, int ve, hipStream_t s)
 {
     switch (lanes) {
-    case 1: return phase_flags<R, MODEL, 1, UNI>(a, accel, safe, vb, ve, s);
-    case 2: return phase_flags<R, MODEL, 2, UNI>(a, accel, safe, vb, ve, s);
-    case 4: return phase_flags<R, MODEL, 4, UNI>(a, accel, safe, vb, ve, s);
-    case 8: return phase_flags<R, MODEL, 8, UNI>(a, accel, safe, vb, ve, s);
-    case 16: return phase_flags<R, MODEL, 16, UNI>(a, accel, safe, vb, ve, s);
+    case 1: return phase_flags<R, MODEL, 1, UNI, EXTRA>(a, accel, safe, vb, ve, s);
+    case 2: return phase_flags<R, MODEL, 2, UNI, EXTRA>(a, accel, safe, vb, ve, s);
+    case 4: return phase_flags<R, MODEL, 4, UNI, EXTRA>(a, accel, safe, vb, ve, s);
+    case 8: return phase_flags<R, MODEL, 8, UNI, EXTRA>(a, accel, safe, vb, ve, s);
+    case 16: return phase_flags<R, MODEL, 16, UNI, EXTRA>(a, accel, safe, vb, ve, s);
     default: return hipErrorInvalidValue;
     }
+}
+
+template <class R, bool UNI, bool EXTRA>
+hipError_t phase_models(const Sweep2Args<R>& a, int model, int lanes, bool accel, bool safe, int vb, int ve,
+                        hipStream_t s)
+{
+    if (model == kPlanarNeo) return phase_lanes<R, kPlanarNeo, UNI, EXTRA>(a, lanes, accel, safe, vb, ve, s);
+    return phase_lanes<R, kPlanarCor, UNI, EXTRA>(a, lanes, accel, safe, vb, ve, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -248,6 +424,30 @@ __global__ __launch_bounds__(kBlk) void k2_tri_stress(Res2Args<R> a)
     a.ebuf[e] = G.A0 * psi;
 }
 
+// C_c = sum_j w_j x_{v_j} in FP64.
+template <class R>
+__device__ __forceinline__ double2 constraint_value2(const Res2Args<R>& a, int c)
+{
+    double2 C{0.0, 0.0};
+    for (int j = a.wc_ptr[c]; j < a.wc_ptr[c + 1]; ++j) {
+        const double2 p = x64(a.X[a.wc_vert[j]]);
+        C.x += a.wc_w[j] * p.x;
+        C.y += a.wc_w[j] * p.y;
+    }
+    return C;
+}
+
+// 1/2 C_c^T K_c C_c of every weak constraint into its energy slot.
+template <class R>
+__global__ __launch_bounds__(kBlk) void k2_wc_energy(Res2Args<R> a)
+{
+    const int c = blockIdx.x * kBlk + int(threadIdx.x);
+    if (c >= a.n_wc) return;
+    const double2 C = constraint_value2(a, c);
+    const double* K = a.wc_K + 3 * int64_t(c);
+    a.ebuf[a.n_tris + a.n_verts + c] = 0.5 * (K[0] * C.x * C.x + 2.0 * K[1] * C.x * C.y + K[2] * C.y * C.y);
+}
+
 template <class R>
 __global__ __launch_bounds__(kBlk) void k2_vertex_residual(Res2Args<R> a, double* r_out)
 {
@@ -255,17 +455,43 @@ __global__ __launch_bounds__(kBlk) void k2_vertex_residual(Res2Args<R> a, double
     if (v >= a.n_verts) return;
     const double2 xi = x64(a.X[v]);
     const double fx = a.fext64[2 * v], fy = a.fext64[2 * v + 1];
-    double rx = 0.0, ry = 0.0;
+    double rx = 0.0, ry = 0.0, E = -(xi.x * fx + xi.y * fy);
+    // half-plane penalties on every vertex
+    double px = 0.0, py = 0.0;
+    for (int q = 0; q < a.n_planes; ++q) {
+        const double* pl = a.planes + 4 * q;
+        const double phi = pl[0] * xi.x + pl[1] * xi.y - pl[2];
+        if (phi < 0.0) {
+            E += 0.5 * pl[3] * phi * phi;
+            px += pl[3] * phi * pl[0];
+            py += pl[3] * phi * pl[1];
+        }
+    }
     if (v < a.n_free) {
-        rx = fx;
-        ry = fy;
+        rx = fx - px;
+        ry = fy - py;
         for (int k = a.rvptr[v]; k < a.rvptr[v + 1]; ++k) {
             const double* p = a.vp + 2 * int64_t(a.rv[k]);
             rx -= p[0];
             ry -= p[1];
         }
+        if (a.n_wc > 0)
+            for (int k = a.wvptr[v]; k < a.wvptr[v + 1]; ++k) {
+                const int c = a.wv_c[k];
+                const double2 C = constraint_value2(a, c);
+                const double* K = a.wc_K + 3 * int64_t(c);
+                rx -= a.wv_s[k] * (K[0] * C.x + K[1] * C.y);
+                ry -= a.wv_s[k] * (K[1] * C.x + K[2] * C.y);
+            }
+        if (a.inert) {
+            const double c = a.inert[v];
+            const double dx = xi.x - a.xhat[2 * v], dy = xi.y - a.xhat[2 * v + 1];
+            E += 0.5 * c * (dx * dx + dy * dy);
+            rx -= c * dx;
+            ry -= c * dy;
+        }
     }
-    a.ebuf[a.n_tris + v] = -(xi.x * fx + xi.y * fy);
+    a.ebuf[a.n_tris + v] = E;
     a.rsq[v] = rx * rx + ry * ry;
     if (r_out) {
         double* o = r_out + 2 * int64_t(a.orig_of[v]);
@@ -311,18 +537,43 @@ __global__ __launch_bounds__(kBlk) void k2_store(const typename R2t<R>::T* src, 
     x_user[2 * int64_t(o) + 1] = p.y;
 }
 
+template <class R>
+__global__ __launch_bounds__(kBlk) void k2_xhat(const double* x_n, const double* x_prev, const int* orig_of,
+                                                double* xhat64, typename R2t<R>::T* xhat, int n_free)
+{
+    const int v = blockIdx.x * kBlk + int(threadIdx.x);
+    if (v >= n_free) return;
+    const int64_t o = orig_of[v];
+    const double hx = 2.0 * x_n[2 * o] - x_prev[2 * o], hy = 2.0 * x_n[2 * o + 1] - x_prev[2 * o + 1];
+    xhat64[2 * int64_t(v)] = hx;
+    xhat64[2 * int64_t(v) + 1] = hy;
+    typename R2t<R>::T h;
+    h.x = R(hx);
+    h.y = R(hy);
+    xhat[v] = h;
+}
+
 }  // namespace
 
 template <class R>
-hipError_t launch_phase2(const Sweep2Args<R>& a, int model, int lanes, bool accel, bool safe, bool uniform,
-                         int vbeg, int vend, hipStream_t s)
+hipError_t launch_xhat2(const double* x_n, const double* x_prev, const int* orig_of, double* xhat64,
+                        typename R2t<R>::T* xhat, int n_free, hipStream_t s)
 {
-    if (uniform) {
-        if (model == kPlanarNeo) return phase_lanes<R, kPlanarNeo, true>(a, lanes, accel, safe, vbeg, vend, s);
-        return phase_lanes<R, kPlanarCor, true>(a, lanes, accel, safe, vbeg, vend, s);
-    }
-    if (model == kPlanarNeo) return phase_lanes<R, kPlanarNeo, false>(a, lanes, accel, safe, vbeg, vend, s);
-    return phase_lanes<R, kPlanarCor, false>(a, lanes, accel, safe, vbeg, vend, s);
+    if (n_free > 0)
+        hipLaunchKernelGGL((k2_xhat<R>), dim3(nblocks(n_free)), dim3(kBlk), 0, s, x_n, x_prev, orig_of, xhat64,
+                           xhat, n_free);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_phase2(const Sweep2Args<R>& a, int model, int lanes, bool accel, bool safe, bool uniform,
+                         bool extra, int vbeg, int vend, hipStream_t s)
+{
+    if (extra)
+        return uniform ? phase_models<R, true, true>(a, model, lanes, accel, safe, vbeg, vend, s)
+                       : phase_models<R, false, true>(a, model, lanes, accel, safe, vbeg, vend, s);
+    return uniform ? phase_models<R, true, false>(a, model, lanes, accel, safe, vbeg, vend, s)
+                   : phase_models<R, false, false>(a, model, lanes, accel, safe, vbeg, vend, s);
 }
 
 template <class R>
@@ -336,6 +587,7 @@ hipError_t launch_residual2(const Res2Args<R>& a, double* r_out, hipStream_t s)
     }
     if (a.n_verts > 0)
         hipLaunchKernelGGL((k2_vertex_residual<R>), dim3(nblocks(a.n_verts)), dim3(kBlk), 0, s, a, r_out);
+    if (a.n_wc > 0) hipLaunchKernelGGL((k2_wc_energy<R>), dim3(nblocks(a.n_wc)), dim3(kBlk), 0, s, a);
     return hipGetLastError();
 }
 
@@ -361,12 +613,14 @@ hipError_t launch_store2(const typename R2t<R>::T* src, const int* orig_of, R* x
 }
 
 #define PBNG2D_INSTANTIATE(R)                                                                                  \
-    template hipError_t launch_phase2<R>(const Sweep2Args<R>&, int, int, bool, bool, bool, int, int,          \
+    template hipError_t launch_phase2<R>(const Sweep2Args<R>&, int, int, bool, bool, bool, bool, int, int,    \
                                          hipStream_t);                                                        \
     template hipError_t launch_residual2<R>(const Res2Args<R>&, double*, hipStream_t);                       \
     template hipError_t launch_load2<R>(const R*, const int*, const R2t<R>::T*, R2t<R>::T*, R2t<R>::T*,       \
                                         R2t<R>::T*, int, int, hipStream_t);                                   \
-    template hipError_t launch_store2<R>(const R2t<R>::T*, const int*, R*, int, hipStream_t);
+    template hipError_t launch_store2<R>(const R2t<R>::T*, const int*, R*, int, hipStream_t);                \
+    template hipError_t launch_xhat2<R>(const double*, const double*, const int*, double*, R2t<R>::T*, int,  \
+                                        hipStream_t);
 
 PBNG2D_INSTANTIATE(float)
 PBNG2D_INSTANTIATE(double)

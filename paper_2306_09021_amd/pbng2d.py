@@ -20,7 +20,8 @@ class Problem2D(C.Structure):
                 ("model", C.c_int32), ("mu", C.c_double), ("lambda_", C.c_double), ("mu_tri", _dp),
                 ("lambda_tri", _dp), ("density", C.c_double), ("gravity", C.c_double * 2),
                 ("nodal_force", _dp), ("n_dirichlet", C.c_int32), ("dirichlet_idx", _ip),
-                ("dirichlet_x", _dp)]
+                ("dirichlet_x", _dp), ("n_wc", C.c_int32), ("wc_ptr", _ip), ("wc_vert", _ip),
+                ("wc_w", _dp), ("wc_K", _dp), ("n_planes", C.c_int32), ("planes", _dp)]
 
 
 _ready = False
@@ -44,6 +45,7 @@ def lib():
             "pbng2d_store": ([vp, vp, vp], C.c_int32),
             "pbng2d_sweeps": ([vp, C.c_int32, C.POINTER(SolveOpts), vp], C.c_int32),
             "pbng2d_phase_bytes": ([vp, C.c_int32, i64, i64, i64], C.c_int32),
+            "pbng2d_workspace_set_inertia": ([vp, C.c_double, vp, vp, vp], C.c_int32),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)
@@ -56,14 +58,16 @@ def lib():
 def exported_symbols() -> List[str]:
     return ["pbng2d_color", "pbng2d_workspace_create", "pbng2d_workspace_destroy",
             "pbng2d_workspace_info", "pbng2d_workspace_colors", "pbng2d_solve", "pbng2d_residual",
-            "pbng2d_load", "pbng2d_store", "pbng2d_sweeps", "pbng2d_phase_bytes"]
+            "pbng2d_load", "pbng2d_store", "pbng2d_sweeps", "pbng2d_phase_bytes",
+            "pbng2d_workspace_set_inertia"]
 
 
 class HostProblem2D:
     """A planar problem in host memory; keeps the numpy buffers alive."""
 
     def __init__(self, rest_pos, tris, model, mu, lam, dirichlet_idx, dirichlet_x, density=0.0,
-                 gravity=(0.0, 0.0), nodal_force=None):
+                 gravity=(0.0, 0.0), nodal_force=None, wc_ptr=None, wc_vert=None, wc_w=None, wc_K=None,
+                 planes=None):
         self.rest_pos = np.ascontiguousarray(rest_pos, np.float64).reshape(-1, 2)
         self.tris = np.ascontiguousarray(tris, np.int32).reshape(-1, 3)
         nt = self.tris.shape[0]
@@ -81,6 +85,12 @@ class HostProblem2D:
         self.gravity = tuple(float(g) for g in gravity)
         self.nodal_force = (None if nodal_force is None
                             else np.ascontiguousarray(nodal_force, np.float64).reshape(-1, 2))
+        self.wc_ptr = np.ascontiguousarray(np.zeros(1) if wc_ptr is None else wc_ptr, np.int32).reshape(-1)
+        self.wc_vert = np.ascontiguousarray(np.zeros(0) if wc_vert is None else wc_vert, np.int32).reshape(-1)
+        self.wc_w = np.ascontiguousarray(np.zeros(0) if wc_w is None else wc_w, np.float64).reshape(-1)
+        self.wc_K = np.ascontiguousarray(np.zeros((0, 3)) if wc_K is None else wc_K, np.float64).reshape(-1, 3)
+        self.planes = np.ascontiguousarray(np.zeros((0, 4)) if planes is None else planes,
+                                           np.float64).reshape(-1, 4)
 
     @property
     def n_verts(self):
@@ -97,6 +107,13 @@ class HostProblem2D:
         s.nodal_force = _d(self.nodal_force)
         s.n_dirichlet = self.dirichlet_idx.size
         s.dirichlet_idx, s.dirichlet_x = _i(self.dirichlet_idx), _d(self.dirichlet_x)
+        s.n_wc = self.wc_ptr.size - 1
+        if s.n_wc > 0:
+            s.wc_ptr, s.wc_vert = _i(self.wc_ptr), _i(self.wc_vert)
+            s.wc_w, s.wc_K = _d(self.wc_w), _d(self.wc_K)
+        s.n_planes = self.planes.shape[0]
+        if s.n_planes > 0:
+            s.planes = _d(self.planes)
         return s
 
 
@@ -105,7 +122,9 @@ def problem_from_scenario(sc) -> HostProblem2D:
     Lame conversion."""
     mu, lam = lame(sc.E, sc.nu)
     return HostProblem2D(sc.rest_pos, sc.tris, sc.model, mu, lam, sc.dirichlet_idx, sc.dirichlet_x,
-                         density=sc.density, gravity=sc.gravity, nodal_force=sc.nodal_force)
+                         density=sc.density, gravity=sc.gravity, nodal_force=sc.nodal_force,
+                         wc_ptr=sc.wc_ptr, wc_vert=sc.wc_vert, wc_w=sc.wc_w, wc_K=sc.wc_K,
+                         planes=sc.planes)
 
 
 def color(problem: HostProblem2D):
@@ -178,6 +197,21 @@ class Workspace2D:
         out = np.zeros(self.n_verts, np.int32)
         _check(lib().pbng2d_workspace_colors(self.handle, _i(out)))
         return out
+
+    def set_inertia(self, dt, x_n=None, x_prev=None, stream=None):
+        """Backward-Euler inertia with time step dt and xhat = 2 x^n - x^{n-1}
+        (float64 cuda tensors [n_verts, 2], caller order); dt <= 0 turns it
+        off."""
+        import torch
+        if dt > 0:
+            for t in (x_n, x_prev):
+                if t is None or t.dtype != torch.float64 or not t.is_cuda or t.numel() != 2 * self.n_verts:
+                    raise ValueError("x^n and x^{n-1} must be float64 cuda tensors [%d, 2]" % self.n_verts)
+            x_n, x_prev = x_n.contiguous(), x_prev.contiguous()
+            _check(lib().pbng2d_workspace_set_inertia(self.handle, float(dt), _ptr(x_n), _ptr(x_prev),
+                                                      _stream(stream)))
+        else:
+            _check(lib().pbng2d_workspace_set_inertia(self.handle, float(dt), None, None, _stream(stream)))
 
     def load(self, x, stream=None):
         self._check_x(x)

@@ -608,3 +608,41 @@ def stretched_square(n: int, model: str = NEOHOOKEAN, stretch: float = 1.5, E: f
     return Scenario2D(name="stretched_square_%d_%s" % (n, model), rest_pos=X, tris=T, model=model,
                       E=np.asarray(E, np.float64), nu=np.asarray(nu, np.float64), dirichlet_idx=idx,
                       dirichlet_x=xd, x0=x0, density=density, gravity=tuple(gravity))
+
+
+def planar_terms(n: int = 17, model: str = NEOHOOKEAN, seed: int = 21, k_ground: float = 1e6,
+                 n_springs: int = 12) -> Scenario2D:
+    """A planar problem with every extra term: an n x n-vertex unit block
+    (E = 1e4, nu = 0.3, R0 = 100, gravity -9.8 * 40 along y) hanging from
+    its top row, seeded weak constraints (two-vertex springs K = 1e3 I
+    between random free vertices, plus three-vertex constraints with random
+    weights and a coupled K), and a ground half-plane y >= -0.02 (n = +y,
+    k = k_ground) that the bottom row, started 0.01 above it and jittered,
+    is pressed into."""
+    rng = np.random.default_rng(seed)
+    X, T = square_mesh(n, n, 1.0 / (n - 1))
+    top = np.nonzero(X[:, 1] > 1.0 - 1e-12)[0].astype(np.int32)
+    free = np.setdiff1d(np.arange(n * n), top)
+    ptr, vert, w, K = [0], [], [], []
+    for _ in range(n_springs):
+        a, b = rng.choice(free, 2, replace=False)
+        vert += [int(a), int(b)]
+        w += [1.0, -1.0]
+        ptr.append(len(vert))
+        K.append([1e3, 0.0, 1e3])
+    for _ in range(n_springs // 3):
+        m = rng.choice(free, 3, replace=False)
+        vert += [int(v) for v in m]
+        w += list(rng.uniform(-1.0, 1.0, 3))
+        ptr.append(len(vert))
+        K.append([800.0, 150.0, 500.0])
+    x0 = X.copy()
+    x0[:, 1] -= 0.03 * (1.0 - X[:, 1])           # sag toward the ground: bottom row at -0.03 + 0.01
+    x0[:, 1] += 0.01
+    x0 += 0.002 * rng.uniform(-1.0, 1.0, x0.shape)
+    x0[top] = X[top]
+    return Scenario2D(name="planar_terms_%d_%s" % (n, model), rest_pos=X, tris=T, model=model,
+                      E=np.asarray(1e4), nu=np.asarray(0.3), dirichlet_idx=top, dirichlet_x=X[top].copy(),
+                      x0=x0, density=100.0, gravity=(0.0, -9.8 * 40.0), wc_ptr=np.array(ptr, np.int32),
+                      wc_vert=np.array(vert, np.int32), wc_w=np.array(w), wc_K=np.array(K),
+                      planes=np.array([[0.0, 1.0, -0.02, k_ground]]))

@@ -25,7 +25,7 @@ def header_functions():
 def test_library_exports_every_planar_symbol():
     L = ctypes.CDLL(pbng.LIB_PATH)
     names = header_functions()
-    assert len(names) == 11
+    assert len(names) == 12
     for n in names:
         assert hasattr(L, n), n
     assert sorted(pbng2d.exported_symbols()) == names
@@ -87,3 +87,37 @@ def test_planar_workspace_rejects_invalid_problems_before_device_work():
     assert pbng2d.lib().pbng2d_workspace_create(ctypes.byref(s), None, pbng.REAL["mixed"],
                                                 ctypes.byref(h)) == -1
     assert not h.value
+
+
+def test_planar_constraints_and_planes_are_validated_before_device_work():
+    def fresh():
+        sc = S.stretched_square(6, "nh", 1.2)
+        sc.wc_ptr = np.array([0, 2, 5], np.int32)
+        sc.wc_vert = np.array([7, 22, 14, 16, 28], np.int32)   # members share no triangle
+        sc.wc_w = np.array([1.0, -1.0, 0.5, 0.25, -0.75])
+        sc.wc_K = np.array([[10.0, 1.0, 5.0], [3.0, 0.0, 3.0]])
+        sc.planes = np.array([[0.0, 1.0, 0.1, 100.0]])
+        return pbng2d.problem_from_scenario(sc)
+    hp = fresh()
+    c, n = pbng2d.color(hp)
+    assert c[7] != c[22] and len({c[14], c[16], c[28]}) == 3     # constraint members differ
+    hp = fresh()
+    hp.wc_ptr[1] = 6                                   # not monotone
+    assert _create_err(hp) == -1
+    hp = fresh()
+    hp.wc_vert[1] = 7                                  # a constraint repeats a vertex
+    assert _create_err(hp) == -2
+    hp = fresh()
+    hp.wc_vert[0] = 10 ** 6                            # out of range
+    assert _create_err(hp) == -2
+    hp = fresh()
+    hp.wc_K[1, 0] = np.nan                             # non-finite stiffness
+    assert _create_err(hp) == -5
+    hp = fresh()
+    hp.planes[0, 3] = -1.0                             # negative half-plane stiffness
+    assert _create_err(hp) == -1
+    hp = fresh()
+    col, _ = pbng2d.color(hp)
+    col = col.copy()
+    col[22] = col[7]                                   # constraint members share a colour
+    assert _create_err(hp, colors=col) == -4

@@ -188,3 +188,75 @@ def test_full_size_one_sweep_and_residual(real):
     n_o, E_o, r_o = P.residual(op, xg)
     assert abs(rn - n_o) <= 1e-10 * n_o and abs(E - E_o) <= 1e-10 * abs(E_o)
     assert np.abs(host(r) - r_o).max() <= 1e-9 * np.abs(r_o).max()
+
+
+@pytest.mark.parametrize("model", ["nh", "corotated"])
+@pytest.mark.parametrize("real", ["f64", "f32"])
+@pytest.mark.parametrize("accel", ["none", "chebyshev"])
+def test_constraints_and_half_plane_parity(model, real, accel):
+    """Weak constraints, a stiff ground half-plane and gravity: the full step
+    overshoots into the half-plane, so the safeguard halves (the corotated
+    kernel then evaluates its energy exactly)."""
+    sc = S.planar_terms(17, model)
+    kw = dict(accel=accel, rho=0.9, gamma=1.0, safeguard="backtrack")
+    announce("planar terms %s %s %s" % (model, real, accel))
+    xg, xo, st, sto, ws = both(sc, real, 30, **kw)
+    e = rel_err(xg, xo)
+    print("rel err", e, "oracle halvings", sto["halvings"], "rejected", sto["rejected"], st["rejected"])
+    assert sto["halvings"] > 0
+    assert e <= TOL[real]
+    assert st["rejected"] == sto["rejected"]
+
+
+@pytest.mark.parametrize("model", ["nh", "corotated"])
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_backward_euler_frames_parity(model, real):
+    """Four backward-Euler frames (dt = 1/100) of the same block: each frame
+    sets xhat from the two previous frames on both sides, then 20 sweeps."""
+    sc = S.planar_terms(13, model)
+    announce("planar backward euler %s %s" % (model, real))
+    ws = ws2(sc, real)
+    op = P.make_problem(sc)
+    col = ws.colors()
+    dt = 0.01
+    xo_prev = xo_n = sc.initial_iterate()
+    xg_prev = xg_n = torch.tensor(sc.initial_iterate(), dtype=torch.float64, device="cuda")
+    for frame in range(4):
+        op.set_inertia(dt, xo_n, xo_prev)
+        xo, sto = P.solve(op, col, xo_n, max_sweeps=20, safeguard="backtrack")
+        ws.set_inertia(dt, xg_n, xg_prev)
+        x = xg_n.clone().to(ws.dtype).contiguous()     # a copy: the solve works in place
+        ws.solve(x, max_sweeps=20, rel_tol=0.0, check_every=20, safeguard="backtrack")
+        e = rel_err(host(x), xo)
+        print("frame", frame, "rel err", e, "halvings", sto["halvings"])
+        assert e <= TOL[real] * (1 + frame)
+        xo_prev, xo_n = xo_n, xo
+        xg_prev, xg_n = xg_n, x.to(torch.float64).clone()
+    ws.set_inertia(0.0)
+    x = dev2(sc.initial_iterate(), real)
+    ws.solve(x, max_sweeps=10, rel_tol=0.0, check_every=10, safeguard="backtrack")
+    op.set_inertia(0.0)
+    xo, _ = P.solve(op, col, sc.initial_iterate(), max_sweeps=10, safeguard="backtrack")
+    assert rel_err(host(x), xo) <= TOL[real]      # inertia off: the quasistatic solve again
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_residual_and_energy_with_every_term(real):
+    sc = S.planar_terms(13, "corotated")
+    announce("planar residual all terms %s" % real)
+    ws = ws2(sc, real)
+    op = P.make_problem(sc)
+    rng = np.random.default_rng(3)
+    x0 = sc.initial_iterate() + 0.01 * rng.normal(size=(sc.n_verts, 2))
+    x0[sc.dirichlet_idx] = sc.dirichlet_x
+    x = dev2(x0, real)
+    xh = host(x)                                     # the positions as stored (float in f32)
+    xn = torch.tensor(xh + 0.003, dtype=torch.float64, device="cuda")
+    xp = torch.tensor(xh - 0.001, dtype=torch.float64, device="cuda")
+    ws.set_inertia(0.02, xn, xp)
+    op.set_inertia(0.02, host(xn), host(xp))
+    rn, en, r = ws.residual(x, want_r=True)
+    ro, eo, rvo = P.residual(op, xh)
+    assert abs(rn - ro) <= 1e-10 * ro
+    assert abs(en - eo) <= 1e-10 * max(1.0, abs(eo))
+    assert np.abs(host(r) - rvo).max() <= 1e-10 * np.abs(rvo).max()
