@@ -281,7 +281,8 @@ def sub_reports(args, pbng, S, torch, stream):
             "paper_blocks": lambda: paper_boxes_report(pbng, S, torch, stream),
             "backward_euler": lambda: dynamics_report(pbng, S, torch, stream),
             "collisions": lambda: collision_report(pbng, S, torch, stream),
-            "planar": lambda: planar_report(torch, stream, sweeps=args.planar_sweeps)}
+            "planar": lambda: planar_report(torch, stream, sweeps=args.planar_sweeps),
+            "planar_terms": lambda: planar_terms_report(torch, stream)}
 
 
 def batched_report(pbng, S, torch, stream, subset):
@@ -664,6 +665,56 @@ def collision_report(pbng, S, torch, stream, frames=8):
             "iterations_per_frame": sub * iters, "ms_per_frame": round(tm * 1e3, 3),
             "contacts_per_frame_end": n_contacts, "colours": n_colors,
             "paper_ms_per_frame_cpu": 1630.0}
+
+
+def planar_terms_report(torch, stream, n=1025, frames=5, iters=40, roof_sweeps=20):
+    """The planar path with every extra term at full size: an n x n block
+    hanging from its top row under strong gravity, 2000 seeded springs and
+    666 three-vertex weak constraints, a stiff ground half-plane it is
+    pressed into, and backward-Euler frames (dt = 1/100, FP32, 40 plain
+    iterations per frame, safeguard on; the Chebyshev blend with rho = 0.9
+    diverges on this problem, in the oracle too, from 129^2 vertices on).
+    Timed: frames 2..frames.  The sweep roofline counts the elastic visit
+    records of pbng2d_phase_bytes, not the constraint, half-plane and
+    inertia data."""
+    from paper_2306_09021_amd import pbng2d
+    from paper_2306_09021_amd import scenarios as S
+    sc = S.planar_terms(n, "nh", n_springs=2000)
+    ws = pbng2d.Workspace2D(pbng2d.problem_from_scenario(sc), real="f32")
+    dt = 0.01
+    opts = pbng2d.solve_opts(accel="none", safeguard="backtrack", rel_tol=0.0, max_sweeps=iters,
+                             check_every=iters)
+    x = torch.tensor(sc.initial_iterate(), dtype=torch.float32, device="cuda")
+    x_prev = x.double().clone()
+    x_n = x_prev.clone()
+    times, rel = [], []
+    for f in range(frames):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ws.set_inertia(dt, x_n, x_prev, stream=stream)
+        _, st = ws.solve(x, opts, stream=stream)
+        x_prev, x_n = x_n, x.double().clone()
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+        rel.append(round(st["rel_residual"], 6))
+    tm = sum(times[1:]) / (frames - 1)
+    ws.load(x, stream=stream)
+    ws.sweeps(3, opts, stream=stream)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    ws.sweeps(roof_sweeps, opts, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    t = ev0.elapsed_time(ev1) * 1e-3 / roof_sweeps
+    b = sum(ws.phase_bytes(c)[0] for c in range(ws.n_colors))
+    return {"workload": "hanging_block_%dx%d_neohookean_springs_ground_backward_euler" % (n, n),
+            "vertices": ws.n_verts, "triangles": ws.n_tris, "weak_constraints": int(sc.wc_ptr.size - 1),
+            "colours": ws.n_colors, "iterations_per_frame": iters, "ms_per_frame": round(tm * 1e3, 3),
+            "vertex_updates_per_s": round(iters * ws.n_free / tm, 1), "frame_rel_residual_fp64": rel,
+            "sweep_roofline": {"sweep_us": round(t * 1e6, 2), "algorithmic_bytes_per_sweep": int(b),
+                               "achieved_GBs": round(b / t / 1e9, 1),
+                               "frac_of_hbm_peak": round(b / t / 1e9 / HBM_PEAK_GBS, 4)}}
 
 
 def planar_report(torch, stream, n=1025, sweeps=200, roof_sweeps=20):

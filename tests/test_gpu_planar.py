@@ -260,3 +260,35 @@ def test_residual_and_energy_with_every_term(real):
     assert abs(rn - ro) <= 1e-10 * ro
     assert abs(en - eo) <= 1e-10 * max(1.0, abs(eo))
     assert np.abs(host(r) - rvo).max() <= 1e-10 * np.abs(rvo).max()
+
+
+@pytest.mark.parametrize("real", ["f64", "f32"])
+def test_full_size_terms_one_sweep_and_residual(real):
+    """The measured planar-terms workload at full size (1025 x 1025 hanging
+    block, 2000 springs and 666 three-vertex constraints, ground half-plane,
+    inertia): one GPU sweep against one oracle sweep over every vertex (the
+    safeguard on in FP64; off in FP32, where float and double energy tests
+    could decide a tie differently), then the FP64 residual vector."""
+    sc = S.planar_terms(1025, "nh", n_springs=2000)
+    op = P.make_problem(sc)
+    announce("planar terms full size one sweep %s" % real)
+    ws = ws2(sc, real)
+    x0 = sc.initial_iterate()
+    xr = x0.astype(np.float32).astype(np.float64) if real == "f32" else x0
+    xp = xr.copy()
+    xp[:, 1] += 0.001                        # moving down at 0.1 m/s with dt = 0.01
+    op.set_inertia(0.01, xr, xp)
+    ws.set_inertia(0.01, torch.tensor(xr, device="cuda"), torch.tensor(xp, device="cuda"))
+    sg = "backtrack" if real == "f64" else "none"
+    xo, sto = P.solve(op, ws.colors(), xr, max_sweeps=1, safeguard=sg)
+    x = dev2(xr, real)
+    ws.solve(x, max_sweeps=1, rel_tol=0.0, check_every=1, safeguard=sg, accel="chebyshev", rho=0.9, gamma=1.0)
+    xg = host(x)
+    d = np.abs(xg - xo).max(axis=1)
+    scale = np.abs(xo - xr).max()
+    print("max diff", d.max(), "scale", scale, "oracle halvings", sto["halvings"])
+    assert d.max() <= (1e-10 if real == "f64" else 1e-5) * max(scale, 1e-3) + (0.0 if real == "f64" else 1e-6)
+    rn, E, r = ws.residual(x, want_r=True)
+    n_o, E_o, r_o = P.residual(op, xg)
+    assert abs(rn - n_o) <= 1e-10 * n_o and abs(E - E_o) <= 1e-10 * abs(E_o)
+    assert np.abs(host(r) - r_o).max() <= 1e-9 * np.abs(r_o).max()
