@@ -1,7 +1,7 @@
 """GPU parity: the HIP path (through the C ABI) against the FP64 oracle on
 the same seeded inputs.
 
-Tolerances (see also DESIGN.md):
+Tolerances:
 * FP64 sweeps: relative position error <= 1e-9 after the same sweep count.
   Both sides follow the same colour order and per-vertex step; they differ
   only in rounding order (accumulation order, cofactor by cross products vs
