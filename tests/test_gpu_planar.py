@@ -292,3 +292,27 @@ def test_full_size_terms_one_sweep_and_residual(real):
     n_o, E_o, r_o = P.residual(op, xg)
     assert abs(rn - n_o) <= 1e-10 * n_o and abs(E - E_o) <= 1e-10 * abs(E_o)
     assert np.abs(host(r) - r_o).max() <= 1e-9 * np.abs(r_o).max()
+
+
+@pytest.mark.parametrize("model", ["nh", "corotated"])
+@pytest.mark.parametrize("lanes", [1, 2, 8, 16])
+def test_terms_per_triangle_materials_and_lanes(model, lanes):
+    """The extra terms with per-triangle Lame parameters (the 32-byte record
+    form) and every lane count (the weak constraints of a vertex are spread
+    over its lanes like its visits), safeguard on, FP64."""
+    sc = S.planar_terms(17, model)
+    rng = np.random.default_rng(9)
+    sc.E = np.exp(rng.uniform(np.log(3e3), np.log(3e4), sc.n_tris))
+    sc.nu = rng.uniform(0.2, 0.45, sc.n_tris)
+    announce("planar terms per-triangle %s lanes=%d" % (model, lanes))
+    ws = ws2(sc, "f64")
+    op = P.make_problem(sc)
+    op.set_inertia(0.02, sc.initial_iterate(), sc.initial_iterate())
+    x0 = torch.tensor(sc.initial_iterate(), dtype=torch.float64, device="cuda")
+    ws.set_inertia(0.02, x0, x0)
+    xo, sto = P.solve(op, ws.colors(), sc.initial_iterate(), max_sweeps=25, safeguard="backtrack")
+    x = dev2(sc.initial_iterate(), "f64")
+    ws.solve(x, max_sweeps=25, rel_tol=0.0, check_every=25, safeguard="backtrack", lanes=lanes)
+    e = rel_err(host(x), xo)
+    print("rel err", e, "halvings", sto["halvings"])
+    assert e <= 1e-10
