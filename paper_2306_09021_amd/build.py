@@ -18,6 +18,7 @@ UNITS = [("pbng_kernels.hip", ["-DPBNG_KERNEL_SET=0"], "kernels_f32.o"),
          ("pbng_kernels.hip", ["-DPBNG_KERNEL_SET=1"], "kernels_f64.o"),
          ("pbng_kernels.hip", ["-DPBNG_KERNEL_SET=2"], "kernels_mixed.o"),
          ("pbng_contacts.hip", [], "contacts.o"),
+         ("pbng_upload.hip", [], "upload.o"),
          ("pbng2d_kernels.hip", [], "planar_kernels.o"),
          ("pbng_host.cpp", [], "host.o"),
          ("pbng2d_host.cpp", [], "planar_host.o")]

@@ -311,6 +311,9 @@ struct pbng_workspace {
     };
     std::vector<Contact> contacts;
     std::vector<int> h_int_of, h_orig_of;
+    // every installed constraint (static and dynamic, internal indices) and
+    // the per-vertex CSR of the constraints of each vertex
+    std::vector<int> h_all_wc_ptr, h_all_wc_vert, h_wvptr, h_wv_c;
     // current colouring (internal order, -1 on Dirichlet vertices), the
     // host incidence it is checked against, and the launch plan of a sweep:
     // per colour the home range (skipping vertices recoloured away) and
@@ -327,7 +330,8 @@ struct pbng_workspace {
     bool moved_any = false;
     int ncol_dyn = 0;
     Dev pcol, xlist;
-    Pinned stage;                          // staging of batched uploads
+    Pinned stage;                          // staging of batched uploads (host, device)
+    Dev ustage;
     // proximity detection: candidate surface vertices (built on first use)
     // and scratch sized for n_cand candidates and det_cap pairs
     int n_cand = -1;
@@ -526,23 +530,13 @@ void rebuild_phases(pbng_workspace* ws, Uploader& up)
 // colour none of them has.  Colours of vertices processed earlier count.
 void recolor_contacts(pbng_workspace* ws)
 {
-    const int nv = int(ws->nv), nf = int(ws->nfree);
-    // weak-constraint incidence per internal vertex (static and dynamic)
-    std::vector<std::vector<int>> nb(nv);
-    auto link = [&](const int* m, int cnt) {
-        for (int i = 0; i < cnt; ++i)
-            for (int j = 0; j < cnt; ++j)
-                if (i != j) nb[m[i]].push_back(m[j]);
-    };
-    for (size_t c = 0; c + 1 < ws->h_wc_ptr.size(); ++c)
-        link(ws->h_wc_vert.data() + ws->h_wc_ptr[c], ws->h_wc_ptr[c + 1] - ws->h_wc_ptr[c]);
+    const int nf = int(ws->nfree);
+    // the constraints of every vertex (static and dynamic) come from the
+    // per-vertex CSR that install_constraints has just built
     std::vector<int> extra;
-    for (const auto& ct : ws->contacts) {
-        const int m[2] = {ct.a, ct.b};
-        link(m, 2);
-        for (int v : m)
+    for (const auto& ct : ws->contacts)
+        for (int v : {ct.a, ct.b})
             if (v < nf) extra.push_back(v);
-    }
     std::sort(extra.begin(), extra.end(), [&](int x, int y) { return ws->h_orig_of[x] < ws->h_orig_of[y]; });
     extra.erase(std::unique(extra.begin(), extra.end()), extra.end());
     std::vector<char> used;
@@ -559,8 +553,13 @@ void recolor_contacts(pbng_workspace* ws)
             for (int u : {t.x, t.y, t.z, t.w})
                 if (u != v) mark(u);
         }
-        for (int u : nb[v])
-            if (u != v) mark(u);
+        for (int k = ws->h_wvptr[v]; k < ws->h_wvptr[v + 1]; ++k) {
+            const int c = ws->h_wv_c[k];
+            for (int m = ws->h_all_wc_ptr[c]; m < ws->h_all_wc_ptr[c + 1]; ++m) {
+                const int u = ws->h_all_wc_vert[m];
+                if (u != v) mark(u);
+            }
+        }
         const int cur = ws->h_color[v];
         if (cur >= 0 && (cur >= int(used.size()) || !used[cur])) continue;
         int c = 0;
@@ -587,7 +586,6 @@ void install_constraints(pbng_workspace* ws, Uploader& up)
     std::vector<double> wc_w, wc_K, wv_s;
     std::vector<int> tet_eidx(nt), vert_eidx(nv);
     std::vector<int64_t> seg_e(n + 1);
-    std::vector<std::vector<std::pair<int, double>>> per(nv);
     int64_t eo = 0;
     for (int q = 0; q < n; ++q) {
         const int64_t vo = ws->v_off[q], to = ws->t_off[q];
@@ -597,11 +595,9 @@ void install_constraints(pbng_workspace* ws, Uploader& up)
         for (int64_t i = 0; i < nvq; ++i) vert_eidx[vo + i] = int(eo + ntq + i);
         int64_t slot = eo + ntq + nvq;
         auto add = [&](const int* verts, const double* w, int m, const double* K) {
-            const int gc = int(wc_ptr.size()) - 1;
             for (int j = 0; j < m; ++j) {
                 wc_vert.push_back(verts[j]);
                 wc_w.push_back(w[j]);
-                per[verts[j]].push_back({gc, w[j]});
             }
             wc_ptr.push_back(int(wc_vert.size()));
             for (int j = 0; j < 6; ++j) wc_K.push_back(K[j]);
@@ -619,14 +615,23 @@ void install_constraints(pbng_workspace* ws, Uploader& up)
         eo = slot;
     }
     seg_e[n] = eo;
-    for (int64_t k = 0; k < nv; ++k) {
-        for (auto& pr : per[k]) {
-            wv_c.push_back(pr.first);
-            wv_s.push_back(pr.second);
-        }
-        wvptr[k + 1] = int(wv_c.size());
+    // per-vertex CSR of (constraint, weight), constraints in ascending
+    // order for every vertex (a stable counting pass over the members)
+    const int n_all = int(wc_ptr.size()) - 1;
+    for (int v : wc_vert) wvptr[v + 1]++;
+    for (int64_t k = 0; k < nv; ++k) wvptr[k + 1] += wvptr[k];
+    wv_c.resize(wc_vert.size());
+    wv_s.resize(wc_vert.size());
+    {
+        std::vector<int> fill(wvptr.begin(), wvptr.end() - 1);
+        for (int c = 0; c < n_all; ++c)
+            for (int m = wc_ptr[c]; m < wc_ptr[c + 1]; ++m) {
+                const int k = fill[wc_vert[m]]++;
+                wv_c[k] = c;
+                wv_s[k] = wc_w[m];
+            }
     }
-    ws->n_wc = int(wc_ptr.size()) - 1;
+    ws->n_wc = n_all;
     ws->any_wc = ws->n_wc > 0 || ws->n_planes > 0;
     auto upR = [&](Dev& d, const std::vector<double>& v) {
         if (ws->math64()) stage_real<double>(up, d, v);
@@ -647,6 +652,11 @@ void install_constraints(pbng_workspace* ws, Uploader& up)
     up.add(ws->vert_eidx, vert_eidx);
     ws->ebuf.reserve(std::max<int64_t>(1, eo) * sizeof(double));
     ws->plan_e = make_plan(seg_e, ws->seg_e_cb, ws->seg_e_ce, ws->seg_e_q, ws->seg_e_part, up);
+    // host copies for the recolouring (the uploader holds its own)
+    ws->h_all_wc_ptr = std::move(wc_ptr);
+    ws->h_all_wc_vert = std::move(wc_vert);
+    ws->h_wvptr = std::move(wvptr);
+    ws->h_wv_c = std::move(wv_c);
 }
 
 void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const int32_t* colors_in)
@@ -968,7 +978,7 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     Uploader up;
     ws->plan_r = make_plan(seg_r, ws->seg_r_cb, ws->seg_r_ce, ws->seg_r_q, ws->seg_r_part, up);
     install_constraints(ws, up);
-    up.flush(ws->stage, nullptr);
+    up.flush(ws->stage, ws->ustage, nullptr);
     ws->out_r.alloc(n * sizeof(double));
     ws->out_e.alloc(n * sizeof(double));
     ws->W.alloc(nv * ws->r4());
@@ -982,7 +992,7 @@ void build_workspace(pbng_workspace* ws, const pbng_problem* ps, int n, const in
     for (int c = 0; c < ws->ncol; ++c)
         for (int k = ws->col_ptr[c]; k < ws->col_ptr[c + 1]; ++k) ws->h_color[k] = c;
     rebuild_phases(ws, up);
-    up.flush(ws->stage, nullptr);
+    up.flush(ws->stage, ws->ustage, nullptr);
 }
 
 template <class R, class PR>
@@ -1860,7 +1870,7 @@ int32_t pbng_workspace_set_contacts(pbng_workspace* ws, int32_t n, const int32_t
         install_constraints(ws, up);
         recolor_contacts(ws);
         rebuild_phases(ws, up);
-        up.flush(ws->stage, s);
+        up.flush(ws->stage, ws->ustage, s);
         ws->drop_graph();
         ws->ring_valid = false;
         return PBNG_OK;

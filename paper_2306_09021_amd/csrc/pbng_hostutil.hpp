@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
@@ -111,6 +112,17 @@ struct Dev {
     }
 };
 
+// One entry of a batched upload: n_words 32-bit words from byte offset
+// src_off of the staged payload to dst.
+struct CopyItem {
+    void* dst;
+    uint32_t src_off;
+    uint32_t n_words;
+};
+
+// Device side of a batched upload (one launch for every entry).
+hipError_t launch_scatter_words(const void* staged, int n_items, uint32_t max_words, hipStream_t s);
+
 // Pinned host memory that grows on demand.
 struct Pinned {
     void* p = nullptr;
@@ -135,10 +147,12 @@ struct Pinned {
 
 // Batched uploads: add() sizes the target (keeping its allocation when it
 // is large enough, see Dev::reserve) and packs the host array; flush()
-// copies the packed arrays into one pinned staging buffer, issues one
-// asynchronous copy per target on the stream and waits for them, so the
-// staging buffer and every target are ready when it returns.  Replaces one synchronous pageable copy plus a
-// free and an allocation per array.
+// writes a table of CopyItem entries and the packed arrays into one pinned
+// staging buffer, copies it to the device in one transfer, places every
+// array with one scatter launch and waits, so the staging buffers and every
+// target are ready when it returns.  Replaces one synchronous pageable copy
+// plus a free and an allocation per array.  Array sizes are whole 32-bit
+// words.
 struct Uploader {
     struct Item {
         Dev* d;
@@ -158,18 +172,29 @@ struct Uploader {
         if (n) std::memcpy(payload.data() + off, v.data(), n);
         items.push_back({&d, off, n});
     }
-    void flush(Pinned& stage, hipStream_t s)
+    void flush(Pinned& stage, Dev& dstage, hipStream_t s)
     {
-        if (items.empty()) return;
-        stage.reserve(std::max<size_t>(payload.size(), 256));
-        std::memcpy(stage.p, payload.data(), payload.size());
+        std::vector<CopyItem> tab;
+        uint32_t max_words = 0;
+        const size_t table = (items.size() * sizeof(CopyItem) + 255) & ~size_t(255);
+        if (table + payload.size() >= (size_t(1) << 32)) fail(PBNG_EUNSUPPORTED, "upload batch too large");
         for (const Item& it : items) {
-            if (it.n)
-                hipchk(hipMemcpyAsync(it.d->p, static_cast<unsigned char*>(stage.p) + it.off, it.n,
-                                      hipMemcpyHostToDevice, s),
-                       "upload");
+            if (it.n % 4) fail(PBNG_EINVAL, "upload of %zu bytes is not whole 32-bit words", it.n);
+            if (it.n == 0) continue;
+            tab.push_back({it.d->p, uint32_t(table + it.off), uint32_t(it.n / 4)});
+            max_words = std::max(max_words, uint32_t(it.n / 4));
         }
-        hipchk(hipStreamSynchronize(s), "upload");
+        if (!tab.empty()) {
+            const size_t total = table + payload.size();
+            stage.reserve(total);
+            dstage.reserve(total);
+            unsigned char* h = static_cast<unsigned char*>(stage.p);
+            std::memcpy(h, tab.data(), tab.size() * sizeof(CopyItem));
+            std::memcpy(h + table, payload.data(), payload.size());
+            hipchk(hipMemcpyAsync(dstage.p, stage.p, total, hipMemcpyHostToDevice, s), "upload");
+            hipchk(launch_scatter_words(dstage.p, int(tab.size()), max_words, s), "upload scatter");
+            hipchk(hipStreamSynchronize(s), "upload");
+        }
         payload.clear();
         items.clear();
     }
