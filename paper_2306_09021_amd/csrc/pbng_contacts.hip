@@ -7,7 +7,7 @@
 // part.  A uniform grid of cell size r is formed by sorting the candidates
 // by a 64-bit key (instance, cell x, y, z with 15-bit wrapped cell
 // coordinates; wrapping only adds candidates, which the distance test
-// removes).  Every candidate then looks up the 27 cells around it by binary
+// removes); the sorts cover only the key bits in use.  Every candidate then looks up the 27 cells around it by binary
 // search in the sorted keys and emits each pair (a, b), a < b in caller
 // order, of vertices of different parts of one instance within r (not both
 // Dirichlet, not coincident).  The pairs are sorted afterwards, so the
@@ -102,21 +102,22 @@ __global__ __launch_bounds__(kBlk) void k_pairs(const P* x, const ContactCand c,
             }
 }
 
-__global__ __launch_bounds__(kBlk) void k_pair_keys(const int2* pairs, int n, unsigned long long* keys)
+// (a, b) as a << vb | b: ascending keys order the pairs by a, then b.
+__global__ __launch_bounds__(kBlk) void k_pair_keys(const int2* pairs, int n, int vb, unsigned long long* keys)
 {
     const int k = blockIdx.x * kBlk + threadIdx.x;
     if (k >= n) return;
-    keys[k] = (static_cast<unsigned long long>(static_cast<unsigned>(pairs[k].x)) << 32) |
+    keys[k] = (static_cast<unsigned long long>(static_cast<unsigned>(pairs[k].x)) << vb) |
               static_cast<unsigned>(pairs[k].y);
 }
 
 template <class P>
-__global__ __launch_bounds__(kBlk) void k_pair_out(const P* x, const unsigned long long* keys, int n,
+__global__ __launch_bounds__(kBlk) void k_pair_out(const P* x, const unsigned long long* keys, int n, int vb,
                                                    int* pairs_out, double* normals_out)
 {
     const int k = blockIdx.x * kBlk + threadIdx.x;
     if (k >= n) return;
-    const int ga = int(keys[k] >> 32), gb = int(keys[k] & 0xffffffffull);
+    const int ga = int(keys[k] >> vb), gb = int(keys[k] & ((1ull << vb) - 1));
     double pa[3], pb[3];
     pos_of(x, ga, pa);
     pos_of(x, gb, pb);
@@ -147,7 +148,7 @@ hipError_t launch_detect(const P* x, const ContactCand& c, double r, int max_pai
                        w.vals_in);
     size_t tmp = w.tmp_bytes;
     e = hipcub::DeviceRadixSort::SortPairs(w.tmp, tmp, w.keys_in, w.keys_out, w.vals_in, w.vals_out, c.n,
-                                           0, 64, s);
+                                           0, 45 + c.inst_bits, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero, dim3(1), dim3(kBlk), 0, s, w.count);
     hipLaunchKernelGGL((k_pairs<P>), dim3(nblocks(c.n)), dim3(kBlk), 0, s, x, c, r, w.keys_out,
@@ -159,12 +160,12 @@ hipError_t launch_detect(const P* x, const ContactCand& c, double r, int max_pai
     if (e != hipSuccess) return e;
     *n_found = h;
     if (h == 0 || h > max_pairs) return hipGetLastError();
-    hipLaunchKernelGGL(k_pair_keys, dim3(nblocks(h)), dim3(kBlk), 0, s, w.pairs, h, w.pkeys_in);
+    hipLaunchKernelGGL(k_pair_keys, dim3(nblocks(h)), dim3(kBlk), 0, s, w.pairs, h, c.vert_bits, w.pkeys_in);
     tmp = w.tmp_bytes;
-    e = hipcub::DeviceRadixSort::SortKeys(w.tmp, tmp, w.pkeys_in, w.pkeys_out, h, 0, 64, s);
+    e = hipcub::DeviceRadixSort::SortKeys(w.tmp, tmp, w.pkeys_in, w.pkeys_out, h, 0, 2 * c.vert_bits, s);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_pair_out<P>), dim3(nblocks(h)), dim3(kBlk), 0, s, x, w.pkeys_out, h, pairs_out,
-                       normals_out);
+    hipLaunchKernelGGL((k_pair_out<P>), dim3(nblocks(h)), dim3(kBlk), 0, s, x, w.pkeys_out, h, c.vert_bits,
+                       pairs_out, normals_out);
     return hipGetLastError();
 }
 

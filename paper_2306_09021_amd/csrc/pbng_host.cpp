@@ -1960,8 +1960,16 @@ int32_t pbng_detect_contacts(pbng_workspace* ws, const void* x_dev, double radiu
             ws->d_tmp.alloc(ws->d_tmp_bytes);
             ws->det_cap = cap;
         }
+        auto bits = [](int64_t v) {
+            int b = 0;
+            while (v > 0) {
+                ++b;
+                v >>= 1;
+            }
+            return b;
+        };
         ContactCand c{ws->n_cand, ws->cand_caller.as<int>(), ws->cand_inst.as<int>(), ws->cand_body.as<int>(),
-                      ws->cand_dir.as<int>()};
+                      ws->cand_dir.as<int>(), bits(ws->n_inst - 1), std::max(1, bits(ws->nv - 1))};
         DetectScratch w{ws->d_keys_in.as<unsigned long long>(), ws->d_keys_out.as<unsigned long long>(),
                         ws->d_vals_in.as<int>(), ws->d_vals_out.as<int>(), ws->d_pairs.as<int2>(),
                         ws->d_pkeys_in.as<unsigned long long>(), ws->d_pkeys_out.as<unsigned long long>(),

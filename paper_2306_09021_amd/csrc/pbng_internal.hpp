@@ -235,6 +235,8 @@ struct ContactCand {
     const int* inst;
     const int* body;
     const int* dir;
+    int inst_bits;          // bits of the largest instance index (0 for one)
+    int vert_bits;          // bits of the largest caller vertex index
 };
 struct DetectScratch {
     unsigned long long* keys_in;
