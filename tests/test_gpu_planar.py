@@ -316,3 +316,44 @@ def test_terms_per_triangle_materials_and_lanes(model, lanes):
     e = rel_err(host(x), xo)
     print("rel err", e, "halvings", sto["halvings"])
     assert e <= 1e-10
+
+
+def test_terms_degenerate_cases():
+    """Edge cases of the extra terms: a constraint whose members are all
+    Dirichlet (energy only), a free vertex that no triangle touches held by
+    a spring alone (its A_i is s^2 K), a half-plane with k = 0 (no effect),
+    and inertia on a vertex of zero lumped mass (no effect)."""
+    X, T = S.square_mesh(6, 6, 0.2)
+    X = np.vstack([X, [[3.0, 3.0]]])               # vertex 36: no triangle
+    n = X.shape[0]
+    top = np.nonzero(X[:36, 1] > 1.0 - 1e-12)[0]
+    didx = np.concatenate([top, [0, 1]]).astype(np.int32)      # 0, 1: bottom corner pinned too
+    rng = np.random.default_rng(4)
+    x0 = X + 0.01 * rng.normal(size=X.shape)
+    x0[didx] = X[didx]
+    f = np.zeros((n, 2))
+    f[36] = [0.5, -0.25]
+    sc = S.Scenario2D(name="terms_edge", rest_pos=X, tris=T, model="nh", E=np.asarray(1e3), nu=np.asarray(0.3),
+                      dirichlet_idx=didx, dirichlet_x=X[didx].copy(), x0=x0, density=10.0, gravity=(0.0, -9.8),
+                      nodal_force=f,
+                      wc_ptr=np.array([0, 2, 4, 6], np.int32),
+                      wc_vert=np.array([0, 1, 36, 35, 12, 20], np.int32),   # all-Dirichlet; lone vertex; inner spring
+                      wc_w=np.array([1.0, -1.0, 1.0, -1.0, 1.0, -1.0]),
+                      wc_K=np.array([[50.0, 0.0, 50.0], [80.0, 10.0, 40.0], [30.0, 0.0, 30.0]]),
+                      planes=np.array([[0.0, 1.0, 0.5, 0.0]]))
+    announce("planar terms degenerate cases")
+    for real in ("f64", "f32"):
+        ws = ws2(sc, real)
+        op = P.make_problem(sc)
+        xn = torch.tensor(sc.initial_iterate(), dtype=torch.float64, device="cuda")
+        ws.set_inertia(0.05, xn, xn)
+        op.set_inertia(0.05, sc.initial_iterate(), sc.initial_iterate())
+        assert op.mass[36] == 0.0
+        xo, sto = P.solve(op, ws.colors(), sc.initial_iterate(), max_sweeps=20, safeguard="backtrack")
+        x = dev2(sc.initial_iterate(), real)
+        rc, st = ws.solve(x, max_sweeps=20, rel_tol=0.0, check_every=20, safeguard="backtrack")
+        assert st["rejected"] == sto["rejected"] == 0
+        assert rel_err(host(x), xo) <= TOL[real]
+        rn, en = ws.residual(x)
+        ro, eo, _ = P.residual(op, host(x))
+        assert abs(rn - ro) <= 1e-10 * max(1.0, ro) and abs(en - eo) <= 1e-10 * max(1.0, abs(eo))
