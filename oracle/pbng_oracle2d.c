@@ -667,3 +667,143 @@ int32_t or2_sweep_energy_trace(const or2_problem* p, const int32_t* colors, doub
     adj_free(&A);
     return n;
 }
+
+/* ------------------------------------------------------------------ */
+/* Adjoint: the true Hessian and the parameter gradients                */
+/* ------------------------------------------------------------------ */
+/* dP[L], the derivative of P(F) along L, for d = 2.  cof is linear in F
+ * here (cof(F + L) = cof F + cof L), and det F has derivative cof F : L.
+ *   Neo-Hookean: mu L + lhat (cof F : L) cof F + (lhat (J - 1) - mu) cof L
+ *   corotated:   2 mu (L - dR[L]) + lambda (cof F : L) cof F
+ *                + lambda (J - 1) cof L,
+ * with R = [[c, -s], [s, c]] at the angle theta = atan2(b, a) of
+ * (a, b) = (F00 + F11, F10 - F01) and dR = dtheta [[-s, -c], [c, -s]],
+ * dtheta = (a (L10 - L01) - b (L00 + L11)) / (a^2 + b^2) (0 where a = b = 0,
+ * the one configuration without a unique closest rotation). */
+void or2_stress_diff(int model, double mu, double lam, const double* F, const double* L, double* dP)
+{
+    double C[4], CL[4], J = det2(F);
+    cofactor2(F, C);
+    cofactor2(L, CL);
+    double cl = 0.0;
+    for (int k = 0; k < 4; ++k) cl += C[k] * L[k];
+    if (model == OR2_NEOHOOKEAN) {
+        double lh = mu + lam;
+        for (int k = 0; k < 4; ++k) dP[k] = mu * L[k] + lh * cl * C[k] + (lh * (J - 1.0) - mu) * CL[k];
+        return;
+    }
+    double a = F[0] + F[3], b = F[2] - F[1], r2 = a * a + b * b;
+    double R[4], dR[4] = {0.0, 0.0, 0.0, 0.0};
+    or2_rotation(F, R);
+    if (r2 > 0.0) {
+        double dth = (a * (L[2] - L[1]) - b * (L[0] + L[3])) / r2;
+        double c = R[0], s = R[2];
+        dR[0] = -s * dth;
+        dR[1] = -c * dth;
+        dR[2] = c * dth;
+        dR[3] = -s * dth;
+    }
+    for (int k = 0; k < 4; ++k) dP[k] = 2.0 * mu * (L[k] - dR[k]) + lam * cl * C[k] + lam * (J - 1.0) * CL[k];
+}
+
+/* out = H v for every vertex row, H the true Hessian of the total energy at
+ * y (triangles through dP, weak constraints s_ci K_c C_c(v), active
+ * half-planes k (n . v_i) n, inertia minert_i v_i); v is taken as zero on
+ * Dirichlet vertices.  Returns 0, or < 0 on a mesh error. */
+int32_t or2_hessian_apply(const or2_problem* p, const double* y, const double* v, double* out)
+{
+    or2_adj A;
+    int rc = adj_build(p, &A);
+    if (rc) return rc;
+    for (int k = 0; k < 2 * p->nv; ++k) out[k] = 0.0;
+    for (int e = 0; e < p->nt; ++e) {
+        const int32_t* t = p->tris + 3 * e;
+        const double* g = A.dN + 6 * e;
+        double F[4], L[4] = {0.0, 0.0, 0.0, 0.0}, dP[4];
+        deformation_gradient(y, t, g, F);
+        for (int j = 0; j < 3; ++j) {
+            if (p->is_dir[t[j]]) continue;
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) L[2 * r + c] += v[2 * t[j] + r] * g[2 * j + c];
+        }
+        or2_stress_diff(p->model, p->mu[e], p->lam[e], F, L, dP);
+        for (int j = 0; j < 3; ++j)
+            for (int r = 0; r < 2; ++r)
+                out[2 * t[j] + r] += A.A0[e] * (dP[2 * r] * g[2 * j] + dP[2 * r + 1] * g[2 * j + 1]);
+    }
+    for (int c = 0; c < p->n_wc; ++c) {
+        double Cv[2] = {0.0, 0.0};
+        for (int s = p->wc_ptr[c]; s < p->wc_ptr[c + 1]; ++s) {
+            int u = p->wc_vert[s];
+            if (p->is_dir[u]) continue;
+            Cv[0] += p->wc_w[s] * v[2 * u];
+            Cv[1] += p->wc_w[s] * v[2 * u + 1];
+        }
+        const double* K = p->wc_K + 3 * c;
+        double KC[2] = {K[0] * Cv[0] + K[1] * Cv[1], K[1] * Cv[0] + K[2] * Cv[1]};
+        for (int s = p->wc_ptr[c]; s < p->wc_ptr[c + 1]; ++s)
+            for (int a = 0; a < 2; ++a) out[2 * p->wc_vert[s] + a] += p->wc_w[s] * KC[a];
+    }
+    for (int i = 0; i < p->nv; ++i) {
+        if (p->is_dir[i]) continue;
+        for (int q = 0; q < p->n_planes; ++q) {
+            const double* pl = p->planes + 4 * q;
+            if (plane_phi(pl, y + 2 * i) < 0.0) {
+                double nv = pl[0] * v[2 * i] + pl[1] * v[2 * i + 1];
+                out[2 * i] += pl[3] * nv * pl[0];
+                out[2 * i + 1] += pl[3] * nv * pl[1];
+            }
+        }
+        if (p->minert) {
+            out[2 * i] += p->minert[i] * v[2 * i];
+            out[2 * i + 1] += p->minert[i] * v[2 * i + 1];
+        }
+    }
+    adj_free(&A);
+    return 0;
+}
+
+/* Parameter gradients of L(x*(theta)) from the adjoint lam (H lam = dL/dx
+ * on free vertices, zero on Dirichlet ones): with Lam_e = sum_j lam_j dN_j^T,
+ *   dL/dmu_e     = -A0_e < dP/dmu, Lam_e >,
+ *   dL/dlambda_e = -A0_e (J - 1) < cof F, Lam_e >,
+ * dP/dmu = F + (J - 2) cof F (Neo-Hookean: P = mu F + (lhat (J - 1) - mu)
+ * cof F with lhat = mu + lambda) or 2 (F - R) (corotated). */
+int32_t or2_adjoint_gradients(const or2_problem* p, const double* y, const double* lam_v, double* dmu,
+                              double* dlam)
+{
+    or2_adj A;
+    int rc = adj_build(p, &A);
+    if (rc) return rc;
+    for (int e = 0; e < p->nt; ++e) {
+        const int32_t* t = p->tris + 3 * e;
+        const double* g = A.dN + 6 * e;
+        double F[4], C[4], L[4] = {0.0, 0.0, 0.0, 0.0};
+        deformation_gradient(y, t, g, F);
+        cofactor2(F, C);
+        double J = det2(F);
+        for (int j = 0; j < 3; ++j) {
+            if (p->is_dir[t[j]]) continue;
+            for (int r = 0; r < 2; ++r)
+                for (int c = 0; c < 2; ++c) L[2 * r + c] += lam_v[2 * t[j] + r] * g[2 * j + c];
+        }
+        double FL = 0.0, CL = 0.0;
+        for (int k = 0; k < 4; ++k) {
+            FL += F[k] * L[k];
+            CL += C[k] * L[k];
+        }
+        double dPdmu;
+        if (p->model == OR2_NEOHOOKEAN) {
+            dPdmu = FL + (J - 2.0) * CL;
+        } else {
+            double R[4], RL = 0.0;
+            or2_rotation(F, R);
+            for (int k = 0; k < 4; ++k) RL += R[k] * L[k];
+            dPdmu = 2.0 * (FL - RL);
+        }
+        dmu[e] = -A.A0[e] * dPdmu;
+        dlam[e] = -A.A0[e] * (J - 1.0) * CL;
+    }
+    adj_free(&A);
+    return 0;
+}

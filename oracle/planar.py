@@ -53,6 +53,11 @@ def lib():
         L.or2_solve.restype = C.c_int32
         L.or2_sweep_energy_trace.argtypes = [C.POINTER(_Problem2), _ip, _dp, C.POINTER(_Opts), _dp]
         L.or2_sweep_energy_trace.restype = C.c_int32
+        L.or2_stress_diff.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp, _dp]
+        L.or2_hessian_apply.argtypes = [C.POINTER(_Problem2), _dp, _dp, _dp]
+        L.or2_hessian_apply.restype = C.c_int32
+        L.or2_adjoint_gradients.argtypes = [C.POINTER(_Problem2), _dp, _dp, _dp, _dp]
+        L.or2_adjoint_gradients.restype = C.c_int32
         _ready = True
     return L
 
@@ -220,3 +225,92 @@ def sweep_energy_trace(op: PlanarProblem, colors, x, safeguard="backtrack", max_
     dE = np.zeros(op.nv)
     n = lib().or2_sweep_energy_trace(C.byref(op.struct()), _i(colors), _d(x), C.byref(o), _d(dE))
     return dE[:n], x
+
+
+# ---------------------------------------------------------------------------
+# adjoint (true Hessian, parameter gradients)
+# ---------------------------------------------------------------------------
+def stress_diff(model, mu, lam, F, L):
+    """dP[L] of the 2x2 first Piola-Kirchhoff stress."""
+    out = np.zeros((2, 2))
+    lib().or2_stress_diff(model, mu, lam, _d(_f64(F, (2, 2))), _d(_f64(L, (2, 2))), _d(out))
+    return out
+
+
+def hessian_apply(op: PlanarProblem, x, v):
+    """H v for every vertex row (v taken as zero on Dirichlet rows)."""
+    x = _f64(x, (-1, 2))
+    v = _f64(v, (-1, 2))
+    out = np.zeros((op.nv, 2))
+    rc = lib().or2_hessian_apply(C.byref(op.struct()), _d(x), _d(v), _d(out))
+    if rc:
+        raise ValueError("planar oracle hessian failed (%d)" % rc)
+    return out
+
+
+def adjoint_gradients(op: PlanarProblem, x, lam):
+    """(dL/dmu, dL/dlambda) per triangle from the adjoint lam."""
+    x = _f64(x, (-1, 2))
+    lam = _f64(lam, (-1, 2))
+    dmu, dlam = np.zeros(op.nt), np.zeros(op.nt)
+    rc = lib().or2_adjoint_gradients(C.byref(op.struct()), _d(x), _d(lam), _d(dmu), _d(dlam))
+    if rc:
+        raise ValueError("planar oracle adjoint gradients failed (%d)" % rc)
+    return dmu, dlam
+
+
+def free_dofs(op: PlanarProblem):
+    free = np.nonzero(op.is_dir == 0)[0]
+    return np.stack([2 * free, 2 * free + 1], axis=1).reshape(-1)
+
+
+def dense_hessian(op: PlanarProblem, x):
+    """The true Hessian restricted to the free degrees of freedom, one
+    column per unit vector (small problems only)."""
+    dofs = free_dofs(op)
+    H = np.zeros((dofs.size, dofs.size))
+    for c, d in enumerate(dofs):
+        v = np.zeros(2 * op.nv)
+        v[d] = 1.0
+        H[:, c] = hessian_apply(op, x, v).reshape(-1)[dofs]
+    return H
+
+
+def adjoint(op: PlanarProblem, x, dL_dx):
+    """The adjoint of the equilibrium x by its definition: lam = H^{-1} dL/dx
+    on the free degrees of freedom (dense solve), dL/dx_D = (dL/dx)_D -
+    (H lam)_D, and the parameter gradients.  Returns (lam [nv, 2],
+    dL/dx_D [n_dirichlet, 2] in dirichlet_idx order, dL/dmu, dL/dlambda)."""
+    b = _f64(dL_dx, (-1, 2)).reshape(-1)
+    dofs = free_dofs(op)
+    lam = np.zeros(2 * op.nv)
+    lam[dofs] = np.linalg.solve(dense_hessian(op, x), b[dofs])
+    lam = lam.reshape(-1, 2)
+    Hl = hessian_apply(op, x, lam)
+    dxd = b.reshape(-1, 2)[op.dirichlet_idx] - Hl[op.dirichlet_idx]
+    dmu, dlam = adjoint_gradients(op, x, lam)
+    return lam, dxd, dmu, dlam
+
+
+def newton_equilibrium(op: PlanarProblem, x0, tol=1e-13, max_iter=60):
+    """Equilibrium by Newton's method with the dense true Hessian and a
+    backtracking line search on the energy (small problems only)."""
+    x = np.array(x0, dtype=np.float64).reshape(-1, 2)
+    x[op.dirichlet_idx] = op.dirichlet_x
+    dofs = free_dofs(op)
+    r0 = residual(op, x)[0]
+    for _ in range(max_iter):
+        rn, E, r = residual(op, x)
+        if rn <= tol * max(r0, 1.0):
+            break
+        step = np.linalg.solve(dense_hessian(op, x), r.reshape(-1)[dofs])
+        t = 1.0
+        while True:
+            xt = x.copy().reshape(-1)
+            xt[dofs] += t * step
+            xt = xt.reshape(-1, 2)
+            if residual(op, xt)[1] <= E + 1e-12 * abs(E) or t < 1e-8:
+                break
+            t *= 0.5
+        x = xt
+    return x
