@@ -20,7 +20,7 @@
  * [n][2] arrays in the caller's vertex order.  One problem per workspace.
  * Not supported in the planar family: the stable Neo-Hookean model (its
  * printed rest-state constant 3 mu / (4 lambda) makes F = I stress free
- * only for d = 3), contact detection with recolouring, and the adjoint.
+ * only for d = 3), and contact detection with recolouring.
  */
 #ifndef PBNG2D_H
 #define PBNG2D_H
@@ -147,6 +147,32 @@ int32_t pbng2d_solve(pbng2d_workspace* ws, void* x_inout, const pbng_solve_opts*
  */
 int32_t pbng2d_residual(pbng2d_workspace* ws, const void* x, double* res_norm, double* energy,
                         double* r_out, void* hip_stream);
+
+/*
+ * Adjoint of a planar equilibrium (the planar form of pbng_adjoint): at
+ * x_eq (device [n_verts][2], workspace real type) solve H lam = dL/dx on
+ * the free vertices, H the true Hessian of the energy (triangles, weak
+ * constraints, active half-planes, inertia), by block Gauss-Seidel over the
+ * colours (diagonal blocks: the true H_ii for Neo-Hookean, which in 2-D is
+ * sum A0 (mu |dN_i|^2 I + lhat c c^T); the modified A_ii for corotated),
+ * then assemble
+ *   dL/dmu_e     = -A0_e < dP/dmu (F_e), Lam_e >,
+ *   dL/dlambda_e = -A0_e (J_e - 1) < cof F_e, Lam_e >,
+ *   dL/dx_k      = (dL/dx)_k - (H lam)_k for Dirichlet vertices k,
+ * Lam_e = sum_j lam_j dN_j^T, dP/dmu = F + (J - 2) cof F (Neo-Hookean) or
+ * 2 (F - R) (corotated).  dL_dx: device [n_verts][2], workspace real type.
+ * Outputs (device, double, any may be NULL): dL_dxD [n_dirichlet][2] in the
+ * order of dirichlet_idx, dL_dmu and dL_dlambda [n_tris], lam_out
+ * [n_verts][2] (zero on Dirichlet rows).  o: max_sweeps, rel_tol on
+ * ||b - H lam|| / ||b|| (FP64, free rows), check_every, accel
+ * (PBNG_ACCEL_NONE or PBNG_ACCEL_CHEBYSHEV with rho, gamma), lanes.  stats
+ * (host, one entry, may be NULL): sweeps and the adjoint residuals.
+ * Returns PBNG_OK, PBNG_NOT_CONVERGED (outputs valid), PBNG_ENAN or
+ * another error.
+ */
+int32_t pbng2d_adjoint(pbng2d_workspace* ws, const void* x_eq, const void* dL_dx, double* dL_dxD,
+                       double* dL_dmu, double* dL_dlambda, double* lam_out, const pbng_adjoint_opts* o,
+                       pbng_stats* stats, void* hip_stream);
 
 /*
  * Backward-Euler inertia (Eq. fem_be, minimised as the incremental

@@ -67,6 +67,37 @@ struct Sweep2Args {
     const R2* xhat;         // [n_free] 2 x^n - x^{n-1}
 };
 
+// Adjoint (block Gauss-Seidel on H lam = b over the same colours): X the
+// equilibrium, L the iterate (zero on Dirichlet rows), P / N the previous
+// and blended iterates with the Chebyshev blend.  The visit, constraint,
+// half-plane and inertia data are those of the sweep.
+template <class R>
+struct Adj2Args {
+    using R2 = typename R2t<R>::T;
+    using R4 = typename R4t<R>::T;
+    const R2* X;
+    R2* L;
+    R2* P;
+    R2* N;
+    const R2* B;            // dL/dx, internal order
+    const int* vptr;
+    const int2* jk;
+    const R4* gm;
+    const R2* vw;           // null with uniform materials
+    R mu_u, lam_u;
+    const int* wvptr;
+    const int* wv_c;
+    const R* wv_s;
+    const int* wc_ptr;
+    const int* wc_vert;
+    const R* wc_w;
+    const R* wc_K;
+    const R* planes;
+    int n_planes;
+    const R* inert;         // or null
+    R omega, gamma;
+};
+
 // FP64 residual / energy: per triangle A0 P dN_j (vp) and A0 Psi, per
 // vertex the force balance, -x . fhat, the half-plane penalties and the
 // inertia, per weak constraint its energy.
@@ -78,7 +109,7 @@ struct Res2Args {
     const TriGeo* geo;
     double* vp;             // [n_tris][3][2]
     double* ebuf;           // [n_tris + n_verts + n_wc] energy summands
-    const int* rvptr;       // [n_free + 1] visits of every free vertex
+    const int* rvptr;       // [n_verts + 1] triangle slots of every vertex
     const int* rv;          // tri * 3 + slot
     const double* fext64;   // [n_verts][2] internal order
     const int* orig_of;     // [n_verts]
@@ -107,6 +138,23 @@ hipError_t launch_phase2(const Sweep2Args<R>& a, int model, int lanes, bool acce
                          bool extra, int vbeg, int vend, hipStream_t s);
 template <class R>
 hipError_t launch_residual2(const Res2Args<R>& a, double* r_out, hipStream_t s);
+template <class R>
+hipError_t launch_adj_phase2(const Adj2Args<R>& a, int model, int lanes, bool accel, bool uniform, bool extra,
+                             int vbeg, int vend, hipStream_t s);
+// FP64 adjoint residual: vp <- A0 dP[Lam_e] dN_j per triangle (with
+// dL/dmu_e, dL/dlambda_e when dmu / dlam are non-null), then per vertex
+// H lam from its slots, constraints, half-planes and inertia; rsq[v] =
+// |b_v - (H lam)_v|^2 on free rows, dxd[dir_pos[v - n_free]] = b_v -
+// (H lam)_v on Dirichlet rows (dxd may be null).  The slots of every
+// vertex (rvptr / rv) and the constraint CSR (wvptr) cover all vertices.
+template <class R>
+hipError_t launch_adjoint_residual2(const Res2Args<R>& a, const typename R2t<R>::T* L,
+                                    const typename R2t<R>::T* B, double* dmu, double* dlam, double* dxd,
+                                    const int* dir_pos, hipStream_t s);
+// lam_out (caller order, double [n_verts][2]) from an internal iterate
+template <class R>
+hipError_t launch_store2_f64(const typename R2t<R>::T* src, const int* orig_of, double* out, int n_verts,
+                             hipStream_t s);
 template <class R>
 hipError_t launch_load2(const R* x_user, const int* orig_of, const typename R2t<R>::T* xd_int,
                         typename R2t<R>::T* d0, typename R2t<R>::T* d1, typename R2t<R>::T* d2, int n_free,

@@ -44,6 +44,9 @@ struct pbng2d_workspace {
     std::vector<double> mass_h;     // lumped m_ii, internal order
     Dev wvptr, wv_c, wv_s, wv_s64, wc_ptr, wc_vert, wc_w, wc_w64, wc_K, wc_K64, planes, planes64;
     Dev inert, inert64, xhat, xhat64;
+    // adjoint: equilibrium, iterate ring, right-hand side (internal order),
+    // Dirichlet vertex -> its position in the caller's Dirichlet list
+    Dev XA, LA, LPa, LNa, BA, dir_pos;
     bool extra() const { return n_wc > 0 || n_planes > 0 || inertia; }
 
     size_t r2() const { return real == PBNG_F64 ? 2 * sizeof(double) : 2 * sizeof(float); }
@@ -279,7 +282,6 @@ void pack(pbng2d_workspace* ws, const pbng2d_problem* p, const Inc& I, const std
     std::vector<int2> jk(std::max<int64_t>(1, ws->nvis));
     std::vector<R4> gm(std::max<int64_t>(1, ws->nvis));
     std::vector<R2> vw(std::max<int64_t>(1, ws->nvis));
-    std::vector<int> rv(std::max<int64_t>(1, ws->nvis));
     std::vector<TriGeo> geo(nt);
     std::vector<int4> tri(nt);
     for (int64_t e = 0; e < nt; ++e) {
@@ -309,7 +311,6 @@ void pack(pbng2d_workspace* ws, const pbng2d_problem* p, const Inc& I, const std
             jk[k] = int2{int_of[t[j]], int_of[t[l]]};
             gm[k] = R4{R(gx[j]), R(gy[j]), R(gx[l]), R(gy[l])};
             vw[k] = R2{R(G.A0 * G.mu), R(G.A0 * G.lam)};
-            rv[k] = 3 * e + s;
         }
     }
     // lumped loads: R0 g A0 / 3 per incident triangle, then nodal forces
@@ -332,10 +333,13 @@ void pack(pbng2d_workspace* ws, const pbng2d_problem* p, const Inc& I, const std
     {
         std::vector<int> pos(p->n_verts, -1);
         for (int k = 0; k < p->n_dirichlet; ++k) pos[p->dirichlet_idx[k]] = k;
+        std::vector<int> dpos(std::max<int64_t>(1, nv - nf), 0);
         for (int64_t v = nf; v < nv; ++v) {
             const int k = pos[ws->orig_h[v]];
             xd[v - nf] = R2{R(p->dirichlet_x[2 * k]), R(p->dirichlet_x[2 * k + 1])};
+            dpos[v - nf] = k;
         }
+        ws->dir_pos.upload(dpos);
     }
     // weak constraints in internal indices, the per-free-vertex CSR of
     // (constraint, weight), half-planes and the lumped masses
@@ -343,7 +347,7 @@ void pack(pbng2d_workspace* ws, const pbng2d_problem* p, const Inc& I, const std
     ws->n_planes = p->n_planes;
     {
         const int nnz = p->n_wc > 0 ? p->wc_ptr[p->n_wc] : 0;
-        std::vector<int> wcp(p->n_wc + 1, 0), wcv(std::max(1, nnz)), wvp(nf + 1, 0), wvc;
+        std::vector<int> wcp(p->n_wc + 1, 0), wcv(std::max(1, nnz)), wvp(nv + 1, 0), wvc;
         std::vector<double> wcw(std::max(1, nnz)), wck(std::max<int64_t>(1, 3 * int64_t(p->n_wc))), wvs;
         if (p->n_wc > 0) std::copy(p->wc_ptr, p->wc_ptr + p->n_wc + 1, wcp.begin());
         for (int k = 0; k < nnz; ++k) {
@@ -351,7 +355,7 @@ void pack(pbng2d_workspace* ws, const pbng2d_problem* p, const Inc& I, const std
             wcw[k] = p->wc_w[k];
         }
         for (int64_t k = 0; k < 3 * int64_t(p->n_wc); ++k) wck[k] = p->wc_K[k];
-        for (int64_t v = 0; v < nf; ++v) {
+        for (int64_t v = 0; v < nv; ++v) {   // every vertex (the adjoint needs the Dirichlet rows)
             const int o = ws->orig_h[v];
             for (int m = I.cptr[o]; m < I.cptr[o + 1]; ++m) {
                 wvc.push_back(I.clist[m]);
@@ -395,8 +399,19 @@ void pack(pbng2d_workspace* ws, const pbng2d_problem* p, const Inc& I, const std
     ws->lam_u = geo[0].lam;
     if (!ws->uniform) ws->vw.upload(vw);
     ws->fext.upload(fr);
-    ws->rvptr.upload(vptr);
-    ws->rv.upload(rv);
+    // triangle slots (3 e + local index) of every vertex, internal order
+    {
+        std::vector<int> rvp(nv + 1, 0), rva;
+        rva.reserve(3 * size_t(nt));
+        for (int64_t v = 0; v < nv; ++v) {
+            const int o = ws->orig_h[v];
+            for (int m = I.ptr[o]; m < I.ptr[o + 1]; ++m) rva.push_back(3 * I.tri[m] + I.slot[m]);
+            rvp[v + 1] = int(rva.size());
+        }
+        if (rva.empty()) rva.push_back(0);
+        ws->rvptr.upload(rvp);
+        ws->rv.upload(rva);
+    }
     ws->geo.upload(geo);
     ws->tri.upload(tri);
     ws->fext64.upload(f64);
@@ -487,7 +502,7 @@ void build2(pbng2d_workspace* ws, const pbng2d_problem* p, const int32_t* colors
 }
 
 template <class R>
-void residual2(pbng2d_workspace* ws, const void* X, double* r_out, hipStream_t s)
+Res2Args<R> res_args(pbng2d_workspace* ws, const void* X)
 {
     Res2Args<R> a;
     a.X = static_cast<const typename R2t<R>::T*>(X);
@@ -516,6 +531,13 @@ void residual2(pbng2d_workspace* ws, const void* X, double* r_out, hipStream_t s
     a.n_planes = ws->n_planes;
     a.inert = ws->inertia ? ws->inert64.as<double>() : nullptr;
     a.xhat = ws->inertia ? ws->xhat64.as<double>() : nullptr;
+    return a;
+}
+
+template <class R>
+void residual2(pbng2d_workspace* ws, const void* X, double* r_out, hipStream_t s)
+{
+    const Res2Args<R> a = res_args<R>(ws, X);
     hipchk(launch_residual2<R>(a, r_out, s), "residual");
     double* out = ws->out.as<double>();
     hipchk(launch_segsum(ws->rsq.as<double>(), ws->plan_r, 1, out, s), "residual sum");
@@ -674,6 +696,110 @@ int32_t solve2(pbng2d_workspace* ws, void* x, const pbng_solve_opts* o, pbng_sta
     return conv ? PBNG_OK : PBNG_NOT_CONVERGED;
 }
 
+// ||b - H lam|| over free vertices (FP64) of the adjoint iterate in LA.
+template <class R>
+double adjoint_check2(pbng2d_workspace* ws, const Res2Args<R>& a, hipStream_t s)
+{
+    using R2 = typename R2t<R>::T;
+    hipchk(launch_adjoint_residual2<R>(a, ws->LA.as<R2>(), ws->BA.as<R2>(), nullptr, nullptr, nullptr, nullptr, s),
+           "adjoint residual");
+    double* out = ws->out.as<double>();
+    hipchk(launch_segsum(ws->rsq.as<double>(), ws->plan_r, 1, out, s), "adjoint residual sum");
+    hipchk(hipMemcpyAsync(ws->hbuf, out, sizeof(double), hipMemcpyDeviceToHost, s), "d2h");
+    hipchk(hipStreamSynchronize(s), "sync");
+    return std::sqrt(ws->hbuf[0]);
+}
+
+// Block Gauss-Seidel on H lam = dL/dx (free rows) over the colours, with
+// the Chebyshev blend on request, then dL/dx_D, dL/dmu, dL/dlambda and lam.
+template <class R>
+int32_t adjoint2(pbng2d_workspace* ws, const void* x_eq, const void* dL_dx, double* dxd, double* dmu,
+                 double* dlam, double* lam_out, const pbng_adjoint_opts* o, pbng_stats* st, hipStream_t s)
+{
+    using R2 = typename R2t<R>::T;
+    using R4 = typename R4t<R>::T;
+    const int nv = int(ws->nv), nf = int(ws->nfree);
+    const bool accel = o->accel == PBNG_ACCEL_CHEBYSHEV;
+    const size_t bytes = size_t(std::max(nv, 1)) * ws->r2();
+    for (Dev* d : {&ws->XA, &ws->LA, &ws->LPa, &ws->LNa, &ws->BA}) d->reserve(bytes);
+    // caller order -> internal order, every row from the caller's arrays
+    hipchk(launch_load2<R>(static_cast<const R*>(x_eq), ws->orig_of.as<int>(), nullptr, ws->XA.as<R2>(), nullptr,
+                           nullptr, nf, nv, s),
+           "load");
+    hipchk(launch_load2<R>(static_cast<const R*>(dL_dx), ws->orig_of.as<int>(), nullptr, ws->BA.as<R2>(), nullptr,
+                           nullptr, nf, nv, s),
+           "load");
+    for (Dev* d : {&ws->LA, &ws->LPa, &ws->LNa}) hipchk(hipMemsetAsync(d->p, 0, bytes, s), "memset");
+    const Res2Args<R> ra = res_args<R>(ws, ws->XA.p);
+    const double b0 = adjoint_check2<R>(ws, ra, s);   // lam = 0: ||b|| over free rows
+    if (!std::isfinite(b0)) fail(PBNG_ENAN, "non-finite dL/dx");
+    Adj2Args<R> a;
+    a.X = ws->XA.as<R2>();
+    a.B = ws->BA.as<R2>();
+    a.vptr = ws->vptr.as<int>();
+    a.jk = ws->jk.as<int2>();
+    a.gm = ws->gm.as<R4>();
+    a.vw = ws->uniform ? nullptr : ws->vw.as<R2>();
+    a.mu_u = R(ws->mu_u);
+    a.lam_u = R(ws->lam_u);
+    a.wvptr = ws->wvptr.as<int>();
+    a.wv_c = ws->wv_c.as<int>();
+    a.wv_s = ws->wv_s.as<R>();
+    a.wc_ptr = ws->wc_ptr.as<int>();
+    a.wc_vert = ws->wc_vert.as<int>();
+    a.wc_w = ws->wc_w.as<R>();
+    a.wc_K = ws->wc_K.as<R>();
+    a.planes = ws->planes.as<R>();
+    a.n_planes = ws->n_planes;
+    a.inert = ws->inertia ? ws->inert.as<R>() : nullptr;
+    const int lanes = o->lanes == 0 ? 4 : o->lanes;
+    double rr = b0, omega_prev = 1.0;
+    bool conv = b0 == 0.0, nan = false;
+    int sweeps = 0;
+    const double t0 = wall_ms();
+    for (int sw = 0; sw < o->max_sweeps && !conv; ++sw) {
+        const double omega = accel ? chebyshev_next2(sw, o->rho, omega_prev) : 1.0;
+        omega_prev = omega;
+        a.L = ws->LA.as<R2>();
+        a.P = ws->LPa.as<R2>();
+        a.N = ws->LNa.as<R2>();
+        a.omega = R(omega);
+        a.gamma = R(accel ? o->gamma : 1.0);
+        for (int c = 0; c < ws->ncol; ++c)
+            hipchk(launch_adj_phase2<R>(a, ws->model, lanes, accel, ws->uniform, ws->extra(), ws->cptr[c],
+                                        ws->cptr[c + 1], s),
+                   "adjoint phase");
+        if (accel) std::swap(ws->LA.p, ws->LNa.p);
+        sweeps = sw + 1;
+        if (sweeps % o->check_every == 0 || sweeps == o->max_sweeps) {
+            rr = adjoint_check2<R>(ws, ra, s);
+            if (!std::isfinite(rr)) {
+                nan = true;
+                break;
+            }
+            if (o->rel_tol > 0 && rr <= o->rel_tol * b0) conv = true;
+        }
+    }
+    hipchk(launch_adjoint_residual2<R>(ra, ws->LA.as<R2>(), ws->BA.as<R2>(), dmu, dlam, dxd,
+                                       ws->dir_pos.as<int>(), s),
+           "adjoint gradients");
+    if (lam_out) hipchk(launch_store2_f64<R>(ws->LA.as<R2>(), ws->orig_of.as<int>(), lam_out, nv, s), "store");
+    hipchk(hipStreamSynchronize(s), "sync");
+    if (st) {
+        *st = pbng_stats{};
+        st->sweeps = sweeps;
+        st->converged = conv;
+        st->n_colors = ws->ncol;
+        st->residual0 = b0;
+        st->residual = rr;
+        st->rel_residual = b0 > 0 ? rr / b0 : 0.0;
+        st->time_ms = wall_ms() - t0;
+        st->vertex_updates = double(sweeps) * double(ws->nfree);
+    }
+    if (nan) fail(PBNG_ENAN, "adjoint iterate became non-finite");
+    return conv ? PBNG_OK : PBNG_NOT_CONVERGED;
+}
+
 void check_ws2(const pbng2d_workspace* ws)
 {
     if (!ws) fail(PBNG_EINVAL, "workspace is null");
@@ -777,6 +903,28 @@ int32_t pbng2d_residual(pbng2d_workspace* ws, const void* x, double* res_norm, d
         if (res_norm) *res_norm = ws->hbuf[0];
         if (energy) *energy = ws->hbuf[1];
         return PBNG_OK;
+    });
+}
+
+int32_t pbng2d_adjoint(pbng2d_workspace* ws, const void* x_eq, const void* dL_dx, double* dL_dxD, double* dL_dmu,
+                       double* dL_dlambda, double* lam_out, const pbng_adjoint_opts* o, pbng_stats* stats,
+                       void* hip_stream)
+{
+    return guard([&] {
+        check_ws2(ws);
+        if (!x_eq || !dL_dx || !o) fail(PBNG_EINVAL, "null argument");
+        if (o->max_sweeps < 0 || o->check_every < 1) fail(PBNG_EINVAL, "max_sweeps must be >= 0 and check_every >= 1");
+        if (o->accel != PBNG_ACCEL_NONE && o->accel != PBNG_ACCEL_CHEBYSHEV)
+            fail(PBNG_EINVAL, "the adjoint takes no acceleration or Chebyshev");
+        if (o->accel == PBNG_ACCEL_CHEBYSHEV && !(o->rho > 0 && o->rho < 1 && o->gamma > 0))
+            fail(PBNG_EINVAL, "Chebyshev needs 0 < rho < 1 and gamma > 0");
+        if (!std::isfinite(o->rel_tol) || o->rel_tol < 0) fail(PBNG_EINVAL, "rel_tol must be >= 0");
+        if (!(o->lanes == 0 || o->lanes == 1 || o->lanes == 2 || o->lanes == 4 || o->lanes == 8 || o->lanes == 16))
+            fail(PBNG_EINVAL, "planar lanes must be 0, 1, 2, 4, 8 or 16");
+        hipStream_t s = static_cast<hipStream_t>(hip_stream);
+        return ws->real == PBNG_F64
+                   ? adjoint2<double>(ws, x_eq, dL_dx, dL_dxD, dL_dmu, dL_dlambda, lam_out, o, stats, s)
+                   : adjoint2<float>(ws, x_eq, dL_dx, dL_dxD, dL_dmu, dL_dlambda, lam_out, o, stats, s);
     });
 }
 

@@ -537,6 +537,306 @@ __global__ __launch_bounds__(kBlk) void k2_store(const typename R2t<R>::T* src, 
     x_user[2 * int64_t(o) + 1] = p.y;
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint: block Gauss-Seidel on H lam = b, FP64 residual and gradients
+// ---------------------------------------------------------------------------
+// dP[Lam] for d = 2, scaled by the rest area through wm = A0 mu and
+// wl = A0 lambda (cof is linear in F here: dcof[Lam] = cof Lam):
+//   Neo-Hookean: wm Lam + lh (C:Lam) C + (lh (J - 1) - wm) cof Lam, lh = wm + wl
+//   corotated:   2 wm (Lam - dR[Lam]) + wl (C:Lam) C + wl (J - 1) cof Lam,
+// C = cof F, dR = dtheta [[-s, -c], [c, -s]] at the rotation angle theta of
+// (a, b) = (F00 + F11, F10 - F01), dtheta = (a db - b da) / (a^2 + b^2).
+template <class R, int MODEL>
+__device__ __forceinline__ void stress_diff2(R f00, R f01, R f10, R f11, R l00, R l01, R l10, R l11, R wm, R wl,
+                                             R& d00, R& d01, R& d10, R& d11)
+{
+    const R J = f00 * f11 - f01 * f10;
+    const R cl = f11 * l00 - f10 * l01 - f01 * l10 + f00 * l11;   // C : Lam
+    if constexpr (MODEL == kPlanarNeo) {
+        const R lh = wm + wl, q = lh * (J - R(1)) - wm, p = lh * cl;
+        d00 = wm * l00 + p * f11 + q * l11;
+        d01 = wm * l01 - p * f10 - q * l10;
+        d10 = wm * l10 - p * f01 - q * l01;
+        d11 = wm * l11 + p * f00 + q * l00;
+    } else {
+        const R a = f00 + f11, b = f10 - f01, r2 = a * a + b * b;
+        R c, sn;
+        rot2(f00, f01, f10, f11, c, sn);
+        const R dth = r2 > R(0) ? (a * (l10 - l01) - b * (l00 + l11)) / r2 : R(0);
+        const R q = wl * (J - R(1)), p = wl * cl, m2 = R(2) * wm;
+        d00 = m2 * (l00 + sn * dth) + p * f11 + q * l11;
+        d01 = m2 * (l01 + c * dth) - p * f10 - q * l10;
+        d10 = m2 * (l10 - c * dth) - p * f01 - q * l01;
+        d11 = m2 * (l11 + sn * dth) + p * f00 + q * l00;
+    }
+}
+
+// One block Gauss-Seidel update of lam_i: r_i = b_i - (H lam)_i with the
+// current lam, lam_i += D_i^{-1} r_i, D_i the true diagonal block for
+// Neo-Hookean (sum A0 (mu |dN_i|^2 I + lhat c c^T): in 2-D the cofactor
+// term of H_ii vanishes) and the modified A_i for corotated, plus s^2 K,
+// the active half-planes' k n n^T and the inertia.
+template <class R, int MODEL, int LANES, bool ACCEL, bool UNI, bool EXTRA>
+__global__ __launch_bounds__(kBlk) void k2_adj_phase(Adj2Args<R> a, int vbeg, int vend)
+{
+    using R2 = typename R2t<R>::T;
+    const int t = xcd_block() * kBlk + int(threadIdx.x);
+    const int v = vbeg + t / LANES;
+    const int lane = t & (LANES - 1);
+    if (v >= vend) return;
+    const R2 xi = at(a.X, v), li = at(a.L, v);
+    const int kb = at(a.vptr, v), ke = at(a.vptr, v + 1);
+    R hx = R(0), hy = R(0), dxx = R(0), dxy = R(0), dyy = R(0);
+    for (int k = kb + lane; k < ke; k += LANES) {
+        const int2 jk = at(a.jk, k);
+        const auto g = at(a.gm, k);
+        R wm, wl;
+        if constexpr (UNI) {
+            const R A0 = R(0.5) / abs_(g.x * g.w - g.y * g.z);
+            wm = a.mu_u * A0;
+            wl = a.lam_u * A0;
+        } else {
+            const R2 w = at(a.vw, k);
+            wm = w.x;
+            wl = w.y;
+        }
+        const R2 xj = at(a.X, jk.x), xk = at(a.X, jk.y);
+        const R2 lj = at(a.L, jk.x), lk = at(a.L, jk.y);
+        const R e1x = xj.x - xi.x, e1y = xj.y - xi.y, e2x = xk.x - xi.x, e2y = xk.y - xi.y;
+        const R f00 = e1x * g.x + e2x * g.z, f01 = e1x * g.y + e2x * g.w;
+        const R f10 = e1y * g.x + e2y * g.z, f11 = e1y * g.y + e2y * g.w;
+        const R m1x = lj.x - li.x, m1y = lj.y - li.y, m2x = lk.x - li.x, m2y = lk.y - li.y;
+        const R l00 = m1x * g.x + m2x * g.z, l01 = m1x * g.y + m2x * g.w;
+        const R l10 = m1y * g.x + m2y * g.z, l11 = m1y * g.y + m2y * g.w;
+        const R ax = -(g.x + g.z), ay = -(g.y + g.w);
+        R d00, d01, d10, d11;
+        stress_diff2<R, MODEL>(f00, f01, f10, f11, l00, l01, l10, l11, wm, wl, d00, d01, d10, d11);
+        hx += d00 * ax + d01 * ay;
+        hy += d10 * ax + d11 * ay;
+        const R cx = f11 * ax - f10 * ay, cy = f00 * ay - f01 * ax, sa = ax * ax + ay * ay;
+        if constexpr (MODEL == kPlanarNeo) {
+            const R lh = wm + wl;
+            dxx += wm * sa + lh * cx * cx;
+            dxy += lh * cx * cy;
+            dyy += wm * sa + lh * cy * cy;
+        } else {
+            dxx += R(2) * wm * sa + wl * cx * cx;
+            dxy += wl * cx * cy;
+            dyy += R(2) * wm * sa + wl * cy * cy;
+        }
+    }
+    if constexpr (EXTRA) {
+        for (int k = at(a.wvptr, v) + lane; k < at(a.wvptr, v + 1); k += LANES) {
+            const int c = at(a.wv_c, k);
+            const R sc = at(a.wv_s, k);
+            R Cx = R(0), Cy = R(0);
+            for (int j = at(a.wc_ptr, c); j < at(a.wc_ptr, c + 1); ++j) {
+                const R w = at(a.wc_w, j);
+                const R2 p = at(a.L, at(a.wc_vert, j));
+                Cx += w * p.x;
+                Cy += w * p.y;
+            }
+            const R K0 = at(a.wc_K, 3 * c), K1 = at(a.wc_K, 3 * c + 1), K2 = at(a.wc_K, 3 * c + 2);
+            hx += sc * (K0 * Cx + K1 * Cy);
+            hy += sc * (K1 * Cx + K2 * Cy);
+            dxx += sc * sc * K0;
+            dxy += sc * sc * K1;
+            dyy += sc * sc * K2;
+        }
+    }
+    if (LANES > 1) {
+        hx = lsum<LANES>(hx);
+        hy = lsum<LANES>(hy);
+        dxx = lsum<LANES>(dxx);
+        dxy = lsum<LANES>(dxy);
+        dyy = lsum<LANES>(dyy);
+    }
+    if constexpr (EXTRA) {
+        for (int q = 0; q < a.n_planes; ++q) {
+            const R nx = at(a.planes, 4 * q), ny = at(a.planes, 4 * q + 1), kp = at(a.planes, 4 * q + 3);
+            if (nx * xi.x + ny * xi.y - at(a.planes, 4 * q + 2) < R(0)) {
+                const R nl = kp * (nx * li.x + ny * li.y);
+                hx += nl * nx;
+                hy += nl * ny;
+                dxx += kp * nx * nx;
+                dxy += kp * nx * ny;
+                dyy += kp * ny * ny;
+            }
+        }
+        if (a.inert) {
+            const R c = at(a.inert, v);
+            hx += c * li.x;
+            hy += c * li.y;
+            dxx += c;
+            dyy += c;
+        }
+    }
+    if (lane != 0) return;
+    const R2 b = at(a.B, v);
+    const R rx = b.x - hx, ry = b.y - hy;
+    const R det = dxx * dyy - dxy * dxy;
+    R2 ln = li;
+    if (dxx > R(0) && det > R(0)) {
+        const R id = R(1) / det;
+        ln.x = li.x + (dyy * rx - dxy * ry) * id;
+        ln.y = li.y + (dxx * ry - dxy * rx) * id;
+    }
+    if (ACCEL) {
+        const R2 lp = at(a.P, v);
+        R2 bl;
+        bl.x = a.omega * (a.gamma * (ln.x - li.x) + li.x - lp.x) + lp.x;
+        bl.y = a.omega * (a.gamma * (ln.y - li.y) + li.y - lp.y) + lp.y;
+        *ptr_at(a.L, v) = ln;
+        *ptr_at(a.P, v) = li;
+        *ptr_at(a.N, v) = bl;
+    } else {
+        *ptr_at(a.L, v) = ln;
+    }
+}
+
+// FP64: per triangle the slot terms A0 dP[Lam_e] dN_j, and the gradients
+// dL/dmu_e = -A0 <dP/dmu, Lam_e> (dP/dmu = F + (J - 2) C for Neo-Hookean,
+// 2 (F - R) for corotated) and dL/dlambda_e = -A0 (J - 1) <C, Lam_e>.
+template <class R, int MODEL>
+__global__ __launch_bounds__(kBlk) void k2_tri_adjoint(Res2Args<R> a, const typename R2t<R>::T* L, double* dmu,
+                                                       double* dlam)
+{
+    const int e = blockIdx.x * kBlk + int(threadIdx.x);
+    if (e >= a.n_tris) return;
+    const int4 t = a.tri[e];
+    const TriGeo G = a.geo[e];
+    const double2 x0 = x64(a.X[t.x]), x1 = x64(a.X[t.y]), x2 = x64(a.X[t.z]);
+    const double2 l0 = x64(L[t.x]), l1 = x64(L[t.y]), l2 = x64(L[t.z]);
+    const double e1x = x1.x - x0.x, e1y = x1.y - x0.y, e2x = x2.x - x0.x, e2y = x2.y - x0.y;
+    const double f00 = e1x * G.g1x + e2x * G.g2x, f01 = e1x * G.g1y + e2x * G.g2y;
+    const double f10 = e1y * G.g1x + e2y * G.g2x, f11 = e1y * G.g1y + e2y * G.g2y;
+    const double m1x = l1.x - l0.x, m1y = l1.y - l0.y, m2x = l2.x - l0.x, m2y = l2.y - l0.y;
+    const double l00 = m1x * G.g1x + m2x * G.g2x, l01 = m1x * G.g1y + m2x * G.g2y;
+    const double l10 = m1y * G.g1x + m2y * G.g2x, l11 = m1y * G.g1y + m2y * G.g2y;
+    double d00, d01, d10, d11;
+    stress_diff2<double, MODEL>(f00, f01, f10, f11, l00, l01, l10, l11, G.A0 * G.mu, G.A0 * G.lam, d00, d01,
+                                d10, d11);
+    const double gx[3] = {-(G.g1x + G.g2x), G.g1x, G.g2x};
+    const double gy[3] = {-(G.g1y + G.g2y), G.g1y, G.g2y};
+    double* o = a.vp + 6 * int64_t(e);
+    for (int j = 0; j < 3; ++j) {
+        o[2 * j] = d00 * gx[j] + d01 * gy[j];
+        o[2 * j + 1] = d10 * gx[j] + d11 * gy[j];
+    }
+    const double J = f00 * f11 - f01 * f10;
+    const double CL = f11 * l00 - f10 * l01 - f01 * l10 + f00 * l11;
+    const double FL = f00 * l00 + f01 * l01 + f10 * l10 + f11 * l11;
+    if (dmu) {
+        double dPdmu;
+        if constexpr (MODEL == kPlanarNeo) {
+            dPdmu = FL + (J - 2.0) * CL;
+        } else {
+            double c, sn;
+            rot2(f00, f01, f10, f11, c, sn);
+            dPdmu = 2.0 * (FL - (c * l00 - sn * l01 + sn * l10 + c * l11));
+        }
+        dmu[e] = -G.A0 * dPdmu;
+    }
+    if (dlam) dlam[e] = -G.A0 * (J - 1.0) * CL;
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlk) void k2_vertex_adjoint(Res2Args<R> a, const typename R2t<R>::T* L,
+                                                          const typename R2t<R>::T* B, double* dxd,
+                                                          const int* dir_pos)
+{
+    const int v = blockIdx.x * kBlk + int(threadIdx.x);
+    if (v >= a.n_verts) return;
+    double hx = 0.0, hy = 0.0;
+    for (int k = a.rvptr[v]; k < a.rvptr[v + 1]; ++k) {
+        const double* p = a.vp + 2 * int64_t(a.rv[k]);
+        hx += p[0];
+        hy += p[1];
+    }
+    if (a.n_wc > 0)
+        for (int k = a.wvptr[v]; k < a.wvptr[v + 1]; ++k) {
+            const int c = a.wv_c[k];
+            double Cx = 0.0, Cy = 0.0;
+            for (int j = a.wc_ptr[c]; j < a.wc_ptr[c + 1]; ++j) {
+                const double2 p = x64(L[a.wc_vert[j]]);
+                Cx += a.wc_w[j] * p.x;
+                Cy += a.wc_w[j] * p.y;
+            }
+            const double* K = a.wc_K + 3 * int64_t(c);
+            hx += a.wv_s[k] * (K[0] * Cx + K[1] * Cy);
+            hy += a.wv_s[k] * (K[1] * Cx + K[2] * Cy);
+        }
+    const double2 b = x64(B[v]);
+    if (v < a.n_free) {
+        const double2 xi = x64(a.X[v]), li = x64(L[v]);
+        for (int q = 0; q < a.n_planes; ++q) {
+            const double* pl = a.planes + 4 * q;
+            if (pl[0] * xi.x + pl[1] * xi.y - pl[2] < 0.0) {
+                const double nl = pl[3] * (pl[0] * li.x + pl[1] * li.y);
+                hx += nl * pl[0];
+                hy += nl * pl[1];
+            }
+        }
+        if (a.inert) {
+            hx += a.inert[v] * li.x;
+            hy += a.inert[v] * li.y;
+        }
+        a.rsq[v] = (b.x - hx) * (b.x - hx) + (b.y - hy) * (b.y - hy);
+    } else {
+        a.rsq[v] = 0.0;
+        if (dxd) {
+            const int pos = dir_pos[v - a.n_free];
+            dxd[2 * int64_t(pos)] = b.x - hx;
+            dxd[2 * int64_t(pos) + 1] = b.y - hy;
+        }
+    }
+}
+
+template <class R>
+__global__ __launch_bounds__(kBlk) void k2_store64(const typename R2t<R>::T* src, const int* orig_of, double* out,
+                                                   int n_verts)
+{
+    const int v = blockIdx.x * kBlk + int(threadIdx.x);
+    if (v >= n_verts) return;
+    const int64_t o = orig_of[v];
+    out[2 * o] = double(src[v].x);
+    out[2 * o + 1] = double(src[v].y);
+}
+
+template <class R, int MODEL, int LANES, bool UNI, bool EXTRA>
+hipError_t adj_t(const Adj2Args<R>& a, bool accel, int vb, int ve, hipStream_t s)
+{
+    const int64_t threads = int64_t(ve - vb) * LANES;
+    if (threads <= 0) return hipSuccess;
+    if (accel)
+        hipLaunchKernelGGL((k2_adj_phase<R, MODEL, LANES, true, UNI, EXTRA>), dim3(nblocks(threads)), dim3(kBlk),
+                           0, s, a, vb, ve);
+    else
+        hipLaunchKernelGGL((k2_adj_phase<R, MODEL, LANES, false, UNI, EXTRA>), dim3(nblocks(threads)),
+                           dim3(kBlk), 0, s, a, vb, ve);
+    return hipGetLastError();
+}
+
+template <class R, int MODEL, bool UNI, bool EXTRA>
+hipError_t adj_lanes(const Adj2Args<R>& a, int lanes, bool accel, int vb, int ve, hipStream_t s)
+{
+    switch (lanes) {
+    case 1: return adj_t<R, MODEL, 1, UNI, EXTRA>(a, accel, vb, ve, s);
+    case 2: return adj_t<R, MODEL, 2, UNI, EXTRA>(a, accel, vb, ve, s);
+    case 4: return adj_t<R, MODEL, 4, UNI, EXTRA>(a, accel, vb, ve, s);
+    case 8: return adj_t<R, MODEL, 8, UNI, EXTRA>(a, accel, vb, ve, s);
+    case 16: return adj_t<R, MODEL, 16, UNI, EXTRA>(a, accel, vb, ve, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <class R, bool UNI, bool EXTRA>
+hipError_t adj_models(const Adj2Args<R>& a, int model, int lanes, bool accel, int vb, int ve, hipStream_t s)
+{
+    if (model == kPlanarNeo) return adj_lanes<R, kPlanarNeo, UNI, EXTRA>(a, lanes, accel, vb, ve, s);
+    return adj_lanes<R, kPlanarCor, UNI, EXTRA>(a, lanes, accel, vb, ve, s);
+}
+
 template <class R>
 __global__ __launch_bounds__(kBlk) void k2_xhat(const double* x_n, const double* x_prev, const int* orig_of,
                                                 double* xhat64, typename R2t<R>::T* xhat, int n_free)
@@ -562,6 +862,45 @@ hipError_t launch_xhat2(const double* x_n, const double* x_prev, const int* orig
     if (n_free > 0)
         hipLaunchKernelGGL((k2_xhat<R>), dim3(nblocks(n_free)), dim3(kBlk), 0, s, x_n, x_prev, orig_of, xhat64,
                            xhat, n_free);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_adj_phase2(const Adj2Args<R>& a, int model, int lanes, bool accel, bool uniform, bool extra,
+                             int vbeg, int vend, hipStream_t s)
+{
+    if (extra)
+        return uniform ? adj_models<R, true, true>(a, model, lanes, accel, vbeg, vend, s)
+                       : adj_models<R, false, true>(a, model, lanes, accel, vbeg, vend, s);
+    return uniform ? adj_models<R, true, false>(a, model, lanes, accel, vbeg, vend, s)
+                   : adj_models<R, false, false>(a, model, lanes, accel, vbeg, vend, s);
+}
+
+template <class R>
+hipError_t launch_adjoint_residual2(const Res2Args<R>& a, const typename R2t<R>::T* L,
+                                    const typename R2t<R>::T* B, double* dmu, double* dlam, double* dxd,
+                                    const int* dir_pos, hipStream_t s)
+{
+    if (a.n_tris > 0) {
+        if (a.model == kPlanarNeo)
+            hipLaunchKernelGGL((k2_tri_adjoint<R, kPlanarNeo>), dim3(nblocks(a.n_tris)), dim3(kBlk), 0, s, a, L,
+                               dmu, dlam);
+        else
+            hipLaunchKernelGGL((k2_tri_adjoint<R, kPlanarCor>), dim3(nblocks(a.n_tris)), dim3(kBlk), 0, s, a, L,
+                               dmu, dlam);
+    }
+    if (a.n_verts > 0)
+        hipLaunchKernelGGL((k2_vertex_adjoint<R>), dim3(nblocks(a.n_verts)), dim3(kBlk), 0, s, a, L, B, dxd,
+                           dir_pos);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_store2_f64(const typename R2t<R>::T* src, const int* orig_of, double* out, int n_verts,
+                             hipStream_t s)
+{
+    if (n_verts > 0)
+        hipLaunchKernelGGL((k2_store64<R>), dim3(nblocks(n_verts)), dim3(kBlk), 0, s, src, orig_of, out, n_verts);
     return hipGetLastError();
 }
 
@@ -620,7 +959,12 @@ hipError_t launch_store2(const typename R2t<R>::T* src, const int* orig_of, R* x
                                         R2t<R>::T*, int, int, hipStream_t);                                   \
     template hipError_t launch_store2<R>(const R2t<R>::T*, const int*, R*, int, hipStream_t);                \
     template hipError_t launch_xhat2<R>(const double*, const double*, const int*, double*, R2t<R>::T*, int,  \
-                                        hipStream_t);
+                                        hipStream_t);                                                         \
+    template hipError_t launch_adj_phase2<R>(const Adj2Args<R>&, int, int, bool, bool, bool, int, int,        \
+                                             hipStream_t);                                                    \
+    template hipError_t launch_adjoint_residual2<R>(const Res2Args<R>&, const R2t<R>::T*, const R2t<R>::T*,   \
+                                                    double*, double*, double*, const int*, hipStream_t);      \
+    template hipError_t launch_store2_f64<R>(const R2t<R>::T*, const int*, double*, int, hipStream_t);
 
 PBNG2D_INSTANTIATE(float)
 PBNG2D_INSTANTIATE(double)

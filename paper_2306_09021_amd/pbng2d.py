@@ -9,7 +9,8 @@ from typing import List, Optional
 import numpy as np
 
 from . import pbng as _b
-from .pbng import MODEL, REAL, SolveOpts, Stats, _check, _d, _i, _ptr, _stream, lame, solve_opts
+from .pbng import (MODEL, REAL, AdjointOpts, SolveOpts, Stats, _check, _d, _i, _ptr, _stream, adjoint_opts,
+                   lame, solve_opts)
 
 _ip = C.POINTER(C.c_int32)
 _dp = C.POINTER(C.c_double)
@@ -46,6 +47,8 @@ def lib():
             "pbng2d_sweeps": ([vp, C.c_int32, C.POINTER(SolveOpts), vp], C.c_int32),
             "pbng2d_phase_bytes": ([vp, C.c_int32, i64, i64, i64], C.c_int32),
             "pbng2d_workspace_set_inertia": ([vp, C.c_double, vp, vp, vp], C.c_int32),
+            "pbng2d_adjoint": ([vp, vp, vp, vp, vp, vp, vp, C.POINTER(AdjointOpts), C.POINTER(Stats), vp],
+                               C.c_int32),
         }
         for name, (args, res) in sigs.items():
             f = getattr(L, name)
@@ -59,7 +62,7 @@ def exported_symbols() -> List[str]:
     return ["pbng2d_color", "pbng2d_workspace_create", "pbng2d_workspace_destroy",
             "pbng2d_workspace_info", "pbng2d_workspace_colors", "pbng2d_solve", "pbng2d_residual",
             "pbng2d_load", "pbng2d_store", "pbng2d_sweeps", "pbng2d_phase_bytes",
-            "pbng2d_workspace_set_inertia"]
+            "pbng2d_workspace_set_inertia", "pbng2d_adjoint"]
 
 
 class HostProblem2D:
@@ -197,6 +200,28 @@ class Workspace2D:
         out = np.zeros(self.n_verts, np.int32)
         _check(lib().pbng2d_workspace_colors(self.handle, _i(out)))
         return out
+
+    def adjoint(self, x_eq, dL_dx, opts: Optional[AdjointOpts] = None, stream=None, **kw):
+        """pbng2d_adjoint; returns (status, dict of float64 cuda tensors
+        xd [n_dirichlet, 2] (dL/dx_D), mu and lam [n_tris] (dL/dmu,
+        dL/dlambda), lam_vec [n_verts, 2] (the adjoint), stats)."""
+        import torch
+        self._check_x(x_eq)
+        self._check_x(dL_dx)
+        o = opts if opts is not None else adjoint_opts(**kw)
+        dev = x_eq.device
+        nd = self.problem.dirichlet_idx.size
+        out = {"xd": torch.zeros((max(nd, 1), 2), dtype=torch.float64, device=dev),
+               "mu": torch.zeros(max(self.n_tris, 1), dtype=torch.float64, device=dev),
+               "lam": torch.zeros(max(self.n_tris, 1), dtype=torch.float64, device=dev),
+               "lam_vec": torch.zeros((self.n_verts, 2), dtype=torch.float64, device=dev)}
+        st = Stats()
+        rc = _check(lib().pbng2d_adjoint(self.handle, _ptr(x_eq), _ptr(dL_dx), _ptr(out["xd"]), _ptr(out["mu"]),
+                                         _ptr(out["lam"]), _ptr(out["lam_vec"]), C.byref(o), C.byref(st),
+                                         _stream(stream)))
+        out["xd"] = out["xd"][:nd]
+        out["mu"], out["lam"] = out["mu"][:self.n_tris], out["lam"][:self.n_tris]
+        return rc, out, st.to_dict()
 
     def set_inertia(self, dt, x_n=None, x_prev=None, stream=None):
         """Backward-Euler inertia with time step dt and xhat = 2 x^n - x^{n-1}

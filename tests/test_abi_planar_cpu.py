@@ -25,7 +25,7 @@ def header_functions():
 def test_library_exports_every_planar_symbol():
     L = ctypes.CDLL(pbng.LIB_PATH)
     names = header_functions()
-    assert len(names) == 12
+    assert len(names) == 13
     for n in names:
         assert hasattr(L, n), n
     assert sorted(pbng2d.exported_symbols()) == names

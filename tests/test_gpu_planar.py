@@ -357,3 +357,42 @@ def test_terms_degenerate_cases():
         rn, en = ws.residual(x)
         ro, eo, _ = P.residual(op, host(x))
         assert abs(rn - ro) <= 1e-10 * max(1.0, ro) and abs(en - eo) <= 1e-10 * max(1.0, abs(eo))
+
+
+def _adjoint_case(kind, model):
+    if kind == "square":
+        sc = S.stretched_square(9, model, 1.3, noise=0.2, seed=2)
+        sc.nodal_force = 2.0 * np.random.default_rng(4).normal(size=(sc.n_verts, 2))
+    else:
+        sc = S.planar_terms(9, model, n_springs=6, k_ground=300.0)
+    op = P.make_problem(sc)
+    if kind == "terms":
+        op.set_inertia(0.05, sc.initial_iterate(), sc.initial_iterate())
+    x = P.newton_equilibrium(op, sc.initial_iterate())
+    rng = np.random.default_rng(11)
+    b = rng.normal(size=x.shape)
+    return sc, op, x, b
+
+
+@pytest.mark.parametrize("kind", ["square", "terms"])
+@pytest.mark.parametrize("model", ["nh", "corotated"])
+@pytest.mark.parametrize("real,tol", [("f64", 1e-8), ("f32", 1e-4)])
+@pytest.mark.parametrize("accel", ["none", "chebyshev"])
+def test_adjoint_matches_the_dense_solve(kind, model, real, tol, accel):
+    """pbng2d_adjoint at a Newton equilibrium against the oracle's dense
+    adjoint: lam, dL/dx_D, dL/dmu and dL/dlambda (with the extra terms:
+    springs, the ground half-plane and inertia)."""
+    sc, op, x, b = _adjoint_case(kind, model)
+    announce("planar adjoint %s %s %s %s" % (kind, model, real, accel))
+    lam_o, xd_o, dmu_o, dlam_o = P.adjoint(op, x, b)
+    ws = ws2(sc, real)
+    if kind == "terms":
+        x0 = torch.tensor(sc.initial_iterate(), dtype=torch.float64, device="cuda")
+        ws.set_inertia(0.05, x0, x0.clone())
+    rc, out, st = ws.adjoint(dev2(x, real), dev2(b, real), max_sweeps=20000, rel_tol=1e-12 if real == "f64" else 1e-6,
+                             check_every=50, accel=accel, rho=0.9, gamma=1.0)
+    print("sweeps", st["sweeps"], "rel", st["rel_residual"])
+    assert rc == 0
+    for g, o_ in ((out["lam_vec"], lam_o), (out["xd"], xd_o), (out["mu"], dmu_o), (out["lam"], dlam_o)):
+        gg = host(g)
+        assert np.abs(gg - o_).max() <= tol * np.abs(o_).max(), (np.abs(gg - o_).max(), np.abs(o_).max())
