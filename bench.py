@@ -728,8 +728,9 @@ def planar_report(torch, stream, n=1025, sweeps=200, roof_sweeps=20):
     blends diverge from 257^2 and 129^2 vertices on (oracle and GPU alike).
     Reports vertex
     updates per second over `sweeps` sweeps, the FP64 relative residual after
-    50 and after `sweeps` sweeps, and the HBM roofline of the planar
-    colour-phase kernel from HIP events on the launch stream."""
+    50 and after `sweeps` sweeps, the HBM roofline of the planar
+    colour-phase kernel from HIP events on the launch stream, the corotated
+    square's rate, and `sweeps` adjoint sweeps at the final iterate."""
     from paper_2306_09021_amd import pbng2d
     from paper_2306_09021_amd import scenarios as S
     sc = S.stretched_square(n, "nh", 1.5)
@@ -778,7 +779,20 @@ def planar_report(torch, stream, n=1025, sweeps=200, roof_sweeps=20):
     _, stc = wsc.solve(xc, max_sweeps=sweeps, check_every=sweeps, stream=stream, **kw)
     torch.cuda.synchronize()
     elc = time.perf_counter() - t0
+    # the adjoint of the same square at the iterate reached above (H is
+    # positive definite there): block Gauss-Seidel sweeps for dL/dx = x - X
+    b = (x.double() - torch.tensor(sc.rest_pos, dtype=torch.float64, device="cuda")).to(x.dtype).contiguous()
+    ao = pbng2d.adjoint_opts(max_sweeps=sweeps, rel_tol=0.0, check_every=sweeps)
+    ws.adjoint(x, b, ao, stream=stream)                                                 # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, _, sta = ws.adjoint(x, b, ao, stream=stream)
+    torch.cuda.synchronize()
+    ela = time.perf_counter() - t0
     return {"workload": "stretched_square_%dx%d_neohookean" % (n, n), "vertices": ws.n_verts,
+            "adjoint": {"ms_per_sweep": round(1e3 * ela / sweeps, 4),
+                        "vertex_updates_per_s": round(sta["vertex_updates"] / ela, 1),
+                        "rel_residual_after": sta["rel_residual"]},
             "corotated": {"ms_per_sweep": round(1e3 * elc / sweeps, 4),
                           "vertex_updates_per_s": round(stc["vertex_updates"] / elc, 1),
                           "rel_residual_after": stc["rel_residual"]},

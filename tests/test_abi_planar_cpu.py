@@ -121,3 +121,12 @@ def test_planar_constraints_and_planes_are_validated_before_device_work():
     col = col.copy()
     col[22] = col[7]                                   # constraint members share a colour
     assert _create_err(hp, colors=col) == -4
+
+
+def test_planar_adjoint_and_inertia_reject_bad_arguments_on_the_host():
+    L = pbng2d.lib()
+    o = pbng.adjoint_opts()
+    st = pbng.Stats()
+    assert L.pbng2d_adjoint(None, None, None, None, None, None, None, ctypes.byref(o), ctypes.byref(st),
+                            None) == -1
+    assert L.pbng2d_workspace_set_inertia(None, 0.01, None, None, None) == -1
