@@ -823,10 +823,18 @@ def cpu_baseline(sc, sweeps):
     _, st = O.solve(op, col, sc.initial_iterate(), max_sweeps=sweeps, accel="sor", omega=1.6,
                     safeguard="backtrack", check_every=sweeps, n_threads=threads)
     t = time.perf_counter() - t0
+    # the serial definition as well: one thread over a shorter sample
+    s1 = max(1, sweeps // 15)
+    t1 = time.perf_counter()
+    _, st1 = O.solve(op, col, sc.initial_iterate(), max_sweeps=s1, accel="sor", omega=1.6,
+                     safeguard="backtrack", check_every=s1, n_threads=1)
+    t1 = time.perf_counter() - t1
     return {"value": round(sc.n_free * st["sweeps"] / t, 1), "unit": "vertex updates/s",
             "cores": threads, "kind": "oracle",
             "sample": "first %d sweeps of the same beam (FP64 C oracle, OpenMP within a colour, "
-                      "residual at start and end), %.1f s" % (st["sweeps"], t)}
+                      "residual at start and end), %.1f s" % (st["sweeps"], t),
+            "single_thread": {"value": round(sc.n_free * st1["sweeps"] / t1, 1), "cores": 1,
+                              "sample": "first %d sweeps, residual at start and end, %.1f s" % (st1["sweeps"], t1)}}
 
 
 if __name__ == "__main__":
