@@ -568,3 +568,25 @@ def test_sixty_four_colours_parity(real, tol):
     e = rel_err(xg, xo)
     print("rel err", e)
     assert e <= tol
+
+
+def test_phase_bytes_follow_their_definition():
+    """The roofline's algorithmic bytes, recomputed from the mesh and the
+    colouring: per colour phase 60 B per visit (free vertex of the colour,
+    incident tet), 24 B per updated vertex and 12 B per distinct other
+    vertex of those tets (integer-exact)."""
+    sc = S.gravity_beam(12, 5, 5, 0.25)
+    ws = workspace([sc], "f32")
+    col = ws.colors()
+    for c in range(ws.n_colors):
+        verts = np.nonzero(col == c)[0]
+        inc = [t for t in sc.tets if np.any(col[t] == c)]
+        vis = sum(int(np.sum(col[t] == c)) for t in sc.tets)
+        others = set()
+        for t in inc:
+            for v in t:
+                if col[v] == c:
+                    others.update(int(u) for u in t if u != v)
+        b, nv_, nvis = ws.phase_bytes(c)
+        assert (nv_, nvis) == (verts.size, vis)
+        assert b == 60 * vis + 24 * verts.size + 12 * len(others)

@@ -396,3 +396,25 @@ def test_adjoint_matches_the_dense_solve(kind, model, real, tol, accel):
     for g, o_ in ((out["lam_vec"], lam_o), (out["xd"], xd_o), (out["mu"], dmu_o), (out["lam"], dlam_o)):
         gg = host(g)
         assert np.abs(gg - o_).max() <= tol * np.abs(o_).max(), (np.abs(gg - o_).max(), np.abs(o_).max())
+
+
+@pytest.mark.parametrize("real,fb", [("f32", 1), ("f64", 2)])
+def test_phase_bytes_follow_their_definition(real, fb):
+    """pbng2d_phase_bytes recomputed from the mesh and the colouring: per
+    visit 8 + 24 fb bytes, per updated vertex 4 + 24 fb, per distinct other
+    vertex of the visited triangles 8 fb (fb = 1 in FP32, 2 in FP64)."""
+    sc = S.stretched_square(17, "nh", 1.3, diagonal="alternate")
+    ws = ws2(sc, real)
+    col = ws.colors()
+    for c in range(ws.n_colors):
+        verts = np.nonzero(col == c)[0]
+        vis = 0
+        others = set()
+        for t in sc.tris:
+            for v in t:
+                if col[v] == c:
+                    vis += 1
+                    others.update(int(u) for u in t if u != v)
+        b, nv_, nvis = ws.phase_bytes(c)
+        assert (nv_, nvis) == (verts.size, vis)
+        assert b == nvis * (8 + 24 * fb) + nv_ * (4 + 24 * fb) + len(others) * 8 * fb
